@@ -1,0 +1,172 @@
+"""Seeded synthetic inputs: initial colour-index fields, force fields and
+parameter sets for the benchmark and test workloads.
+
+This module holds no arithmetic of the scheme itself; it only builds the
+geometry (drops, layers, emulsions) and the parameter dictionaries that both
+the HIP path and the test oracle consume.  All randomness comes from
+``numpy.random.default_rng(seed)``.
+
+Workloads (the paper's own runs are synthetic drops and flat layers; these
+take their structure):
+
+* ``static_drop``      64x64 periodic, centred drop of radius 16, Lambda = 10
+* ``layered_channel``  256x128, walls at rows 0 and 127, red below, blue above
+* ``emulsion``         4096x4096 periodic, 50 non-overlapping drops, radii U[20, 80]
+* ``ellipse_drop``     one axis-aligned elliptic drop per lattice (batched runs)
+* ``gaussian_bumps``   smooth per-site body-force field
+"""
+import math
+
+import numpy as np
+
+STENCIL_PAPER = (3, 3, 3, 3)     # high-order stencil for every derivative (App. B)
+STENCIL_COMPACT = (1, 1, 1, 1)
+
+
+def alphas_for_ratio(Lambda):
+    """(alpha_R, alpha_B) for a density ratio Lambda = rho_0R / rho_0B.
+
+    The lighter phase keeps alpha = 1/2 and the heavier one takes
+    1 - 1/(2 Lambda) (resp. Lambda/2), the convention of the paper's
+    micro-current tables, so that (1 - a_B) = Lambda (1 - a_R)."""
+    if Lambda >= 1.0:
+        return 1.0 - 0.5 / Lambda, 0.5
+    return 0.5, 1.0 - 0.5 * Lambda
+
+
+def base_params(Lambda=10.0, rho0_R=1.0, sigma=0.01, beta=0.67, nu=1.0 / 6.0,
+                lambda6=1.4, lambda7=1.2, stencil=STENCIL_PAPER):
+    aR, aB = alphas_for_ratio(Lambda)
+    return dict(rho0_R=rho0_R, rho0_B=rho0_R / Lambda, alpha_R=aR, alpha_B=aB,
+                nu_R=nu, nu_B=nu, sigma=sigma, beta=beta, lambda6=lambda6, lambda7=lambda7,
+                gx=0.0, gy=0.0, stencil=tuple(stencil), walls=False, ghost_eq=0,
+                fixed_K=None, eps_n=1e-6)
+
+
+# ----------------------------------------------------------------------------
+# geometry
+# ----------------------------------------------------------------------------
+
+def static_drop(nx=64, ny=64, radius=16.0, center=None):
+    """+1 inside a circle (distance < radius), -1 outside; default centre
+    ((nx-1)/2, (ny-1)/2) keeps the lattice problem D4-symmetric."""
+    cx, cy = center if center is not None else ((nx - 1) / 2.0, (ny - 1) / 2.0)
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    return np.where((x - cx) ** 2 + (y - cy) ** 2 < radius * radius, 1.0, -1.0)
+
+
+def layered_channel(nx=256, ny=128):
+    """Red (+1) in fluid rows 1 .. ny/2 - 1, blue (-1) in ny/2 .. ny-2; rows 0
+    and ny-1 are solid (value irrelevant, set to -1)."""
+    out = -np.ones((ny, nx), dtype=np.float64)
+    out[1:ny // 2] = 1.0
+    return out
+
+
+def emulsion_drops(nx=4096, ny=4096, ndrops=50, rmin=20.0, rmax=80.0, gap=6.0, seed=0,
+                   max_tries=1_000_000):
+    """Radii ~ U[rmin, rmax], centres ~ U[0, n)^2, accepted when every pair is
+    separated (minimum image) by at least r_a + r_b + gap."""
+    rng = np.random.default_rng(seed)
+    radii = rng.uniform(rmin, rmax, size=ndrops)
+    centres = []
+    tries = 0
+    for r in radii:
+        while True:
+            tries += 1
+            if tries > max_tries:
+                raise RuntimeError("could not place drops")
+            c = rng.uniform(0.0, 1.0, size=2) * (nx, ny)
+            ok = True
+            for (cx, cy), r2 in zip(centres, radii):
+                dx = abs(c[0] - cx)
+                dy = abs(c[1] - cy)
+                dx = min(dx, nx - dx)
+                dy = min(dy, ny - dy)
+                if dx * dx + dy * dy < (r + r2 + gap) ** 2:
+                    ok = False
+                    break
+            if ok:
+                centres.append((float(c[0]), float(c[1])))
+                break
+    return np.array(centres), radii
+
+
+def emulsion(nx=4096, ny=4096, ndrops=50, rmin=20.0, rmax=80.0, gap=6.0, seed=0):
+    """+1 inside any drop (minimum-image distance < r), -1 elsewhere."""
+    centres, radii = emulsion_drops(nx, ny, ndrops, rmin, rmax, gap, seed)
+    out = -np.ones((ny, nx), dtype=np.float64)
+    for (cx, cy), r in zip(centres, radii):
+        x0, x1 = int(math.floor(cx - r)) - 1, int(math.ceil(cx + r)) + 2
+        y0, y1 = int(math.floor(cy - r)) - 1, int(math.ceil(cy + r)) + 2
+        xs = np.arange(x0, x1)
+        ys = np.arange(y0, y1)
+        X, Y = np.meshgrid(xs, ys)
+        inside = (X - cx) ** 2 + (Y - cy) ** 2 < r * r
+        out[Y[inside] % ny, X[inside] % nx] = 1.0
+    return out
+
+
+def ellipse_drop(n, aspect, center=None):
+    """Axis-aligned ellipse with semi-axes (n/4) sqrt(AR) and (n/4)/sqrt(AR)."""
+    cx, cy = center if center is not None else ((n - 1) / 2.0, (n - 1) / 2.0)
+    a = n / 4.0 * math.sqrt(aspect)
+    b = n / 4.0 / math.sqrt(aspect)
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    return np.where(((x - cx) / a) ** 2 + ((y - cy) / b) ** 2 < 1.0, 1.0, -1.0)
+
+
+def gaussian_bumps(nx, ny, nbumps=8, width=24.0, amplitude=1e-6, seed=2):
+    """Per-site force field [2, ny, nx]: sum of Gaussian bumps with random
+    centres and directions."""
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    out = np.zeros((2, ny, nx))
+    for _ in range(nbumps):
+        cx, cy = rng.uniform(0, nx), rng.uniform(0, ny)
+        ang = rng.uniform(0, 2 * math.pi)
+        dx = np.minimum(abs(x - cx), nx - abs(x - cx))
+        dy = np.minimum(abs(y - cy), ny - abs(y - cy))
+        g = amplitude * np.exp(-(dx * dx + dy * dy) / (2 * width * width))
+        out[0] += g * math.cos(ang)
+        out[1] += g * math.sin(ang)
+    return out
+
+
+def random_state_perturbation(shape, scale, seed):
+    """Multiplicative noise field (1 + scale U[-1, 1]) used by parity tests to
+    drive the step away from equilibrium."""
+    rng = np.random.default_rng(seed)
+    return 1.0 + scale * (2.0 * rng.random(shape) - 1.0)
+
+
+# ----------------------------------------------------------------------------
+# named configurations
+# ----------------------------------------------------------------------------
+
+def config_static_drop():
+    """64x64 periodic static drop, radius 16, Lambda = 10 (rho_R = 1, rho_B = 0.1),
+    sigma = 0.01, beta = 0.67, nu = 1/6, ghost rates 1.4 / 1.2; 1000 steps."""
+    p = base_params(Lambda=10.0, sigma=0.01)
+    return dict(nx=64, ny=64, steps=1000, params=p, rhoN0=static_drop(64, 64, 16.0))
+
+
+def config_layered_channel():
+    """256x128 channel, walls at rows 0 and 127, Lambda = 100, dynamic
+    viscosity ratio 10 (nu_B = 10 nu_R), body force density 1e-6 along x."""
+    p = base_params(Lambda=100.0, sigma=0.01)
+    p.update(nu_R=1.0 / 6.0, nu_B=10.0 / 6.0, gx=1e-6, walls=True)
+    return dict(nx=256, ny=128, steps=20000, params=p, rhoN0=layered_channel(256, 128))
+
+
+def config_emulsion(nx=4096, ny=4096, seed=0):
+    """4096^2 periodic emulsion: 50 drops, radii U[20, 80], Lambda = 10,
+    sigma = 0.005, beta = 0.67, nu = 1/6; 1000 steps."""
+    p = base_params(Lambda=10.0, sigma=0.005)
+    return dict(nx=nx, ny=ny, steps=1000, params=p,
+                rhoN0=emulsion(nx, ny, 50, 20.0, 80.0, 6.0, seed) if nx >= 1024 else None)
+
+
+def emulsion_crop(n=512, ndrops=3, seed=0):
+    """Smaller emulsion for parity runs: ``ndrops`` drops with the same radius law."""
+    return emulsion(n, n, ndrops, 20.0, 80.0 if n >= 400 else n / 8.0, 6.0, seed)
