@@ -1,0 +1,156 @@
+/*
+ * chromo_lbm.h -- C ABI of the MI355X (gfx950) chromodynamic MRT lattice
+ * Boltzmann step.
+ *
+ * The method is the two-colour, density-contrast, Dellar-type MRT scheme of
+ * Spendlove, Xu, Halliday, Schenkel and Halliday, "Chromodynamic multi-relaxation
+ * time lattice Boltzmann scheme for fluids with density difference"
+ * (arXiv 2005.04642):
+ *   - red/blue populations R_i, B_i on a D2Q9 lattice (Sec. II);
+ *   - colour index rho^N and its App. B gradient; Brackbill curvature
+ *     K = div n and Lishchuk force G = sigma K grad(rho^N) / 2 with Guo's
+ *     velocity u = (sum f c + G/2)/rho (Sec. II);
+ *   - modal relaxation with density-difference sources and explicit
+ *     reconstruction f+ = M^{-1} m+ (Sec. III, App. A);
+ *   - d'Ortona recolour (Sec. II) and streaming with periodic x, and either
+ *     periodic y or half-way bounce-back walls at rows 0 and ny-1.
+ *
+ * Memory: every device buffer belongs to the caller.  The library keeps only a
+ * small host-side handle (pointers, parameters, step counter, which of the two
+ * population buffers is live).  Nothing here allocates device memory.
+ *
+ * Populations: two buffers of 18*nx*ny elements, layout [colour 2][link 9][ny][nx]
+ * (x fastest, colour 0 = red).  The live buffer holds, for every site r and
+ * link i, the post-recolour population of the previous step at its source site
+ * (a "pull" layout): the pre-collision population of the current step is
+ * f_i(r) = buf_i(r - c_i), or buf_opp(i)(r) when r - c_i is a solid row.
+ * Link order: c0=(0,0) c1=(1,1) c2=(0,1) c3=(-1,1) c4=(-1,0) c5=(-1,-1)
+ * c6=(0,-1) c7=(1,-1) c8=(1,0)  (odd links are the diagonal ones).
+ * Element type: double for LBM_STORAGE_F64, float for LBM_STORAGE_F32.
+ *
+ * Streams: every call only enqueues work on the given stream; none of them
+ * synchronises, except lbm_masses_host (documented there).
+ *
+ * Errors: every entry point returns an lbm_status value; on failure
+ * lbm_last_error() gives a message (thread-local).  Handles are not thread-safe.
+ */
+#ifndef CHROMO_LBM_H
+#define CHROMO_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbm_status {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,      /* bad sizes, NULL pointers or inconsistent parameters */
+  LBM_EHIP = -2,        /* a HIP runtime call or kernel launch failed */
+  LBM_ENOTIMPL = -3,    /* entry point or option not provided by this build */
+  LBM_ENONFINITE = -4   /* a per-colour mass is not finite */
+} lbm_status;
+
+enum {
+  LBM_STORAGE_F64 = 0,  /* populations and arithmetic in double */
+  LBM_STORAGE_F32 = 1   /* populations and arithmetic in float */
+};
+
+enum {
+  LBM_FLAG_STREAM_ONLY = 1, /* lbm_step only streams: buf'_i(r) = f_i(r) (no collision) */
+  LBM_FLAG_FIXED_K = 2,     /* curvature K := K_fixed instead of div n (Sec. IV, fixed K) */
+  LBM_FLAG_NO_RECOLOR = 4   /* skip the segregation term of the recolour (proportional split) */
+};
+
+/* Parameters of one lattice (Sec. II, App. A).  Units are lattice units
+ * (delta_t = 1, |c_i| = 1 or sqrt 2). */
+typedef struct lbm_params {
+  int32_t nx, ny;       /* lattice size; x is always periodic */
+  int32_t walls_y;      /* 0: y periodic; 1: rows 0 and ny-1 are solid (half-way bounce-back) */
+  int32_t storage;      /* LBM_STORAGE_* */
+  int32_t stencil[4];   /* App. B stencil radius (1 or 3) for grad rho^N, div n, grad Phi', div u */
+  int32_t ghost_eq;     /* 0: N^(0) = h^(6).f^(0) (projected); 1: N^(0) = 0 (App. A, modal eqs.) */
+  int32_t flags;        /* LBM_FLAG_* */
+  double rho0_R, rho0_B;   /* bulk densities; Lambda = rho0_R / rho0_B (Sec. II) */
+  double alpha_R, alpha_B; /* rest fractions; must satisfy (1-alpha_B) = Lambda (1-alpha_R) */
+  double nu_R, nu_B;       /* kinematic viscosity of each bulk phase; nu(rho^N) linear in between */
+  double sigma;            /* interfacial tension */
+  double beta;             /* segregation parameter of the recolour */
+  double lambda6, lambda7; /* ghost-mode relaxation rates (App. A), each in (0, 2) */
+  double gx, gy;           /* uniform body-force density added to G */
+  double K_fixed;          /* curvature used with LBM_FLAG_FIXED_K */
+  double eps_n;            /* |grad rho^N| regularisation: n = grad/sqrt(|grad|^2 + eps_n^2) */
+} lbm_params;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Host-only check of a parameter set (no GPU call).  LBM_OK or LBM_EINVAL.
+ * Rejects: nx, ny < 1; walls with fewer than 1 fluid row; 18*nx*ny >= 2^31;
+ * unknown storage; a stencil radius not in {1, 3}; non-positive densities;
+ * |(1-alpha_B) - Lambda (1-alpha_R)| > 1e-9 (1-alpha_B) (Sec. II density-ratio
+ * relation); alpha outside [0, 1); nu <= 0 (lambda_3 = 2/(6 nu + 1) must lie in
+ * (0, 2)); lambda6, lambda7 outside (0, 2); eps_n <= 0. */
+int lbm_validate_params(const lbm_params* p);
+
+/* Number of elements of one population buffer: 18 * nx * ny. */
+size_t lbm_pops_elems(const lbm_params* p);
+
+/* Bytes of device workspace lbm_init needs (per-block FP64 partial sums of the
+ * mass reduction).  0 on invalid parameters. */
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/* Create a handle and write the initial populations into pops_a (Sec. II
+ * equilibrium at rest): rho_R = rho0_R (1 + rho^N)/2, rho_B = rho0_B (1 - rho^N)/2,
+ * C_i = rho_C phi_i.  rhoN0: device [ny][nx] array of the storage type, values in
+ * [-1, 1] (solid rows ignored).  force: NULL or device [2][ny][nx] per-site body
+ * force density (x then y component) added to G every step; it must stay valid
+ * and unchanged while the handle is used.  pops_a, pops_b: device buffers of
+ * lbm_pops_elems() elements, not overlapping.  workspace: device memory of at
+ * least lbm_workspace_bytes() bytes, 256-byte aligned.  The handle is written
+ * to *out; free it with lbm_destroy.  Enqueued on `stream`. */
+int lbm_init(const lbm_params* p, const void* rhoN0, const void* force,
+             void* pops_a, void* pops_b, void* workspace, size_t ws_bytes,
+             hipStream_t stream, lbm_handle** out);
+
+/* Advance nsteps >= 0 time steps (the whole path: fields, stencils, force,
+ * collision, recolour, streaming), swapping the two buffers each step.  If
+ * mass_RB_dev is not NULL, the FP64 per-colour masses (sum of all red and all
+ * blue populations over fluid sites, exact invariants of the scheme) after the
+ * last step are written there (2 doubles, device).  Enqueued on `stream`. */
+int lbm_step(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t stream);
+
+/* Macroscopic fields of the current state (Sec. II, force-adjusted
+ * observables): rho, u = (sum f c + G/2)/rho, rho^N.  Each output is NULL
+ * (skipped) or a device [ny][nx] array of the storage type; solid rows are
+ * written as NaN.  mass_RB_dev as in lbm_step.  Enqueued on `stream`. */
+int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN,
+               double* mass_RB_dev, hipStream_t stream);
+
+/* Synchronising helper: enqueue the mass reduction, wait for `stream`, copy the
+ * two masses to host out[2].  Returns LBM_ENONFINITE if either is not finite. */
+int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream);
+
+/* Adjoint of one step (gradient back-propagation through lbm_step).  Not
+ * provided by this build: always returns LBM_ENOTIMPL. */
+int lbm_adjoint_step(lbm_handle* h, const void* pops_t, void* adj_pops,
+                     double* dL_dsigma_dev, void* dL_dforce_dev, hipStream_t stream);
+
+/* 0 if pops_a holds the live state, 1 if pops_b does. */
+int lbm_current_pops(const lbm_handle* h);
+
+/* Steps taken since lbm_init. */
+int64_t lbm_step_count(const lbm_handle* h);
+
+/* Free the host handle (device buffers stay with the caller). */
+void lbm_destroy(lbm_handle* h);
+
+/* Message of the last failure on this thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CHROMO_LBM_H */

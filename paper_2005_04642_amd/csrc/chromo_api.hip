@@ -1,0 +1,374 @@
+// C ABI of the chromodynamic MRT lattice Boltzmann step (see include/chromo_lbm.h).
+// Host side: parameter validation, launch planning, kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "chromo_lbm.h"
+#include "chromo_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(LBM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr int MASS_BLOCKS = 512;
+constexpr int NTX_F32 = 256;  // lattice columns per workgroup row, float
+constexpr int NTX_F64 = 64;   // double (validation instantiation)
+
+template <typename T>
+struct NtxOf {
+  static constexpr int value = sizeof(T) == 8 ? NTX_F64 : NTX_F32;
+};
+
+bool radius_ok(int r) { return r == 1 || r == 3; }
+
+int halo(const lbm_params& p) { return p.stencil[0] + p.stencil[1] + p.stencil[3]; }
+
+int ntx_for(const lbm_params& p) { return p.storage == LBM_STORAGE_F64 ? NTX_F64 : NTX_F32; }
+
+int validate(const lbm_params* p) {
+  if (!p) return fail(LBM_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1) return fail(LBM_EINVAL, "lattice %dx%d is empty", p->nx, p->ny);
+  if (p->walls_y != 0 && p->walls_y != 1) return fail(LBM_EINVAL, "walls_y must be 0 or 1");
+  if (p->walls_y && p->ny < 3) return fail(LBM_EINVAL, "walls need ny >= 3 (one fluid row)");
+  if (18.0 * (double)p->nx * (double)p->ny >= 2147483647.0)
+    return fail(LBM_EINVAL, "lattice too large: 18*nx*ny must stay below 2^31");
+  if (p->storage != LBM_STORAGE_F32 && p->storage != LBM_STORAGE_F64)
+    return fail(LBM_EINVAL, "storage %d not provided by this build", p->storage);
+  for (int k = 0; k < 4; ++k)
+    if (!radius_ok(p->stencil[k])) return fail(LBM_EINVAL, "stencil radius %d not in {1,3}", p->stencil[k]);
+  if (!(p->rho0_R > 0.0) || !(p->rho0_B > 0.0)) return fail(LBM_EINVAL, "densities must be positive");
+  if (!(p->alpha_R >= 0.0 && p->alpha_R < 1.0) || !(p->alpha_B >= 0.0 && p->alpha_B < 1.0))
+    return fail(LBM_EINVAL, "alpha must lie in [0,1)");
+  const double Lam = p->rho0_R / p->rho0_B;
+  if (std::fabs((1.0 - p->alpha_B) - Lam * (1.0 - p->alpha_R)) > 1e-9 * (1.0 - p->alpha_B))
+    return fail(LBM_EINVAL, "density ratio relation violated: (1-alpha_B)=%.12g but Lambda(1-alpha_R)=%.12g",
+                1.0 - p->alpha_B, Lam * (1.0 - p->alpha_R));
+  if (!(p->nu_R > 0.0) || !(p->nu_B > 0.0)) return fail(LBM_EINVAL, "viscosities must be positive");
+  if (!(p->lambda6 > 0.0 && p->lambda6 < 2.0) || !(p->lambda7 > 0.0 && p->lambda7 < 2.0))
+    return fail(LBM_EINVAL, "ghost rates must lie in (0,2)");
+  if (!(p->eps_n > 0.0)) return fail(LBM_EINVAL, "eps_n must be positive");
+  if (!std::isfinite(p->sigma) || !std::isfinite(p->beta) || !std::isfinite(p->gx) || !std::isfinite(p->gy) ||
+      !std::isfinite(p->K_fixed))
+    return fail(LBM_EINVAL, "non-finite parameter");
+  if (p->ghost_eq != 0 && p->ghost_eq != 1) return fail(LBM_EINVAL, "ghost_eq must be 0 or 1");
+  if (p->flags & ~(LBM_FLAG_STREAM_ONLY | LBM_FLAG_FIXED_K | LBM_FLAG_NO_RECOLOR))
+    return fail(LBM_EINVAL, "unknown flag bits 0x%x", p->flags);
+  return LBM_OK;
+}
+
+template <typename T>
+chromo::Coef<T> make_coef(const lbm_params& p) {
+  chromo::Coef<T> c;
+  const double Lam = p.rho0_R / p.rho0_B;
+  c.inv_rho0R = (T)(1.0 / p.rho0_R);
+  c.inv_rho0B = (T)(1.0 / p.rho0_B);
+  c.alphaR = (T)p.alpha_R;
+  c.alphaB = (T)p.alpha_B;
+  c.c1R = (T)(1.0 - p.alpha_R);
+  c.c1B = (T)(1.0 - p.alpha_B);
+  c.c06R = (T)(0.6 * (1.0 - p.alpha_R));
+  c.c06B = (T)(0.6 * (1.0 - p.alpha_B));
+  c.phiB = (T)(0.6 * (1.0 - p.alpha_R) * Lam);
+  c.hnuR = (T)(0.5 * p.nu_R);
+  c.hnuB = (T)(0.5 * p.nu_B);
+  c.half_sigma = (T)(0.5 * p.sigma);
+  c.beta18 = (T)(1.8 * p.beta);
+  c.lambda6 = (T)p.lambda6;
+  c.keepJ = (T)(1.0 - p.lambda7);
+  c.gx = (T)p.gx;
+  c.gy = (T)p.gy;
+  c.K_fixed = (T)p.K_fixed;
+  c.eps2 = (T)(p.eps_n * p.eps_n);
+  c.ghost_eq = p.ghost_eq;
+  c.fixed_K = (p.flags & LBM_FLAG_FIXED_K) ? 1 : 0;
+  c.recolor = (p.flags & LBM_FLAG_NO_RECOLOR) ? 0 : 1;
+  return c;
+}
+
+// Strips of at most NTX-2H columns; chunks of rows so that the grid has about
+// one workgroup per compute unit (each workgroup is 3*NTX threads and uses up
+// most of a CU), but no chunk shorter than 24 rows.
+chromo::Geom plan(const lbm_params& p, int ncu) {
+  chromo::Geom g;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.walls = p.walls_y;
+  g.F = p.walls_y ? p.ny - 2 : p.ny;
+  g.plane = p.nx * p.ny;
+  const int txmax = ntx_for(p) - 2 * halo(p);
+  g.nstrips = (p.nx + txmax - 1) / txmax;
+  g.TX = (p.nx + g.nstrips - 1) / g.nstrips;
+  int want = (ncu + g.nstrips / 2) / g.nstrips;
+  if (want < 1) want = 1;
+  int maxchunks = (g.F + 23) / 24;
+  if (maxchunks < 1) maxchunks = 1;
+  int nch = want < maxchunks ? want : maxchunks;
+  g.TY = (g.F + nch - 1) / nch;
+  g.nchunks = (g.F + g.TY - 1) / g.TY;
+  return g;
+}
+
+template <typename T, int NTX, int RG, int RK, int RP, int RU, bool FIELDS>
+hipError_t launch_march(const chromo::StepArgs<T>& a, hipStream_t s) {
+  hipLaunchKernelGGL((chromo::chromo_step_kernel<T, NTX, RG, RK, RP, RU, FIELDS>),
+                     dim3(a.g.nstrips * a.g.nchunks), dim3(NTX * chromo::NR), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, int NTX, bool FIELDS>
+hipError_t dispatch_radii(const chromo::StepArgs<T>& a, const int* r, hipStream_t s) {
+  const int code = (r[0] == 3) * 8 + (r[1] == 3) * 4 + (r[2] == 3) * 2 + (r[3] == 3);
+#define CHROMO_CASE(C, A, B, P, U) \
+  case C:                          \
+    return launch_march<T, NTX, A, B, P, U, FIELDS>(a, s);
+  switch (code) {
+    CHROMO_CASE(0, 1, 1, 1, 1)
+    CHROMO_CASE(1, 1, 1, 1, 3)
+    CHROMO_CASE(2, 1, 1, 3, 1)
+    CHROMO_CASE(3, 1, 1, 3, 3)
+    CHROMO_CASE(4, 1, 3, 1, 1)
+    CHROMO_CASE(5, 1, 3, 1, 3)
+    CHROMO_CASE(6, 1, 3, 3, 1)
+    CHROMO_CASE(7, 1, 3, 3, 3)
+    CHROMO_CASE(8, 3, 1, 1, 1)
+    CHROMO_CASE(9, 3, 1, 1, 3)
+    CHROMO_CASE(10, 3, 1, 3, 1)
+    CHROMO_CASE(11, 3, 1, 3, 3)
+    CHROMO_CASE(12, 3, 3, 1, 1)
+    CHROMO_CASE(13, 3, 3, 1, 3)
+    CHROMO_CASE(14, 3, 3, 3, 1)
+    CHROMO_CASE(15, 3, 3, 3, 3)
+  }
+#undef CHROMO_CASE
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+struct lbm_handle {
+  lbm_params p;
+  void* pops[2];
+  int live;
+  void* ws;
+  size_t ws_bytes;
+  const void* force;
+  int64_t steps;
+  chromo::Geom g;
+};
+
+namespace {
+
+template <typename T>
+chromo::StepArgs<T> args_for(const lbm_handle* h, const T* src, T* dst) {
+  chromo::StepArgs<T> a;
+  a.src = src;
+  a.dst = dst;
+  a.force = static_cast<const T*>(h->force);
+  a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = nullptr;
+  a.g = h->g;
+  a.c = make_coef<T>(h->p);
+  return a;
+}
+
+template <typename T>
+int mass_into(lbm_handle* h, double* out, hipStream_t s) {
+  const T* live = static_cast<const T*>(h->pops[h->live]);
+  double* part = static_cast<double*>(h->ws);
+  hipLaunchKernelGGL(chromo::mass_partial_kernel<T>, dim3(MASS_BLOCKS), dim3(256), 0, s, live, h->g, part);
+  hipLaunchKernelGGL(chromo::mass_final_kernel, dim3(1), dim3(256), 0, s, part, MASS_BLOCKS, out);
+  HIP_TRY(hipGetLastError());
+  return LBM_OK;
+}
+
+template <typename T>
+int step_impl(lbm_handle* h, int nsteps, hipStream_t s) {
+  for (int k = 0; k < nsteps; ++k) {
+    const T* src = static_cast<const T*>(h->pops[h->live]);
+    T* dst = static_cast<T*>(h->pops[1 - h->live]);
+    if (h->p.flags & LBM_FLAG_STREAM_ONLY) {
+      dim3 grid((h->g.nx + 255) / 256, h->g.F);
+      hipLaunchKernelGGL(chromo::stream_only_kernel<T>, grid, dim3(256), 0, s, src, dst, h->g);
+      HIP_TRY(hipGetLastError());
+    } else {
+      chromo::StepArgs<T> a = args_for<T>(h, src, dst);
+      hipError_t e = dispatch_radii<T, NtxOf<T>::value, false>(a, h->p.stencil, s);
+      if (e != hipSuccess) return fail(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
+    }
+    h->live = 1 - h->live;
+    h->steps += 1;
+  }
+  return LBM_OK;
+}
+
+template <typename T>
+int fields_impl(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN, hipStream_t s) {
+  const T* src = static_cast<const T*>(h->pops[h->live]);
+  chromo::StepArgs<T> a = args_for<T>(h, src, nullptr);
+  a.out_rho = static_cast<T*>(rho);
+  a.out_ux = static_cast<T*>(ux);
+  a.out_uy = static_cast<T*>(uy);
+  a.out_rhoN = static_cast<T*>(rhoN);
+  hipError_t e = dispatch_radii<T, NtxOf<T>::value, true>(a, h->p.stencil, s);
+  if (e != hipSuccess) return fail(LBM_EHIP, "fields launch: %s", hipGetErrorString(e));
+  if (h->g.walls) {
+    hipLaunchKernelGGL(chromo::fill_rows_kernel<T>, dim3((h->g.nx + 255) / 256), dim3(256), 0, s, a.out_rho,
+                       a.out_ux, a.out_uy, a.out_rhoN, h->g.nx, 0, h->g.ny - 1);
+    HIP_TRY(hipGetLastError());
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_validate_params(const lbm_params* p) {
+  g_last_error.clear();
+  return validate(p);
+}
+
+size_t lbm_pops_elems(const lbm_params* p) {
+  if (!p || p->nx < 1 || p->ny < 1) return 0;
+  return (size_t)18 * (size_t)p->nx * (size_t)p->ny;
+}
+
+size_t lbm_workspace_bytes(const lbm_params* p) {
+  if (validate(p) != LBM_OK) return 0;
+  return (size_t)(MASS_BLOCKS + 1) * 2 * sizeof(double);  // partials + the lbm_masses_host target
+}
+
+int lbm_init(const lbm_params* p, const void* rhoN0, const void* force, void* pops_a, void* pops_b,
+             void* workspace, size_t ws_bytes, hipStream_t stream, lbm_handle** out) {
+  g_last_error.clear();
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int st = validate(p);
+  if (st != LBM_OK) return st;
+  if (!rhoN0 || !pops_a || !pops_b || !workspace)
+    return fail(LBM_EINVAL, "rhoN0, pops_a, pops_b and workspace must be non-NULL");
+  if (pops_a == pops_b) return fail(LBM_EINVAL, "pops_a and pops_b must differ");
+  const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
+  const size_t bytes = lbm_pops_elems(p) * elem;
+  const char* a = static_cast<const char*>(pops_a);
+  const char* b = static_cast<const char*>(pops_b);
+  if (a < b + bytes && b < a + bytes) return fail(LBM_EINVAL, "pops_a and pops_b overlap");
+  if (ws_bytes < lbm_workspace_bytes(p)) return fail(LBM_EINVAL, "workspace too small: %zu < %zu", ws_bytes,
+                                                     lbm_workspace_bytes(p));
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
+  if (reinterpret_cast<uintptr_t>(pops_a) % elem || reinterpret_cast<uintptr_t>(pops_b) % elem)
+    return fail(LBM_EINVAL, "population buffers misaligned");
+
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+
+  lbm_handle* h = new (std::nothrow) lbm_handle;
+  if (!h) return fail(LBM_EINVAL, "out of host memory");
+  h->p = *p;
+  h->pops[0] = pops_a;
+  h->pops[1] = pops_b;
+  h->live = 0;
+  h->ws = workspace;
+  h->ws_bytes = ws_bytes;
+  h->force = force;
+  h->steps = 0;
+  h->g = plan(*p, ncu > 0 ? ncu : 1);
+
+  dim3 grid((p->nx + 255) / 256, p->ny);
+  if (p->storage == LBM_STORAGE_F64) {
+    hipLaunchKernelGGL(chromo::init_kernel<double>, grid, dim3(256), 0, stream, static_cast<const double*>(rhoN0),
+                       static_cast<double*>(pops_a), h->g, make_coef<double>(*p), p->rho0_R, p->rho0_B);
+  } else {
+    hipLaunchKernelGGL(chromo::init_kernel<float>, grid, dim3(256), 0, stream, static_cast<const float*>(rhoN0),
+                       static_cast<float*>(pops_a), h->g, make_coef<float>(*p), (float)p->rho0_R,
+                       (float)p->rho0_B);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    delete h;
+    return fail(LBM_EHIP, "init launch: %s", hipGetErrorString(e));
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_step(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t stream) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  int st = h->p.storage == LBM_STORAGE_F64 ? step_impl<double>(h, nsteps, stream)
+                                           : step_impl<float>(h, nsteps, stream);
+  if (st != LBM_OK || !mass_RB_dev) return st;
+  return h->p.storage == LBM_STORAGE_F64 ? mass_into<double>(h, mass_RB_dev, stream)
+                                         : mass_into<float>(h, mass_RB_dev, stream);
+}
+
+int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN, double* mass_RB_dev,
+               hipStream_t stream) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  int st = LBM_OK;
+  if (rho || ux || uy || rhoN) {
+    st = h->p.storage == LBM_STORAGE_F64 ? fields_impl<double>(h, rho, ux, uy, rhoN, stream)
+                                         : fields_impl<float>(h, rho, ux, uy, rhoN, stream);
+  }
+  if (st != LBM_OK || !mass_RB_dev) return st;
+  return h->p.storage == LBM_STORAGE_F64 ? mass_into<double>(h, mass_RB_dev, stream)
+                                         : mass_into<float>(h, mass_RB_dev, stream);
+}
+
+int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream) {
+  g_last_error.clear();
+  if (!h || !out) return fail(LBM_EINVAL, "handle or out is NULL");
+  double* tgt = static_cast<double*>(h->ws) + 2 * MASS_BLOCKS;  // pair after the block partials
+  int st = h->p.storage == LBM_STORAGE_F64 ? mass_into<double>(h, tgt, stream) : mass_into<float>(h, tgt, stream);
+  if (st != LBM_OK) return st;
+  HIP_TRY(hipMemcpyAsync(out, tgt, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
+    return fail(LBM_ENONFINITE, "per-colour mass not finite: %g %g", out[0], out[1]);
+  return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_handle* h, const void* pops_t, void* adj_pops, double* dL_dsigma_dev,
+                     void* dL_dforce_dev, hipStream_t stream) {
+  (void)h;
+  (void)pops_t;
+  (void)adj_pops;
+  (void)dL_dsigma_dev;
+  (void)dL_dforce_dev;
+  (void)stream;
+  return fail(LBM_ENOTIMPL, "lbm_adjoint_step is not provided by this build");
+}
+
+int lbm_current_pops(const lbm_handle* h) { return h ? h->live : -1; }
+
+int64_t lbm_step_count(const lbm_handle* h) { return h ? h->steps : -1; }
+
+void lbm_destroy(lbm_handle* h) { delete h; }
+
+const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

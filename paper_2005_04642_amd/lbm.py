@@ -1,0 +1,259 @@
+"""Thin Python binding of the C ABI in include/chromo_lbm.h.
+
+The functions keep the C names (``lbm_init``, ``lbm_step``, ``lbm_fields``,
+...) and only marshal arguments: every step of the scheme runs in the HIP
+library.  PyTorch provides device memory and the current stream.  There is no
+CPU fallback: if the library is missing or no GPU is present the calls raise.
+
+``Simulation`` bundles the buffers one lattice needs (two population buffers,
+the workspace, the initial colour index and the optional force field).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libchromo_lbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENOTIMPL, LBM_ENONFINITE = 0, -1, -2, -3, -4
+LBM_STORAGE_F64, LBM_STORAGE_F32 = 0, 1
+LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR = 1, 2, 4
+
+# every symbol the header declares
+EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_workspace_bytes", "lbm_init", "lbm_step",
+            "lbm_fields", "lbm_masses_host", "lbm_adjoint_step", "lbm_current_pops", "lbm_step_count",
+            "lbm_destroy", "lbm_last_error")
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("lbm status %d: %s" % (code, msg))
+        self.code = code
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("walls_y", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("stencil", ctypes.c_int32 * 4), ("ghost_eq", ctypes.c_int32),
+                ("flags", ctypes.c_int32),
+                ("rho0_R", ctypes.c_double), ("rho0_B", ctypes.c_double),
+                ("alpha_R", ctypes.c_double), ("alpha_B", ctypes.c_double),
+                ("nu_R", ctypes.c_double), ("nu_B", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("beta", ctypes.c_double),
+                ("lambda6", ctypes.c_double), ("lambda7", ctypes.c_double),
+                ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+                ("K_fixed", ctypes.c_double), ("eps_n", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load_library(path=None):
+    """Load libchromo_lbm.so (built in-tree by ``build_lib.build()``)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError("HIP library %s is missing: run paper_2005_04642_amd.build_lib.build()" % p)
+    lib = ctypes.CDLL(p)
+    vp, i32, sz, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_size_t, ctypes.POINTER(ctypes.c_double)
+    P = ctypes.POINTER(lbm_params)
+    lib.lbm_validate_params.argtypes = [P]
+    lib.lbm_validate_params.restype = ctypes.c_int
+    lib.lbm_pops_elems.argtypes = [P]
+    lib.lbm_pops_elems.restype = sz
+    lib.lbm_workspace_bytes.argtypes = [P]
+    lib.lbm_workspace_bytes.restype = sz
+    lib.lbm_init.argtypes = [P, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.lbm_init.restype = ctypes.c_int
+    lib.lbm_step.argtypes = [vp, i32, vp, vp]
+    lib.lbm_step.restype = ctypes.c_int
+    lib.lbm_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.lbm_fields.restype = ctypes.c_int
+    lib.lbm_masses_host.argtypes = [vp, dp, vp]
+    lib.lbm_masses_host.restype = ctypes.c_int
+    lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.lbm_adjoint_step.restype = ctypes.c_int
+    lib.lbm_current_pops.argtypes = [vp]
+    lib.lbm_current_pops.restype = ctypes.c_int
+    lib.lbm_step_count.argtypes = [vp]
+    lib.lbm_step_count.restype = ctypes.c_int64
+    lib.lbm_destroy.argtypes = [vp]
+    lib.lbm_destroy.restype = None
+    lib.lbm_last_error.argtypes = []
+    lib.lbm_last_error.restype = ctypes.c_char_p
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(lib, code):
+    if code != LBM_OK:
+        raise LbmError(code, lib.lbm_last_error().decode())
+    return code
+
+
+def make_params(nx, ny, storage="f32", **kw):
+    """lbm_params from keyword parameters (the dictionaries of ``workloads``)."""
+    p = lbm_params()
+    p.nx, p.ny = nx, ny
+    p.walls_y = 1 if kw.get("walls", False) else 0
+    p.storage = {"f64": LBM_STORAGE_F64, "f32": LBM_STORAGE_F32}[storage]
+    st = kw.get("stencil", (3, 3, 3, 3))
+    for k in range(4):
+        p.stencil[k] = int(st[k])
+    p.ghost_eq = int(kw.get("ghost_eq", 0))
+    flags = int(kw.get("flags", 0))
+    if kw.get("fixed_K") is not None:
+        flags |= LBM_FLAG_FIXED_K
+        p.K_fixed = float(kw["fixed_K"])
+    if not kw.get("recolor", True):
+        flags |= LBM_FLAG_NO_RECOLOR
+    p.flags = flags
+    for name in ("rho0_R", "rho0_B", "alpha_R", "alpha_B", "nu_R", "nu_B", "sigma", "beta",
+                 "lambda6", "lambda7", "gx", "gy"):
+        setattr(p, name, float(kw[name]) if name in kw else 0.0)
+    p.eps_n = float(kw.get("eps_n", 1e-6))
+    return p
+
+
+# ---------------------------------------------------------------------------
+# C-name wrappers (argument marshalling only)
+# ---------------------------------------------------------------------------
+
+def lbm_validate_params(p):
+    lib = load_library()
+    return lib.lbm_validate_params(ctypes.byref(p)), lib.lbm_last_error().decode()
+
+
+def lbm_pops_elems(p):
+    return load_library().lbm_pops_elems(ctypes.byref(p))
+
+
+def lbm_workspace_bytes(p):
+    return load_library().lbm_workspace_bytes(ctypes.byref(p))
+
+
+def lbm_init(p, rhoN0_ptr, force_ptr, pops_a_ptr, pops_b_ptr, ws_ptr, ws_bytes, stream):
+    lib = load_library()
+    h = ctypes.c_void_p()
+    _check(lib, lib.lbm_init(ctypes.byref(p), rhoN0_ptr, force_ptr, pops_a_ptr, pops_b_ptr, ws_ptr,
+                             ws_bytes, stream, ctypes.byref(h)))
+    return h
+
+
+def lbm_step(h, nsteps, mass_ptr, stream):
+    lib = load_library()
+    return _check(lib, lib.lbm_step(h, nsteps, mass_ptr, stream))
+
+
+def lbm_fields(h, rho_ptr, ux_ptr, uy_ptr, rhoN_ptr, mass_ptr, stream):
+    lib = load_library()
+    return _check(lib, lib.lbm_fields(h, rho_ptr, ux_ptr, uy_ptr, rhoN_ptr, mass_ptr, stream))
+
+
+def lbm_masses_host(h, stream):
+    lib = load_library()
+    out = (ctypes.c_double * 2)()
+    _check(lib, lib.lbm_masses_host(h, out, stream))
+    return out[0], out[1]
+
+
+def lbm_adjoint_step(h, pops_t_ptr, adj_ptr, dsigma_ptr, dforce_ptr, stream):
+    lib = load_library()
+    return _check(lib, lib.lbm_adjoint_step(h, pops_t_ptr, adj_ptr, dsigma_ptr, dforce_ptr, stream))
+
+
+def lbm_current_pops(h):
+    return load_library().lbm_current_pops(h)
+
+
+def lbm_step_count(h):
+    return load_library().lbm_step_count(h)
+
+
+def lbm_destroy(h):
+    load_library().lbm_destroy(h)
+
+
+def lbm_last_error():
+    return load_library().lbm_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience: one lattice with torch-owned device buffers
+# ---------------------------------------------------------------------------
+
+class Simulation:
+    """Buffers and handle of one lattice.
+
+    params: dict of physical parameters (see ``workloads.base_params``);
+    rhoN0: [ny, nx] initial colour index (numpy or torch); storage 'f32'/'f64';
+    force: optional [2, ny, nx] per-site body force density.
+    """
+
+    def __init__(self, nx, ny, params, rhoN0, storage="f32", force=None, device="cuda:0", flags=0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the chromodynamic LBM step runs only on the HIP device")
+        self.torch = torch
+        self.nx, self.ny = nx, ny
+        self.device = torch.device(device)
+        kw = dict(params)
+        kw["flags"] = kw.get("flags", 0) | flags
+        self.params = make_params(nx, ny, storage, **kw)
+        self.dtype = torch.float64 if storage == "f64" else torch.float32
+        code, msg = lbm_validate_params(self.params)
+        if code != LBM_OK:
+            raise LbmError(code, msg)
+        n = lbm_pops_elems(self.params)
+        self.pops = [torch.empty(n, dtype=self.dtype, device=self.device) for _ in range(2)]
+        wsb = lbm_workspace_bytes(self.params)
+        self.ws = torch.zeros(wsb, dtype=torch.uint8, device=self.device)
+        self.rhoN0 = torch.as_tensor(np.asarray(rhoN0), dtype=self.dtype).to(self.device).contiguous()
+        self.force = None
+        if force is not None:
+            self.force = torch.as_tensor(np.asarray(force), dtype=self.dtype).to(self.device).contiguous()
+        self.mass = torch.zeros(2, dtype=torch.float64, device=self.device)
+        self.h = lbm_init(self.params, self.rhoN0.data_ptr(),
+                          None if self.force is None else self.force.data_ptr(),
+                          self.pops[0].data_ptr(), self.pops[1].data_ptr(), self.ws.data_ptr(), wsb,
+                          self.stream())
+
+    def stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def step(self, n=1, with_mass=False):
+        lbm_step(self.h, int(n), self.mass.data_ptr() if with_mass else None, self.stream())
+        return self
+
+    def fields(self):
+        t = self.torch
+        out = {k: t.empty((self.ny, self.nx), dtype=self.dtype, device=self.device)
+               for k in ("rho", "ux", "uy", "rhoN")}
+        lbm_fields(self.h, out["rho"].data_ptr(), out["ux"].data_ptr(), out["uy"].data_ptr(),
+                   out["rhoN"].data_ptr(), None, self.stream())
+        return out
+
+    def masses(self):
+        return lbm_masses_host(self.h, self.stream())
+
+    def live_pops(self):
+        """View [2, 9, ny, nx] of the live buffer (post-recolour, pull layout)."""
+        return self.pops[lbm_current_pops(self.h)].view(2, 9, self.ny, self.nx)
+
+    @property
+    def steps(self):
+        return lbm_step_count(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

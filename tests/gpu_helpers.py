@@ -1,0 +1,59 @@
+"""Shared helpers of the GPU parity tests (host side only)."""
+import numpy as np
+import torch
+
+from oracle import chromo as O
+from oracle.lattice import C, OPP, Q
+from paper_2005_04642_amd import lbm
+
+
+def pull_gather(S, walls):
+    """Pre-collision populations from a pull-layout buffer S [2, 9, ny, nx]:
+    f_i(r) = S_i(r - c_i), or S_opp(i)(r) when r - c_i is a solid row.
+    Returns the fluid rows only, [2, 9, F, nx]."""
+    S = np.asarray(S)
+    ny = S.shape[2]
+    out = np.empty_like(S)
+    for i in range(Q):
+        cx, cy = C[i]
+        out[:, i] = np.roll(np.roll(S[:, i], cx, axis=-1), cy, axis=-2)
+    if walls:
+        for i in range(Q):
+            cy = C[i][1]
+            if cy == 1:
+                out[:, i, 1] = S[:, OPP[i], 1]
+            elif cy == -1:
+                out[:, i, ny - 2] = S[:, OPP[i], ny - 2]
+        return out[:, :, 1:ny - 1]
+    return out
+
+
+def oracle_params(nx, ny, params):
+    return O.Params(nx=nx, ny=ny, **params)
+
+
+def oracle_post_collision(S, nx, ny, params, force=None):
+    """Post-recolour populations the oracle computes from the pre-collision
+    state encoded in the pull-layout buffer S (fluid rows, [2, 9, F, nx])."""
+    p = oracle_params(nx, ny, params)
+    P = pull_gather(S, p.walls)
+    o = O.Oracle(p, force=force).set_state(torch.from_numpy(P[0]), torch.from_numpy(P[1]))
+    R, B = o.post_collision()
+    return np.stack([R.numpy(), B.numpy()])
+
+
+def fluid(a, walls):
+    return a[..., 1:-1, :] if walls else a
+
+
+def perturbed_buffer(sim, scale, seed):
+    """Multiply the live buffer by (1 + scale U[-1, 1]) (seeded, host-generated)."""
+    from paper_2005_04642_amd import workloads as Wk
+    buf = sim.live_pops()
+    noise = Wk.random_state_perturbation(tuple(buf.shape), scale, seed)
+    buf.mul_(torch.as_tensor(noise, dtype=buf.dtype, device=buf.device))
+    return buf
+
+
+def rel_err(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

@@ -1,0 +1,87 @@
+"""The C-ABI library loads on a CPU-only machine, exports every symbol the
+public header declares, and its host-only validation rejects bad parameters.
+No compute call is made here."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2005_04642_amd import lbm, workloads as Wk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chromo_lbm.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load_library()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(lbm.EXPORTED) == names
+
+
+def good():
+    return lbm.make_params(64, 64, "f32", **Wk.base_params(Lambda=10.0))
+
+
+def test_validate_accepts_workload_parameters():
+    for storage in ("f32", "f64"):
+        for cfg in (Wk.config_static_drop(), Wk.config_layered_channel()):
+            p = lbm.make_params(cfg["nx"], cfg["ny"], storage, **cfg["params"])
+            assert lbm.lbm_validate_params(p)[0] == lbm.LBM_OK
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("ny", -3), ("storage", 7), ("walls_y", 2), ("rho0_B", 0.0), ("alpha_R", 1.0),
+    ("alpha_B", 0.3), ("nu_R", 0.0), ("lambda6", 2.0), ("lambda7", 0.0), ("eps_n", 0.0),
+    ("ghost_eq", 3), ("flags", 64), ("sigma", float("nan")),
+])
+def test_validate_rejects(field, value):
+    p = good()
+    setattr(p, field, value)
+    code, msg = lbm.lbm_validate_params(p)
+    assert code == lbm.LBM_EINVAL and msg
+
+
+def test_validate_rejects_bad_stencil_and_huge_and_wall_height():
+    p = good()
+    p.stencil[2] = 2
+    assert lbm.lbm_validate_params(p)[0] == lbm.LBM_EINVAL
+    p = good()
+    p.nx, p.ny = 20000, 20000
+    assert lbm.lbm_validate_params(p)[0] == lbm.LBM_EINVAL
+    p = good()
+    p.walls_y, p.ny = 1, 2
+    assert lbm.lbm_validate_params(p)[0] == lbm.LBM_EINVAL
+
+
+def test_sizes():
+    p = good()
+    assert lbm.lbm_pops_elems(p) == 18 * 64 * 64
+    assert lbm.lbm_workspace_bytes(p) > 0
+    p.nx = 0
+    assert lbm.lbm_workspace_bytes(p) == 0
+
+
+def test_init_argument_errors_before_any_gpu_call():
+    lib = lbm.load_library()
+    p = good()
+    h = ctypes.c_void_p()
+    code = lib.lbm_init(ctypes.byref(p), None, None, None, None, None, 0, None, ctypes.byref(h))
+    assert code == lbm.LBM_EINVAL and h.value is None
+    code = lib.lbm_step(None, 1, None, None)
+    assert code == lbm.LBM_EINVAL
+
+
+def test_adjoint_is_reported_not_implemented():
+    lib = lbm.load_library()
+    assert lib.lbm_adjoint_step(None, None, None, None, None, None) == lbm.LBM_ENOTIMPL
+    assert "not provided" in lbm.lbm_last_error()

@@ -1,0 +1,277 @@
+"""Parity of the HIP path (through the C ABI) with the oracle.
+
+* streaming and boundary indexing: bit-exact against a host pull-gather;
+* initial state, one step from random non-equilibrium states (every stencil
+  profile, periodic and walls, ragged strips and chunks): FP64 to 1e-13;
+* static drop 64x64 for 1000 steps: FP64 to 1e-11, FP32 to 1e-5 in rho and u;
+* full-size 4096^2 emulsion: sampled sites of the launch the benchmark times,
+  recomputed one by one by the oracle on local windows;
+* per-colour mass conservation, NaN detection, solid rows in the fields.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import chromo as O
+from paper_2005_04642_amd import lbm, workloads as Wk
+
+from gpu_helpers import (fluid, oracle_params, oracle_post_collision, perturbed_buffer, pull_gather,
+                         rel_err)
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def sim_for(nx, ny, params, rn, storage, **kw):
+    return lbm.Simulation(nx, ny, params, rn, storage=storage, device=DEV, **kw)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# streaming (bit-exact)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("shape", [(4, 4), (5, 7), (300, 9), (64, 64)])
+def test_stream_only_bit_exact(storage, walls, shape):
+    nx, ny = shape
+    params = Wk.base_params()
+    params["walls"] = walls
+    sim = sim_for(nx, ny, params, -np.ones((ny, nx)), storage, flags=lbm.LBM_FLAG_STREAM_ONLY)
+    n = 18 * nx * ny
+    payload = torch.arange(n, dtype=sim.dtype, device=DEV)
+    sim.live_pops().copy_(payload.view(2, 9, ny, nx))
+    ref = payload.view(2, 9, ny, nx).cpu().numpy()
+    for _ in range(3):
+        sim.step(1)
+        ref_next = ref.copy()
+        g = pull_gather(ref, walls)
+        if walls:
+            ref_next[:, :, 1:ny - 1] = g
+        else:
+            ref_next = g
+        got = host(sim.live_pops())
+        assert np.array_equal(fluid(got, walls), fluid(ref_next, walls))
+        ref = ref_next
+    sim.close()
+
+
+# ---------------------------------------------------------------------------
+# initial state
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_initial_state_matches_oracle(walls):
+    nx, ny = 37, 23
+    params = Wk.base_params(Lambda=10.0)
+    params["walls"] = walls
+    rn = np.tanh(0.4 * (np.arange(nx)[None, :] - 15.0)) * np.ones((ny, 1))
+    sim = sim_for(nx, ny, params, rn, "f64")
+    P = pull_gather(host(sim.live_pops()), walls)
+    o = O.Oracle(oracle_params(nx, ny, params)).init(rn)
+    assert np.max(np.abs(P[0] - o.R.numpy())) < 1e-15
+    assert np.max(np.abs(P[1] - o.B.numpy())) < 1e-15
+    f = {k: host(v) for k, v in sim.fields().items()}
+    fo = o.fields()
+    for k in ("rho", "ux", "uy", "rhoN"):
+        a, b = fluid(f[k], walls), fluid(fo[k].numpy(), walls)
+        assert np.max(np.abs(a - b)) < 1e-13, k
+    if walls:
+        for k in ("rho", "ux", "uy", "rhoN"):
+            assert np.isnan(f[k][0]).all() and np.isnan(f[k][-1]).all()
+    sim.close()
+
+
+# ---------------------------------------------------------------------------
+# one step from random states, FP64, every stencil profile
+# ---------------------------------------------------------------------------
+
+STENCILS = [(3, 3, 3, 3), (1, 1, 1, 1), (3, 1, 3, 1), (1, 3, 1, 3), (3, 3, 1, 1), (1, 1, 3, 3)]
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("shape", [(8, 8), (47, 29), (100, 60)])
+def test_one_step_random_state_f64(stencil, walls, shape):
+    nx, ny = shape
+    params = Wk.base_params(Lambda=10.0, sigma=0.02, stencil=stencil)
+    params.update(walls=walls, gx=3e-5, gy=-2e-5, nu_B=0.4)
+    rng = np.random.default_rng(7)
+    rn = np.clip(np.tanh(2.0 * rng.standard_normal((ny, nx))), -1, 1)
+    sim = sim_for(nx, ny, params, rn, "f64")
+    S = host(perturbed_buffer(sim, 0.05, seed=3))
+    ref = oracle_post_collision(S, nx, ny, params)
+    sim.step(1)
+    got = fluid(host(sim.live_pops()), walls)
+    err = np.max(np.abs(got - ref))
+    assert err < 1e-13, err
+    sim.close()
+
+
+@pytest.mark.parametrize("walls", [False, True])
+def test_one_step_options_f64(walls):
+    """Fixed curvature, literal ghost equilibrium, no recolour, per-site force."""
+    nx, ny = 40, 30
+    rng = np.random.default_rng(11)
+    rn = np.clip(np.tanh(2.0 * rng.standard_normal((ny, nx))), -1, 1)
+    force = 1e-4 * rng.standard_normal((2, ny, nx))
+    for extra in (dict(fixed_K=0.05), dict(ghost_eq=1), dict(recolor=False), dict()):
+        params = Wk.base_params(Lambda=4.0, sigma=0.02)
+        params.update(walls=walls, **extra)
+        use_force = not extra
+        sim = sim_for(nx, ny, params, rn, "f64", force=force if use_force else None)
+        S = host(perturbed_buffer(sim, 0.05, seed=5))
+        p_or = dict(params)
+        ref = oracle_post_collision(S, nx, ny, p_or, force=torch.from_numpy(force) if use_force else None)
+        sim.step(1)
+        got = fluid(host(sim.live_pops()), walls)
+        assert np.max(np.abs(got - ref)) < 1e-13, extra
+        sim.close()
+
+
+# ---------------------------------------------------------------------------
+# static drop, 1000 steps
+# ---------------------------------------------------------------------------
+
+def run_static_drop(storage, steps=1000):
+    cfg = Wk.config_static_drop()
+    n = cfg["nx"]
+    sim = sim_for(n, n, cfg["params"], cfg["rhoN0"], storage)
+    m0 = sim.masses()
+    sim.step(steps)
+    f = {k: host(v).astype(np.float64) for k, v in sim.fields().items()}
+    m1 = sim.masses()
+    sim.close()
+    return cfg, f, m0, m1
+
+
+@pytest.fixture(scope="module")
+def static_drop_oracle():
+    cfg = Wk.config_static_drop()
+    o = O.Oracle(oracle_params(64, 64, cfg["params"])).init(cfg["rhoN0"]).step(1000)
+    o32 = O.Oracle(oracle_params(64, 64, cfg["params"]), dtype=torch.float32).init(cfg["rhoN0"]).step(1000)
+    return {k: v.numpy() for k, v in o.fields().items()}, {k: v.double().numpy() for k, v in o32.fields().items()}
+
+
+def drop_errors(f, fo):
+    e_rho = float(np.max(np.abs(f["rho"] - fo["rho"]) / fo["rho"]))
+    du = np.hypot(f["ux"] - fo["ux"], f["uy"] - fo["uy"])
+    e_u = float(np.max(du) / np.max(np.hypot(fo["ux"], fo["uy"])))
+    return e_rho, e_u
+
+
+def test_static_drop_f64_1000_steps(static_drop_oracle):
+    fo, _ = static_drop_oracle
+    cfg, f, m0, m1 = run_static_drop("f64")
+    e_rho, e_u = drop_errors(f, fo)
+    print("static drop f64: e_rho %.3e e_u %.3e" % (e_rho, e_u))
+    assert e_rho < 1e-11 and e_u < 1e-11
+    assert abs(m1[0] - m0[0]) / m0[0] < 1e-13 and abs(m1[1] - m0[1]) / m0[1] < 1e-13
+
+
+def test_static_drop_f32_1000_steps(static_drop_oracle):
+    fo, fo32 = static_drop_oracle
+    cfg, f, m0, m1 = run_static_drop("f32")
+    e_rho, e_u = drop_errors(f, fo)
+    floor_rho, floor_u = drop_errors(fo32, fo)
+    print("static drop f32: e_rho %.3e e_u %.3e (fp32 oracle floor: %.3e %.3e)" % (e_rho, e_u, floor_rho, floor_u))
+    assert e_rho < 1e-5
+    assert e_u < 1e-5
+    assert abs(m1[0] - m0[0]) / m0[0] < 1e-6 and abs(m1[1] - m0[1]) / m0[1] < 1e-6
+
+
+# ---------------------------------------------------------------------------
+# walls: layered channel (reduced size), FP64 and FP32
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
+def test_layered_channel_parity(storage, tol):
+    nx, ny, steps = 48, 66, 400
+    params = Wk.base_params(Lambda=10.0, sigma=0.01)
+    params.update(walls=True, nu_R=1.0 / 6.0, nu_B=10.0 / 6.0, gx=1e-5)
+    yy = (np.arange(ny) - 0.5)[:, None] * np.ones((1, nx))
+    rn = np.tanh(0.6 * (ny / 2.0 - yy))
+    sim = sim_for(nx, ny, params, rn, storage)
+    sim.step(steps)
+    f = {k: fluid(host(v).astype(np.float64), True) for k, v in sim.fields().items()}
+    sim.close()
+    o = O.Oracle(oracle_params(nx, ny, params)).init(rn).step(steps)
+    fo = {k: fluid(v.numpy(), True) for k, v in o.fields().items()}
+    e_rho = float(np.max(np.abs(f["rho"] - fo["rho"]) / fo["rho"]))
+    e_u = float(np.max(np.hypot(f["ux"] - fo["ux"], f["uy"] - fo["uy"])) / np.max(np.hypot(fo["ux"], fo["uy"])))
+    print("channel %s: e_rho %.3e e_u %.3e" % (storage, e_rho, e_u))
+    assert e_rho < tol and e_u < tol
+
+
+# ---------------------------------------------------------------------------
+# full-size emulsion: sampled sites of the benchmarked launch
+# ---------------------------------------------------------------------------
+
+def window(S, x, y, half):
+    """Periodic window [2, 9, 2h+1, 2h+1] of a device pull-layout buffer centred at (x, y), on the host."""
+    ny, nx = S.shape[-2:]
+    ys = torch.arange(y - half, y + half + 1, device=S.device) % ny
+    xs = torch.arange(x - half, x + half + 1, device=S.device) % nx
+    return S[:, :, ys][:, :, :, xs].double().cpu().numpy()
+
+
+def test_full_size_emulsion_sampled_sites():
+    cfg = Wk.config_emulsion()
+    n = cfg["nx"]
+    params = cfg["params"]
+    sim = sim_for(n, n, params, cfg["rhoN0"], "f32")
+    sim.step(20)
+    before = sim.live_pops().clone()
+    sim.step(1)
+    after = sim.live_pops()
+    rng = np.random.default_rng(123)
+    # sample interface sites (where every term is active) and random ones
+    rn = cfg["rhoN0"]
+    edge = np.argwhere(np.abs(np.roll(rn, 1, 0) - rn) + np.abs(np.roll(rn, 1, 1) - rn) > 0)
+    picks = [tuple(edge[k]) for k in rng.choice(len(edge), 12, replace=False)]
+    picks += [tuple(rng.integers(0, n, 2)) for _ in range(4)]
+    half = 16
+    worst = 0.0
+    for (y, x) in picks:
+        S = window(before, int(x), int(y), half)
+        ref = oracle_post_collision(S, 2 * half + 1, 2 * half + 1, params)[:, :, half, half]
+        got = after[:, :, y, x].double().cpu().numpy()
+        scale = np.max(np.abs(ref))
+        worst = max(worst, float(np.max(np.abs(got - ref)) / scale))
+    print("emulsion 4096^2 sampled sites: max rel err %.3e" % worst)
+    assert worst < 2e-5
+    sim.close()
+
+
+# ---------------------------------------------------------------------------
+# invariants and failure reporting
+# ---------------------------------------------------------------------------
+
+def test_nan_is_reported_through_masses():
+    cfg = Wk.config_static_drop()
+    sim = sim_for(64, 64, cfg["params"], cfg["rhoN0"], "f32")
+    sim.step(2)
+    sim.live_pops()[0, 3, 10, 10] = float("nan")
+    sim.step(1)
+    with pytest.raises(lbm.LbmError) as ei:
+        sim.masses()
+    assert ei.value.code == lbm.LBM_ENONFINITE
+    sim.close()
+
+
+def test_masses_on_device_match_host_sum():
+    cfg = Wk.config_static_drop()
+    sim = sim_for(64, 64, cfg["params"], cfg["rhoN0"], "f64")
+    sim.step(5, with_mass=True)
+    dev = host(sim.mass)
+    buf = host(sim.live_pops())
+    assert abs(dev[0] - buf[0].sum()) < 1e-10 and abs(dev[1] - buf[1].sum()) < 1e-10
+    sim.close()
