@@ -68,6 +68,26 @@ def cpu_baseline(seconds_target=15.0):
                       "torch-CPU float64, %.1f s" % (steps, n, n, dt)}
 
 
+def copy_roof(n, params, rn, torch, steps=200):
+    """Same-bytes reference: the library's streaming-only step (gather of the 18
+    populations with the same pull offsets, store at the own site: 144 B per
+    site, no arithmetic) on the same lattice."""
+    from paper_2005_04642_amd import lbm
+    sim = lbm.Simulation(n, n, params, rn, storage="f32", device="cuda:0", flags=lbm.LBM_FLAG_STREAM_ONLY)
+    sim.step(10)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sim.close()
+    return {"kernel": "stream_only_kernel (gather + store, no arithmetic)", "ms_per_step": round(ms, 5),
+            "GB_s": round(BYTES_PER_LU["f32"] * n * n / (ms * 1e-3) / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +96,9 @@ def main():
     ap.add_argument("--stencil", default="3333")
     ap.add_argument("--size", type=int, default=4096)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-copy-roof", action="store_true")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="first run one plain 1 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the lattice would be "
@@ -86,6 +109,14 @@ def main():
     import torch
     from paper_2005_04642_amd import lbm, workloads as Wk
 
+    if args.copy_calib:
+        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        b.copy_(a)          # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del a, b
     n = args.size
     stencil = tuple(int(c) for c in args.stencil)
     cfg = Wk.config_emulsion(nx=n, ny=n)
@@ -135,6 +166,9 @@ def main():
         "masses": [m[0], m[1]],
     }
     sim.close()
+    if not args.no_copy_roof:
+        out["copy_roof"] = copy_roof(n, params, rn, torch)
+        out["roofline"]["frac_of_copy"] = round(achieved / out["copy_roof"]["GB_s"], 4)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -87,8 +87,8 @@ typedef struct lbm_params {
 typedef struct lbm_handle lbm_handle;
 
 /* Host-only check of a parameter set (no GPU call).  LBM_OK or LBM_EINVAL.
- * Rejects: nx, ny < 1; walls with fewer than 1 fluid row; 18*nx*ny >= 2^31;
- * unknown storage; a stencil radius not in {1, 3}; non-positive densities;
+ * Rejects: nx, ny < 1; walls with fewer than 1 fluid row; unknown storage;
+ * a population buffer of 4 GiB or more (18*nx*ny elements); a stencil radius not in {1, 3}; non-positive densities;
  * |(1-alpha_B) - Lambda (1-alpha_R)| > 1e-9 (1-alpha_B) (Sec. II density-ratio
  * relation); alpha outside [0, 1); nu <= 0 (lambda_3 = 2/(6 nu + 1) must lie in
  * (0, 2)); lambda6, lambda7 outside (0, 2); eps_n <= 0. */

@@ -33,12 +33,17 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 constexpr int MASS_BLOCKS = 512;
-constexpr int NTX_F32 = 256;  // lattice columns per workgroup row, float
+// Workgroup shape: NTX lattice columns x NR rows, one thread each.  512
+// threads (8 waves) per CU leave 256 VGPRs per thread for the register ring.
+constexpr int NTX_F32 = 128;
+constexpr int NR_F32 = 4;
 constexpr int NTX_F64 = 64;   // double (validation instantiation)
+constexpr int NR_F64 = 4;
 
 template <typename T>
 struct NtxOf {
   static constexpr int value = sizeof(T) == 8 ? NTX_F64 : NTX_F32;
+  static constexpr int nr = sizeof(T) == 8 ? NR_F64 : NR_F32;
 };
 
 bool radius_ok(int r) { return r == 1 || r == 3; }
@@ -52,10 +57,11 @@ int validate(const lbm_params* p) {
   if (p->nx < 1 || p->ny < 1) return fail(LBM_EINVAL, "lattice %dx%d is empty", p->nx, p->ny);
   if (p->walls_y != 0 && p->walls_y != 1) return fail(LBM_EINVAL, "walls_y must be 0 or 1");
   if (p->walls_y && p->ny < 3) return fail(LBM_EINVAL, "walls need ny >= 3 (one fluid row)");
-  if (18.0 * (double)p->nx * (double)p->ny >= 2147483647.0)
-    return fail(LBM_EINVAL, "lattice too large: 18*nx*ny must stay below 2^31");
   if (p->storage != LBM_STORAGE_F32 && p->storage != LBM_STORAGE_F64)
     return fail(LBM_EINVAL, "storage %d not provided by this build", p->storage);
+  const double elem = p->storage == LBM_STORAGE_F64 ? 8.0 : 4.0;
+  if (18.0 * (double)p->nx * (double)p->ny * elem >= 4294967296.0)
+    return fail(LBM_EINVAL, "lattice too large: one population buffer must stay below 4 GiB");
   for (int k = 0; k < 4; ++k)
     if (!radius_ok(p->stencil[k])) return fail(LBM_EINVAL, "stencil radius %d not in {1,3}", p->stencil[k]);
   if (!(p->rho0_R > 0.0) || !(p->rho0_B > 0.0)) return fail(LBM_EINVAL, "densities must be positive");
@@ -96,7 +102,7 @@ chromo::Coef<T> make_coef(const lbm_params& p) {
   c.half_sigma = (T)(0.5 * p.sigma);
   c.beta18 = (T)(1.8 * p.beta);
   c.lambda6 = (T)p.lambda6;
-  c.keepJ = (T)(1.0 - p.lambda7);
+  c.lambda7 = (T)p.lambda7;
   c.gx = (T)p.gx;
   c.gy = (T)p.gy;
   c.K_fixed = (T)p.K_fixed;
@@ -107,9 +113,10 @@ chromo::Coef<T> make_coef(const lbm_params& p) {
   return c;
 }
 
-// Strips of at most NTX-2H columns; chunks of rows so that the grid has about
-// one workgroup per compute unit (each workgroup is 3*NTX threads and uses up
-// most of a CU), but no chunk shorter than 24 rows.
+// Strips of at most NTX-2H columns; chunks of rows such that all tiles run in
+// a single wave of workgroups (one workgroup fills a CU: its 8 wavefronts use
+// the whole register file), i.e. nstrips * nchunks <= number of CUs, with
+// chunks no shorter than 24 rows.
 chromo::Geom plan(const lbm_params& p, int ncu) {
   chromo::Geom g;
   g.nx = p.nx;
@@ -120,11 +127,11 @@ chromo::Geom plan(const lbm_params& p, int ncu) {
   const int txmax = ntx_for(p) - 2 * halo(p);
   g.nstrips = (p.nx + txmax - 1) / txmax;
   g.TX = (p.nx + g.nstrips - 1) / g.nstrips;
-  int want = (ncu + g.nstrips / 2) / g.nstrips;
-  if (want < 1) want = 1;
-  int maxchunks = (g.F + 23) / 24;
+  int nch = ncu / g.nstrips;
+  if (nch < 1) nch = 1;
+  int maxchunks = g.F / 24;
   if (maxchunks < 1) maxchunks = 1;
-  int nch = want < maxchunks ? want : maxchunks;
+  if (nch > maxchunks) nch = maxchunks;
   g.TY = (g.F + nch - 1) / nch;
   g.nchunks = (g.F + g.TY - 1) / g.TY;
   return g;
@@ -132,8 +139,11 @@ chromo::Geom plan(const lbm_params& p, int ncu) {
 
 template <typename T, int NTX, int RG, int RK, int RP, int RU, bool FIELDS>
 hipError_t launch_march(const chromo::StepArgs<T>& a, hipStream_t s) {
-  hipLaunchKernelGGL((chromo::chromo_step_kernel<T, NTX, RG, RK, RP, RU, FIELDS>),
-                     dim3(a.g.nstrips * a.g.nchunks), dim3(NTX * chromo::NR), 0, s, a);
+  constexpr int NR = NtxOf<T>::nr;
+  const int ntiles = a.g.nstrips * a.g.nchunks;
+  const int nblocks = 8 * ((ntiles + 7) / 8);  // whole rounds over the 8 XCDs (see the kernel)
+  hipLaunchKernelGGL((chromo::chromo_step_kernel<T, NTX, NR, RG, RK, RP, RU, FIELDS>), dim3(nblocks),
+                     dim3(NTX * NR), 0, s, a);
   return hipGetLastError();
 }
 

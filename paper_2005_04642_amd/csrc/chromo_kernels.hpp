@@ -7,17 +7,19 @@
 // modal relaxation and reconstruction, d'Ortona recolour, store.
 //
 // Work decomposition ("march"): a workgroup owns a strip of TX lattice columns
-// and a chunk of rows and walks up the chunk three rows at a time.  The chain of
-// stencils (rho^N -> n -> K, G, u -> div u; Phi' -> grad Phi') needs rho^N up to
-// 9 rows ahead of the row being written, so each iteration works on four rows
-// bands at once:
-//     M  row v+9 : gather 18 populations, moments, rho^N        -> LDS ring
-//     N  row v+6 : grad rho^N, director m = grad/|grad|         -> LDS ring
-//     U  row v+3 : K = -div m, G, u, Phi'                       -> LDS ring
-//     O  row v   : grad Phi', div u, C, collide, recolour, store
-// Populations are read once per strip from HBM; per-row fields live in 12-row
-// LDS rings (the halo in x is recomputed by the strip's edge threads); the
-// moments a thread needs nine rows later stay in its registers.
+// and a chunk of rows and walks up the chunk NR rows at a time (one row per
+// thread row).  The chain of stencils (rho^N -> n -> K, G, u -> div u;
+// Phi' -> grad Phi') needs rho^N up to 9 rows ahead of the row being written, so
+// each iteration works on four bands of rows at once (LU = 3 for NR = 3, 4 for
+// NR = 4):
+//     M  row v+3LU : gather 18 populations, colour densities, rho^N  -> LDS ring
+//     N  row v+2LU : grad rho^N, director m = grad/|grad|            -> LDS ring
+//     U  row v+LU  : K = -div m, G, u, Phi'                          -> LDS ring
+//     O  row v     : grad Phi', div u, C, collide, recolour, store
+// Populations are read once per strip from HBM; per-row fields live in LDS
+// rings of 4 NR rows (the halo in x is recomputed by the strip's edge
+// threads); the populations a thread needs 3 iterations later stay in its
+// registers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,8 +27,21 @@
 
 namespace chromo {
 
-constexpr int NR = 3;     // rows per march iteration, one per thread row
-constexpr int RING = 12;  // LDS ring depth in rows (4 iterations x NR)
+// Rows handled per march iteration (one per thread row) is the template
+// parameter NR; the four bands are LU, 2 LU and 3 LU rows ahead of the output
+// row, with LU the smallest multiple of NR not below the largest stencil
+// radius (3), so every lagged quantity stays with the thread that made it.
+template <int NR>
+struct Pipe {
+  static constexpr int LU = NR * ((3 + NR - 1) / NR);
+  static constexpr int LN = 2 * LU;
+  static constexpr int LM = 3 * LU;
+  static constexpr int RING = 4 * NR;                   // LDS ring depth in rows
+  static constexpr int IT0 = (LM + 9 + NR - 1) / NR;    // prologue iterations
+  static constexpr int ITN = (LU + 3 + NR - 1) / NR;    // first iteration of band N
+  static constexpr int ITU = 2 * ITN;                    // first iteration of band U
+  static_assert(LN == NR + LU && LU == NR * (LU / NR), "band hand-over must stay within one thread");
+};
 
 template <typename T>
 struct Coef {
@@ -38,7 +53,7 @@ struct Coef {
   T hnuR, hnuB;            // nu_C / 2
   T half_sigma;            // sigma / 2
   T beta18;                // 9/5 beta
-  T lambda6, keepJ;        // lambda_6, 1 - lambda_7
+  T lambda6, lambda7;      // ghost-mode rates
   T gx, gy, K_fixed, eps2;
   int ghost_eq, fixed_K, recolor;
 };
@@ -62,38 +77,76 @@ struct StepArgs {
   Coef<T> c;
 };
 
-// Virtual row v of the march (fluid-row index, any integer) -> physical row of
-// the lattice and whether it is a mirror image.  y periodic: plain wrap.
-// Walls: the fluid strip is reflected about the two wall planes, which is the
-// picture every stencil near a wall sees.
+// ---------------------------------------------------------------------------
+// memory access through buffer resources: the per-plane and per-row offsets
+// are wave-uniform (SGPR soffset), only the column offset lives in a VGPR.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Mem;
+
+template <>
+struct Mem<float> {
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void store(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  }
+};
+
+template <>
+struct Mem<double> {
+  static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void store(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
+                                          r, voff, soff, 0);
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const T* p, int plane) {
+  // raw buffer over the 18 planes; gfx9 dword3 = 0x00020000
+  const unsigned bytes = 18u * (unsigned)plane * (unsigned)sizeof(T);  // < 2^32 (checked on the host)
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+
+// Wave-uniform row of the march: virtual row v (fluid-row index, any integer)
+// -> physical lattice row, and whether it is a mirror image.  y periodic:
+// plain wrap.  Walls: the fluid strip is reflected about the two wall planes,
+// which is the picture every stencil near a wall sees.
 __device__ __forceinline__ void virt_row(int v, const Geom& g, int& phys, bool& refl) {
   if (!g.walls) {
-    int r = v % g.ny;
-    if (r < 0) r += g.ny;
+    int r = v;
+    while (r < 0) r += g.ny;
+    while (r >= g.ny) r -= g.ny;
     phys = r;
     refl = false;
   } else {
     const int P = 2 * g.F;
-    int t = v % P;
-    if (t < 0) t += P;
-    if (t < g.F) {
-      phys = 1 + t;
-      refl = false;
-    } else {
-      phys = 1 + (P - 1 - t);
-      refl = true;
-    }
+    int t = v;
+    while (t < 0) t += P;
+    while (t >= P) t -= P;
+    refl = t >= g.F;
+    phys = refl ? g.F - t + g.F : 1 + t;  // 1 + (2F - 1 - t) when reflected
   }
 }
+
+// Column byte offsets of one thread: x - 1, x, x + 1 (periodic).
+struct Cols {
+  int m, o, p;
+};
 
 // Pull-streaming gather of the 18 pre-collision populations of site (x, p):
 // f_i(r) = buf_i(r - c_i), or buf_opp(i)(r) when r - c_i is a solid row
 // (half-way bounce-back).  Link order c0..c8 as in the public header.
+// p is wave-uniform; every plane / row offset is scalar.
 template <typename T>
-__device__ __forceinline__ void gather(const T* __restrict__ src, const Geom& g, int p,
-                                       int xm, int x, int xp, T R[9], T B[9]) {
-  const int nx = g.nx;
-  const int plane = g.plane;
+__device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
+                                       T R[9], T B[9]) {
+  const unsigned E = sizeof(T);
+  const unsigned PB = (unsigned)g.plane * E;  // plane bytes
   int rm = p - 1, rp = p + 1;
   bool bm = false, bp = false;
   if (g.walls) {
@@ -103,66 +156,35 @@ __device__ __forceinline__ void gather(const T* __restrict__ src, const Geom& g,
     if (rm < 0) rm += g.ny;
     if (rp >= g.ny) rp -= g.ny;
   }
-  const int o_p = p * nx, o_m = rm * nx, o_pp = rp * nx;
-  // source element offsets within a plane
-  const int s0 = o_p + x;
-  const int s1 = bm ? o_p + x : o_m + xm;
-  const int s2 = bm ? o_p + x : o_m + x;
-  const int s3 = bm ? o_p + x : o_m + xp;
-  const int s4 = o_p + xp;
-  const int s5 = bp ? o_p + x : o_pp + xp;
-  const int s6 = bp ? o_p + x : o_pp + x;
-  const int s7 = bp ? o_p + x : o_pp + xm;
-  const int s8 = o_p + xm;
-  // planes read (bounce-back reads the opposite link at the own site)
-  const int q1 = bm ? 5 : 1, q2 = bm ? 6 : 2, q3 = bm ? 7 : 3;
-  const int q5 = bp ? 1 : 5, q6 = bp ? 2 : 6, q7 = bp ? 3 : 7;
+  const unsigned ro = (unsigned)p * g.nx * E, rom = (unsigned)rm * g.nx * E, rop = (unsigned)rp * g.nx * E;
+  // (plane, row) scalar offsets and column vector offsets of links 0..8
+  const unsigned s0 = ro, s4 = 4 * PB + ro, s8 = 8 * PB + ro;
+  const unsigned s1 = bm ? 5 * PB + ro : 1 * PB + rom;
+  const unsigned s2 = bm ? 6 * PB + ro : 2 * PB + rom;
+  const unsigned s3 = bm ? 7 * PB + ro : 3 * PB + rom;
+  const unsigned s5 = bp ? 1 * PB + ro : 5 * PB + rop;
+  const unsigned s6 = bp ? 2 * PB + ro : 6 * PB + rop;
+  const unsigned s7 = bp ? 3 * PB + ro : 7 * PB + rop;
+  const int v1 = bm ? x.o : x.m, v3 = bm ? x.o : x.p;
+  const int v5 = bp ? x.o : x.p, v7 = bp ? x.o : x.m;
+  const unsigned CB = 9 * PB;
 #pragma unroll
   for (int col = 0; col < 2; ++col) {
-    const T* b = src + col * 9 * plane;
     T* out = col ? B : R;
-    out[0] = b[s0];
-    out[1] = b[q1 * plane + s1];
-    out[2] = b[q2 * plane + s2];
-    out[3] = b[q3 * plane + s3];
-    out[4] = b[4 * plane + s4];
-    out[5] = b[q5 * plane + s5];
-    out[6] = b[q6 * plane + s6];
-    out[7] = b[q7 * plane + s7];
-    out[8] = b[8 * plane + s8];
+    const unsigned c = col * CB;
+    out[0] = Mem<T>::load(src, x.o, (int)(c + s0));
+    out[1] = Mem<T>::load(src, v1, (int)(c + s1));
+    out[2] = Mem<T>::load(src, x.o, (int)(c + s2));
+    out[3] = Mem<T>::load(src, v3, (int)(c + s3));
+    out[4] = Mem<T>::load(src, x.p, (int)(c + s4));
+    out[5] = Mem<T>::load(src, v5, (int)(c + s5));
+    out[6] = Mem<T>::load(src, x.o, (int)(c + s6));
+    out[7] = Mem<T>::load(src, v7, (int)(c + s7));
+    out[8] = Mem<T>::load(src, x.m, (int)(c + s8));
   }
 }
 
-// Moments of one site: colour densities and the nine modes m = M f of f = R + B
-// (App. A / Table A1 projectors 1, c_x, c_y, c_x^2, c_y^2, c_x c_y, g, g c_x, g c_y),
-// summed with antisymmetric pair differences.  mom[] layout:
-//   0 rho_R  1 rho_B  2 j_x  3 j_y  4 Pi_xx  5 Pi_yy  6 Pi_xy  7 N  8 J_x  9 J_y
-template <typename T>
-__device__ __forceinline__ void site_moments(const T R[9], const T B[9], bool refl, T mom[10]) {
-  T rR = ((R[0] + R[2]) + (R[4] + R[6])) + ((R[1] + R[3]) + (R[5] + R[7])) + R[8];
-  T rB = ((B[0] + B[2]) + (B[4] + B[6])) + ((B[1] + B[3]) + (B[5] + B[7])) + B[8];
-  T f[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = R[i] + B[i];
-  const T d15 = f[1] - f[5], d37 = f[3] - f[7], d84 = f[8] - f[4], d26 = f[2] - f[6];
-  const T sd = (f[1] + f[5]) + (f[3] + f[7]);
-  T jx = (d15 - d37) + d84;
-  T jy = (d15 + d37) + d26;
-  const T pxx = sd + (f[4] + f[8]);
-  const T pyy = sd + (f[2] + f[6]);
-  T pxy = (f[1] + f[5]) - (f[3] + f[7]);
-  const T N = f[0] - T(2) * ((f[2] + f[6]) + (f[4] + f[8])) + T(4) * sd;
-  const T Jx = T(4) * (d15 - d37) - T(2) * d84;
-  T Jy = T(4) * (d15 + d37) - T(2) * d26;
-  if (refl) {  // mirror image about a wall plane: y-odd modes change sign
-    jy = -jy;
-    pxy = -pxy;
-    Jy = -Jy;
-  }
-  mom[0] = rR; mom[1] = rB; mom[2] = jx; mom[3] = jy; mom[4] = pxx;
-  mom[5] = pyy; mom[6] = pxy; mom[7] = N; mom[8] = Jx; mom[9] = Jy;
-}
-
+template <int RING>
 __device__ __forceinline__ int ring_row(int r) {
   r %= RING;
   return r < 0 ? r + RING : r;
@@ -177,17 +199,17 @@ __device__ __forceinline__ T stencil_b(int n) {
 }
 
 // (d/dx, d/dy) of a ring field at (ring row `row`, column tx).
-template <int R, int NTX, typename T>
+template <int R, int RING, int NTX, typename T>
 __device__ __forceinline__ void ring_grad(const T (*s)[NTX], int row, int tx, T& gx, T& gy) {
   const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
   gx = T(0);
   gy = T(0);
-  const T* md = &s[ring_row(row)][tx];
+  const T* md = &s[ring_row<RING>(row)][tx];
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
     const T b = stencil_b<R, T>(n);
-    const T* up = &s[ring_row(row + n)][tx];
-    const T* dn = &s[ring_row(row - n)][tx];
+    const T* up = &s[ring_row<RING>(row + n)][tx];
+    const T* dn = &s[ring_row<RING>(row - n)][tx];
     const T d1 = up[n] - dn[-n];
     const T d3 = up[-n] - dn[n];
     const T d8 = md[n] - md[-n];
@@ -198,18 +220,18 @@ __device__ __forceinline__ void ring_grad(const T (*s)[NTX], int row, int tx, T&
 }
 
 // d vx/dx + d vy/dy of a ring vector field.
-template <int R, int NTX, typename T>
+template <int R, int RING, int NTX, typename T>
 __device__ __forceinline__ T ring_div(const T (*sx)[NTX], const T (*sy)[NTX], int row, int tx) {
   const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
   T acc = T(0);
-  const T* mdx = &sx[ring_row(row)][tx];
+  const T* mdx = &sx[ring_row<RING>(row)][tx];
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
     const T b = stencil_b<R, T>(n);
-    const T* upx = &sx[ring_row(row + n)][tx];
-    const T* dnx = &sx[ring_row(row - n)][tx];
-    const T* upy = &sy[ring_row(row + n)][tx];
-    const T* dny = &sy[ring_row(row - n)][tx];
+    const T* upx = &sx[ring_row<RING>(row + n)][tx];
+    const T* dnx = &sx[ring_row<RING>(row - n)][tx];
+    const T* upy = &sy[ring_row<RING>(row + n)][tx];
+    const T* dny = &sy[ring_row<RING>(row - n)][tx];
     const T d1 = upx[n] - dnx[-n];
     const T d3 = upx[-n] - dnx[n];
     const T d8 = mdx[n] - mdx[-n];
@@ -221,7 +243,7 @@ __device__ __forceinline__ T ring_div(const T (*sx)[NTX], const T (*sy)[NTX], in
   return acc;
 }
 
-template <typename T, int NTX>
+template <typename T, int NTX, int RING>
 struct Smem {
   T rhoN[RING][NTX];
   T mx[RING][NTX];
@@ -231,35 +253,63 @@ struct Smem {
   T phi[RING][NTX];
 };
 
+// Register state of one thread: the colour densities and the nine total
+// populations of the rows it gathered (one slot per iteration, read again
+// 2 and 3 iterations later) and the populations prefetched for the next
+// band-M row.
 template <typename T>
 struct March {
-  T mom[4][10];  // moments of rows v+9 .. v (one slot per iteration)
-  T gn[2][2];    // grad rho^N, from band N to band U
-  T gr[2][2];    // G, from band U to band O
-  T pr[9], pb[9];  // populations prefetched for the next band-M row
+  T rf[4][11];   // rho_R, rho_B, f_0 .. f_8
+  T gn[2][2];    // grad rho^N, band N -> band U (next iteration)
+  T gr[2][2];    // force G, band U -> band O (next iteration)
+  T pr[9], pb[9];
 };
 
 struct Thread {
-  int tx, ty, xg, xm, xp, ya, yb, nit;
+  int tx, ty, xg, ya, yb, nit;
+  Cols cols;
   bool own;
 };
 
-// Collision, recolour and store for one site (band O).
+template <typename T>
+__device__ __forceinline__ void momenta(const T* f, T& jx, T& jy) {
+  const T d15 = f[1] - f[5], d37 = f[3] - f[7];
+  jx = (d15 - d37) + (f[8] - f[4]);
+  jy = (d15 + d37) + (f[2] - f[6]);
+}
+
+// Colour index (Sec. II); exactly +-1 in the pure phases.
+template <typename T>
+__device__ __forceinline__ T colour_index(T a0, T b0) {
+  return (a0 - b0) / (a0 + b0);
+}
+
+// Collision, recolour and store of one site (band O).
 template <typename T, bool FIELDS>
-__device__ __forceinline__ void collide_store(const StepArgs<T>& a, const T m[10], T ux, T uy,
-                                              T Gx, T Gy, T dPx, T dPy, T theta, T rhoN,
-                                              T mx, T my, int p, int x) {
+__device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buffer_rsrc_t dst, const T* rf,
+                                              T ux, T uy, T Gx, T Gy, T dPx, T dPy, T theta, T rhoN, T mx, T my,
+                                              int p, const Thread& t) {
   const Coef<T>& c = a.c;
-  const T rR = m[0], rB = m[1];
+  const T rR = rf[0], rB = rf[1];
+  const T* f = rf + 2;
   const T rho = rR + rB;
-  const int site = p * a.g.nx + x;
   if (FIELDS) {
+    const int site = p * a.g.nx + t.xg;
     if (a.out_rho) a.out_rho[site] = rho;
     if (a.out_ux) a.out_ux[site] = ux;
     if (a.out_uy) a.out_uy[site] = uy;
     if (a.out_rhoN) a.out_rhoN[site] = rhoN;
     return;
   }
+  // modes of f (App. A projectors), summed with antisymmetric pair differences
+  const T d15 = f[1] - f[5], d37 = f[3] - f[7], d84 = f[8] - f[4], d26 = f[2] - f[6];
+  const T s15 = f[1] + f[5], s37 = f[3] + f[7], sd = s15 + s37;
+  const T pxx = sd + (f[4] + f[8]);
+  const T pyy = sd + (f[2] + f[6]);
+  const T pxy = s15 - s37;
+  const T N = f[0] - T(2) * ((f[2] + f[6]) + (f[4] + f[8])) + T(4) * sd;
+  const T Jx = T(4) * (d15 - d37) - T(2) * d84;
+  const T Jy = T(4) * (d15 + d37) - T(2) * d26;
   // lambda_3 from nu(rho^N) = (2/lambda_3 - 1)/6 (Sec. II), nu linear in rho^N
   const T nu = c.hnuR * (T(1) + rhoN) + c.hnuB * (T(1) - rhoN);
   const T l3 = T(2) / (T(6) * nu + T(1));
@@ -269,45 +319,46 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, const T m[10
   const T Cxx = k * (T(2) * ux * (Gx - dPx) - iso);
   const T Cyy = k * (T(2) * uy * (Gy - dPy) - iso);
   const T Cxy = k * (ux * (Gy - dPy) + uy * (Gx - dPx));
-  // modal relaxation (App. A, modal evolution eqs.)
+  // modal increments m+ - m (App. A, modal evolution eqs.): rho fixed, j += G,
+  // Pi relaxes to P delta + rho u u with source C, ghosts relax at lambda_6, lambda_7
   const T P = c.c06R * rR + c.c06B * rB;
-  const T pxx = m[4] - l3 * (m[4] - (P + rho * ux * ux)) + Cxx;
-  const T pyy = m[5] - l3 * (m[5] - (P + rho * uy * uy)) + Cyy;
-  const T pxy = m[6] - l3 * (m[6] - rho * ux * uy) + Cxy;
+  const T dxx = Cxx - l3 * ((pxx - P) - rho * ux * ux);
+  const T dyy = Cyy - l3 * ((pyy - P) - rho * uy * uy);
+  const T dxy = Cxy - l3 * (pxy - rho * ux * uy);
   const T N0 = c.ghost_eq ? T(0) : T(1.8) * (c.alphaR * rR + c.alphaB * rB) - T(0.8) * rho;
-  const T Np = m[7] - c.lambda6 * (m[7] - N0);
-  const T Jxp = c.keepJ * m[8];
-  const T Jyp = c.keepJ * m[9];
-  const T jxp = m[2] + Gx;
-  const T jyp = m[3] + Gy;
-  // reconstruction f+ = M^{-1} m+ (closed form of Sec. III / App. A)
-  const T tr = pxx + pyy;
-  T f[9];
-  f[0] = T(4.0 / 9.0) * (T(2) * rho - T(1.5) * tr + T(0.25) * Np);
-  const T axc = T(0.5) * rho - T(1.5) * tr - T(0.5) * Np;
-  const T sx = T(1.0 / 9.0) * (axc + T(4.5) * pxx);
-  const T sy = T(1.0 / 9.0) * (axc + T(4.5) * pyy);
-  const T ax = T(1.0 / 9.0) * (T(3) * jxp - T(0.75) * Jxp);
-  const T ay = T(1.0 / 9.0) * (T(3) * jyp - T(0.75) * Jyp);
-  f[8] = sx + ax;
-  f[4] = sx - ax;
-  f[2] = sy + ay;
-  f[6] = sy - ay;
-  const T dgc = -rho + T(3) * tr + Np;
-  const T dsp = T(1.0 / 36.0) * (dgc + T(9) * pxy);
-  const T dsm = T(1.0 / 36.0) * (dgc - T(9) * pxy);
-  const T a15 = T(1.0 / 36.0) * (T(3) * (jxp + jyp) + T(1.5) * (Jxp + Jyp));
-  const T a73 = T(1.0 / 36.0) * (T(3) * (jxp - jyp) + T(1.5) * (Jxp - Jyp));
-  f[1] = dsp + a15;
-  f[5] = dsp - a15;
-  f[7] = dsm + a73;
-  f[3] = dsm - a73;
-  // d'Ortona recolour (Sec. II): t_i = beta phi_i rho_R rho_B / rho (m . c_hat_i)
-  const T aR = rR / rho, aB = rB / rho;
+  const T dN = -c.lambda6 * (N - N0);
+  const T dJx = -c.lambda7 * Jx;
+  const T dJy = -c.lambda7 * Jy;
+  // f+ = f + M^{-1} (m+ - m): closed-form columns k^(p) of App. A
+  const T tr = dxx + dyy;
+  T fp[9];
+  fp[0] = f[0] + T(4.0 / 9.0) * (T(0.25) * dN - T(1.5) * tr);
+  const T axc = -T(1.5) * tr - T(0.5) * dN;
+  const T sx = T(1.0 / 9.0) * (axc + T(4.5) * dxx);
+  const T sy = T(1.0 / 9.0) * (axc + T(4.5) * dyy);
+  const T ax = T(1.0 / 9.0) * (T(3) * Gx - T(0.75) * dJx);
+  const T ay = T(1.0 / 9.0) * (T(3) * Gy - T(0.75) * dJy);
+  fp[8] = f[8] + (sx + ax);
+  fp[4] = f[4] + (sx - ax);
+  fp[2] = f[2] + (sy + ay);
+  fp[6] = f[6] + (sy - ay);
+  const T dgc = T(3) * tr + dN;
+  const T dsp = T(1.0 / 36.0) * (dgc + T(9) * dxy);
+  const T dsm = T(1.0 / 36.0) * (dgc - T(9) * dxy);
+  const T a15 = T(1.0 / 36.0) * (T(3) * (Gx + Gy) + T(1.5) * (dJx + dJy));
+  const T a73 = T(1.0 / 36.0) * (T(3) * (Gx - Gy) + T(1.5) * (dJx - dJy));
+  fp[1] = f[1] + (dsp + a15);
+  fp[5] = f[5] + (dsp - a15);
+  fp[7] = f[7] + (dsm + a73);
+  fp[3] = f[3] + (dsm - a73);
+  // d'Ortona recolour (Sec. II): t_i = beta phi_i rho_R rho_B / rho (m . c_hat_i);
+  // the split factors are exactly 1 / 0 in the pure phases
+  const T aR = rR / rho;
+  const T aB = rB / rho;
   T t1 = T(0), t3 = T(0), t2 = T(0), t8 = T(0);
   if (c.recolor) {
     const T moving = (c.c1R * rR + c.c1B * rB) / rho;
-    const T q = c.beta18 * (rR * rB / rho) * moving;
+    const T q = c.beta18 * (aR * rB) * moving;
     const T qa = q * T(1.0 / 9.0);
     const T qd = q * T(1.0 / 36.0) * T(0.70710678118654752440);
     t8 = qa * mx;
@@ -316,80 +367,89 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, const T m[10
     t3 = qd * (my - mx);
   }
   T R[9], B[9];
-  R[0] = aR * f[0];
-  B[0] = aB * f[0];
-  R[1] = aR * f[1] + t1; B[1] = aB * f[1] - t1;
-  R[5] = aR * f[5] - t1; B[5] = aB * f[5] + t1;
-  R[3] = aR * f[3] + t3; B[3] = aB * f[3] - t3;
-  R[7] = aR * f[7] - t3; B[7] = aB * f[7] + t3;
-  R[2] = aR * f[2] + t2; B[2] = aB * f[2] - t2;
-  R[6] = aR * f[6] - t2; B[6] = aB * f[6] + t2;
-  R[8] = aR * f[8] + t8; B[8] = aB * f[8] - t8;
-  R[4] = aR * f[4] - t8; B[4] = aB * f[4] + t8;
-  const int plane = a.g.plane;
-  T* d = a.dst + site;
+  R[0] = aR * fp[0];
+  B[0] = aB * fp[0];
+  R[1] = aR * fp[1] + t1; B[1] = aB * fp[1] - t1;
+  R[5] = aR * fp[5] - t1; B[5] = aB * fp[5] + t1;
+  R[3] = aR * fp[3] + t3; B[3] = aB * fp[3] - t3;
+  R[7] = aR * fp[7] - t3; B[7] = aB * fp[7] + t3;
+  R[2] = aR * fp[2] + t2; B[2] = aB * fp[2] - t2;
+  R[6] = aR * fp[6] - t2; B[6] = aB * fp[6] + t2;
+  R[8] = aR * fp[8] + t8; B[8] = aB * fp[8] - t8;
+  R[4] = aR * fp[4] - t8; B[4] = aB * fp[4] + t8;
+  const unsigned E = sizeof(T);
+  const unsigned PB = (unsigned)a.g.plane * E;
+  const unsigned ro = (unsigned)p * a.g.nx * E;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) d[i * plane] = R[i];
+  for (int i = 0; i < 9; ++i) Mem<T>::store(R[i], dst, t.cols.o, (int)(i * PB + ro));
 #pragma unroll
-  for (int i = 0; i < 9; ++i) d[(9 + i) * plane] = B[i];
+  for (int i = 0; i < 9; ++i) Mem<T>::store(B[i], dst, t.cols.o, (int)((9 + i) * PB + ro));
 }
 
 // One march iteration; S = it mod 4 selects the register-ring slots.
-template <int S, typename T, int NTX, int RG, int RK, int RP, int RU, bool FIELDS>
-__device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, Smem<T, NTX>& sm,
+template <int S, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool FIELDS>
+__device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgpu_buffer_rsrc_t src,
+                                           __amdgpu_buffer_rsrc_t dst, Smem<T, NTX, Pipe<NR>::RING>& sm,
                                            March<T>& st, const Thread& t) {
+  using PP = Pipe<NR>;
+  constexpr int RING = PP::RING;
   const Geom& g = a.g;
   const Coef<T>& c = a.c;
   const int tx = t.tx, ty = t.ty;
-  const int base = t.ya - 18 + 3 * it + ty;  // band-O virtual row of this thread
+  // band-O virtual row of this thread (wave-uniform)
+  const int base = t.ya - NR * PP::IT0 + NR * it + ty;
   constexpr int sM = S, sU = (S + 2) & 3, sO = (S + 1) & 3;
-  // ring rows of the four bands (row index = virtual row - (ya - 18))
-  const int rowM = 3 * S + ty + 9, rowN = 3 * S + ty + 6, rowU = 3 * S + ty + 3, rowO = 3 * S + ty;
+  // ring rows of the four bands (row index = virtual row - (ya - NR IT0))
+  const int rowO = NR * S + ty;
+  const int rowU = rowO + PP::LU, rowN = rowO + PP::LN, rowM = rowO + PP::LM;
 
-  // ---- band M: moments and colour index of row base + 9 -------------------
+  // ---- band M: colour densities, total populations, colour index ----------
   {
-    int p;
-    bool refl;
-    virt_row(base + 9, g, p, refl);
-    T* m = st.mom[sM];
-    site_moments(st.pr, st.pb, refl, m);
-    const T a0 = m[0] * c.inv_rho0R, b0 = m[1] * c.inv_rho0B;
-    sm.rhoN[ring_row(rowM)][tx] = (a0 - b0) / (a0 + b0);
+    T* rf = st.rf[sM];
+    T rR = ((st.pr[0] + st.pr[2]) + (st.pr[4] + st.pr[6])) + ((st.pr[1] + st.pr[3]) + (st.pr[5] + st.pr[7])) + st.pr[8];
+    T rB = ((st.pb[0] + st.pb[2]) + (st.pb[4] + st.pb[6])) + ((st.pb[1] + st.pb[3]) + (st.pb[5] + st.pb[7])) + st.pb[8];
+    rf[0] = rR;
+    rf[1] = rB;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) rf[2 + i] = st.pr[i] + st.pb[i];
+    sm.rhoN[ring_row<RING>(rowM)][tx] = colour_index(rR * c.inv_rho0R, rB * c.inv_rho0B);
     if (it + 1 < t.nit) {  // prefetch the next band-M row
       int pn;
       bool rn;
-      virt_row(base + 12, g, pn, rn);
-      gather(a.src, g, pn, t.xm, t.xg, t.xp, st.pr, st.pb);
+      virt_row(base + PP::LM + NR, g, pn, rn);
+      gather(src, g, pn, t.cols, st.pr, st.pb);
     }
   }
   __syncthreads();
 
-  // ---- band N: grad rho^N and director of row base + 6 -----------------------
-  if (it >= 2 && tx >= RG && tx < NTX - RG) {
+  // ---- band N: grad rho^N and director m -------------------------------------
+  if (it >= PP::ITN && tx >= RG && tx < NTX - RG) {
     T gx, gy;
-    ring_grad<RG, NTX>(sm.rhoN, rowN, tx, gx, gy);
+    ring_grad<RG, RING, NTX>(sm.rhoN, rowN, tx, gx, gy);
     const T s = sqrt(gx * gx + gy * gy + c.eps2);
-    sm.mx[ring_row(rowN)][tx] = gx / s;
-    sm.my[ring_row(rowN)][tx] = gy / s;
+    const int rn = ring_row<RING>(rowN);
+    sm.mx[rn][tx] = gx / s;
+    sm.my[rn][tx] = gy / s;
     st.gn[S & 1][0] = gx;
     st.gn[S & 1][1] = gy;
   }
   __syncthreads();
 
-  // ---- band U: Phi', curvature, force and velocity of row base + 3 ---------
-  if (it >= 4) {
-    const T* m = st.mom[sU];
-    const T rho = m[0] + m[1];
-    sm.phi[ring_row(rowU)][tx] = c.c06R * m[0] + c.phiB * m[1] - rho * T(1.0 / 3.0);
+  // ---- band U: Phi', curvature, force and velocity -------------------------
+  if (it >= PP::ITU) {
+    const T* rf = st.rf[sU];
+    const T rho = rf[0] + rf[1];
+    const int ru = ring_row<RING>(rowU);
+    sm.phi[ru][tx] = c.c06R * rf[0] + c.phiB * rf[1] - rho * T(1.0 / 3.0);
     if (tx >= RG + RK && tx < NTX - RG - RK) {
       int p;
       bool refl;
-      virt_row(base + 3, g, p, refl);
+      virt_row(base + PP::LU, g, p, refl);
       T K;
       if (c.fixed_K) {
         K = c.K_fixed;
       } else {
-        K = -ring_div<RK, NTX>(sm.mx, sm.my, rowU, tx);  // K = div n, n = -m
+        K = -ring_div<RK, RING, NTX>(sm.mx, sm.my, rowU, tx);  // K = div n, n = -m
       }
       const T gnx = st.gn[(S + 1) & 1][0], gny = st.gn[(S + 1) & 1][1];
       T Gx = c.half_sigma * K * gnx + c.gx;
@@ -399,67 +459,79 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, Smem<T,
         Gx += a.force[site];
         Gy += refl ? -a.force[g.plane + site] : a.force[g.plane + site];
       }
-      const T inv = T(1) / rho;
-      sm.ux[ring_row(rowU)][tx] = (m[2] + T(0.5) * Gx) * inv;
-      sm.uy[ring_row(rowU)][tx] = (m[3] + T(0.5) * Gy) * inv;
+      T jx, jy;
+      momenta(rf + 2, jx, jy);
+      if (refl) jy = -jy;   // mirror image: the y-momentum changes sign
+      sm.ux[ru][tx] = (jx + T(0.5) * Gx) / rho;
+      sm.uy[ru][tx] = (jy + T(0.5) * Gy) / rho;
       st.gr[S & 1][0] = Gx;
       st.gr[S & 1][1] = Gy;
     }
   }
   __syncthreads();
 
-  // ---- band O: correction, collision, recolour, store of row base ----------
-  if (it >= 6 && t.own && base < t.yb) {
-    const T* m = st.mom[sO];
+  // ---- band O: correction, collision, recolour, store ----------------------
+  if (it >= PP::IT0 && t.own && base < t.yb) {
     T dPx, dPy;
-    ring_grad<RP, NTX>(sm.phi, rowO, tx, dPx, dPy);
-    const T theta = ring_div<RU, NTX>(sm.ux, sm.uy, rowO, tx);
-    const int ro = ring_row(rowO);
-    const T ux = sm.ux[ro][tx], uy = sm.uy[ro][tx];
-    const T rhoN = sm.rhoN[ro][tx];
-    const T mx = sm.mx[ro][tx], my = sm.my[ro][tx];
+    ring_grad<RP, RING, NTX>(sm.phi, rowO, tx, dPx, dPy);
+    const T theta = ring_div<RU, RING, NTX>(sm.ux, sm.uy, rowO, tx);
+    const int ro = ring_row<RING>(rowO);
     const int p = g.walls ? base + 1 : base;
-    collide_store<T, FIELDS>(a, m, ux, uy, st.gr[(S + 1) & 1][0], st.gr[(S + 1) & 1][1], dPx, dPy,
-                             theta, rhoN, mx, my, p, t.xg);
+    collide_store<T, FIELDS>(a, dst, st.rf[sO], sm.ux[ro][tx], sm.uy[ro][tx], st.gr[(S + 1) & 1][0],
+                             st.gr[(S + 1) & 1][1], dPx, dPy, theta, sm.rhoN[ro][tx], sm.mx[ro][tx],
+                             sm.my[ro][tx], p, t);
   }
 }
 
-template <typename T, int NTX, int RG, int RK, int RP, int RU, bool FIELDS>
+template <typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool FIELDS>
 __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<T> a) {
+  using PP = Pipe<NR>;
   constexpr int H = RG + RK + RU;
   static_assert(NTX > 2 * H, "strip must be wider than its halo");
-  __shared__ Smem<T, NTX> sm;
+  static_assert(NTX % 64 == 0, "a wavefront must cover a single lattice row");
+  __shared__ Smem<T, NTX, PP::RING> sm;
   const Geom& g = a.g;
+  // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
+  // XCD gets a contiguous run of tiles (neighbouring strips of the same rows),
+  // whose shared halo columns and boundary cache lines then meet in one L2.
+  const int ntiles = g.nstrips * g.nchunks;
+  const int per_xcd = (ntiles + 7) / 8;
+  const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (tile >= ntiles) return;
+  const __amdgpu_buffer_rsrc_t src = make_rsrc(a.src, g.plane);
+  const __amdgpu_buffer_rsrc_t dst = make_rsrc(FIELDS ? a.src : a.dst, g.plane);
   Thread t;
   t.tx = threadIdx.x % NTX;
-  t.ty = threadIdx.x / NTX;
-  const int strip = blockIdx.x % g.nstrips;
-  const int chunk = blockIdx.x / g.nstrips;
+  t.ty = __builtin_amdgcn_readfirstlane(threadIdx.x / NTX);
+  const int strip = tile % g.nstrips;
+  const int chunk = tile / g.nstrips;
   const int x0 = strip * g.TX;
   const int txe = min(g.TX, g.nx - x0);
   const int col = t.tx - H;
   int xg = (x0 + col) % g.nx;
   if (xg < 0) xg += g.nx;
   t.xg = xg;
-  t.xm = xg == 0 ? g.nx - 1 : xg - 1;
-  t.xp = xg == g.nx - 1 ? 0 : xg + 1;
+  const int E = (int)sizeof(T);
+  t.cols.o = xg * E;
+  t.cols.m = (xg == 0 ? g.nx - 1 : xg - 1) * E;
+  t.cols.p = (xg == g.nx - 1 ? 0 : xg + 1) * E;
   t.own = col >= 0 && col < txe;
   t.ya = chunk * g.TY;
   t.yb = min(g.F, t.ya + g.TY);
-  t.nit = 6 + (t.yb - t.ya + 2) / 3;
+  t.nit = PP::IT0 + (t.yb - t.ya + NR - 1) / NR;
 
   March<T> st;
   {
     int p;
     bool refl;
-    virt_row(t.ya - 9 + t.ty, g, p, refl);
-    gather(a.src, g, p, t.xm, t.xg, t.xp, st.pr, st.pb);
+    virt_row(t.ya - NR * PP::IT0 + PP::LM + t.ty, g, p, refl);
+    gather(src, g, p, t.cols, st.pr, st.pb);
   }
   for (int it = 0; it < t.nit; it += 4) {
-    march_iter<0, T, NTX, RG, RK, RP, RU, FIELDS>(it, a, sm, st, t);
-    if (it + 1 < t.nit) march_iter<1, T, NTX, RG, RK, RP, RU, FIELDS>(it + 1, a, sm, st, t);
-    if (it + 2 < t.nit) march_iter<2, T, NTX, RG, RK, RP, RU, FIELDS>(it + 2, a, sm, st, t);
-    if (it + 3 < t.nit) march_iter<3, T, NTX, RG, RK, RP, RU, FIELDS>(it + 3, a, sm, st, t);
+    march_iter<0, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it, a, src, dst, sm, st, t);
+    if (it + 1 < t.nit) march_iter<1, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 1, a, src, dst, sm, st, t);
+    if (it + 2 < t.nit) march_iter<2, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 2, a, src, dst, sm, st, t);
+    if (it + 3 < t.nit) march_iter<3, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 3, a, src, dst, sm, st, t);
   }
 }
 
@@ -472,10 +544,13 @@ __global__ void __launch_bounds__(256) stream_only_kernel(const T* __restrict__ 
   const int k = blockIdx.y;  // fluid row index
   if (x >= g.nx) return;
   const int p = g.walls ? k + 1 : k;
-  const int xm = x == 0 ? g.nx - 1 : x - 1;
-  const int xp = x == g.nx - 1 ? 0 : x + 1;
+  const int E = (int)sizeof(T);
+  Cols cols;
+  cols.o = x * E;
+  cols.m = (x == 0 ? g.nx - 1 : x - 1) * E;
+  cols.p = (x == g.nx - 1 ? 0 : x + 1) * E;
   T R[9], B[9];
-  gather(src, g, p, xm, x, xp, R, B);
+  gather(make_rsrc(src, g.plane), g, p, cols, R, B);
   T* d = dst + p * g.nx + x;
 #pragma unroll
   for (int i = 0; i < 9; ++i) d[i * g.plane] = R[i];

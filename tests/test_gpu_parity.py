@@ -177,14 +177,26 @@ def test_static_drop_f64_1000_steps(static_drop_oracle):
     assert abs(m1[0] - m0[0]) / m0[0] < 1e-13 and abs(m1[1] - m0[1]) / m0[1] < 1e-13
 
 
+# FP32 tolerances.  rho: 1e-5 relative.  u: the static drop's velocity after
+# 1000 steps is the interfacial micro-current (max |u| ~ 3e-4) carried by
+# populations of order 1, so one FP32 ulp of a rest population (6e-8) is
+# already 2e-4 of max |u|: rounding the state to FP32 after every step, with
+# exact arithmetic otherwise, leaves e_u = 1.1e-4 after 1000 steps.  The test
+# therefore asks for e_u <= 1e-3 (the storage floor times a small factor for
+# FP32 arithmetic), and for the GPU to be at least as accurate as the same
+# algorithm evaluated in FP32 on the CPU.
+FP32_TOL_RHO = 1e-5
+FP32_TOL_U = 1e-3
+
+
 def test_static_drop_f32_1000_steps(static_drop_oracle):
     fo, fo32 = static_drop_oracle
     cfg, f, m0, m1 = run_static_drop("f32")
     e_rho, e_u = drop_errors(f, fo)
     floor_rho, floor_u = drop_errors(fo32, fo)
     print("static drop f32: e_rho %.3e e_u %.3e (fp32 oracle floor: %.3e %.3e)" % (e_rho, e_u, floor_rho, floor_u))
-    assert e_rho < 1e-5
-    assert e_u < 1e-5
+    assert e_rho < FP32_TOL_RHO and e_rho <= floor_rho
+    assert e_u < FP32_TOL_U and e_u <= floor_u
     assert abs(m1[0] - m0[0]) / m0[0] < 1e-6 and abs(m1[1] - m0[1]) / m0[1] < 1e-6
 
 
@@ -192,7 +204,7 @@ def test_static_drop_f32_1000_steps(static_drop_oracle):
 # walls: layered channel (reduced size), FP64 and FP32
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-11), ("f32", 1e-5)])
+@pytest.mark.parametrize("storage,tol", [("f64", (1e-11, 1e-11)), ("f32", (1e-5, 1e-3))])
 def test_layered_channel_parity(storage, tol):
     nx, ny, steps = 48, 66, 400
     params = Wk.base_params(Lambda=10.0, sigma=0.01)
@@ -208,7 +220,7 @@ def test_layered_channel_parity(storage, tol):
     e_rho = float(np.max(np.abs(f["rho"] - fo["rho"]) / fo["rho"]))
     e_u = float(np.max(np.hypot(f["ux"] - fo["ux"], f["uy"] - fo["uy"])) / np.max(np.hypot(fo["ux"], fo["uy"])))
     print("channel %s: e_rho %.3e e_u %.3e" % (storage, e_rho, e_u))
-    assert e_rho < tol and e_u < tol
+    assert e_rho < tol[0] and e_u < tol[1]
 
 
 # ---------------------------------------------------------------------------
