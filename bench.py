@@ -1,12 +1,14 @@
 """Benchmark: D2Q9 chromodynamic MRT step on the 4096x4096 emulsion (FP32).
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--stencil 3333] [--no-cpu]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--stencil 3333]
+                [--storage f32|f16|bf16] [--no-cpu]
 
 Prints one JSON line: MLUPS of the whole step (all stages: gather, fields,
 stencils, force, collision, recolour, store) with the populations resident in
-HBM, the roofline of the step kernel (HBM bound: 144 algorithmic bytes per
-lattice update, read + write of 18 FP32 populations) and the CPU oracle timed
-on a bounded sample of the same workload.
+HBM, the roofline of the step kernel (HBM bound: algorithmic bytes per lattice
+update = read + write of one site's population words: 144 B for FP32 storage,
+80 B for the 16-bit offset formats) and the CPU oracle timed on a bounded
+sample of the same workload.
 """
 import argparse
 import hashlib
@@ -19,10 +21,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0            # MI355X HBM3E, 8 TB/s
-BYTES_PER_LU = {"f32": 144, "f64": 288}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_emulsion4096.json")
+BYTES_PER_LU = {"f32": 144, "f64": 288, "f16": 80, "bf16": 80}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2005_04642_amd", "csrc", f)
-                  for f in ("chromo_kernels.hpp", "chromo_api.hip")]
+                  for f in ("chromo_kernels.hpp", "chromo_launch.hpp", "chromo_host.hpp", "chromo_api.hip")]
+
+
+STORAGE_NAME = {"f32": "FP32", "f16": "FP16-offset (16-bit words, FP32 arithmetic)",
+                "bf16": "BF16-offset (16-bit words, FP32 arithmetic)"}
+
+
+def traffic_file(storage):
+    return os.path.join(ROOT, "profiles", "traffic_step_emulsion4096_%s.json" % storage)
 
 
 def kernel_hash():
@@ -32,11 +41,11 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(storage):
     """HBM bytes per launch from the committed rocprofv3 counter runs, if they
     were taken on the current kernel source (else None)."""
     try:
-        d = json.load(open(TRAFFIC_FILE))
+        d = json.load(open(traffic_file(storage)))
     except (OSError, ValueError):
         return None
     if d.get("kernel_hash") != kernel_hash():
@@ -68,12 +77,12 @@ def cpu_baseline(seconds_target=15.0):
                       "torch-CPU float64, %.1f s" % (steps, n, n, dt)}
 
 
-def copy_roof(n, params, rn, torch, steps=200):
-    """Same-bytes reference: the library's streaming-only step (gather of the 18
-    populations with the same pull offsets, store at the own site: 144 B per
-    site, no arithmetic) on the same lattice."""
+def copy_roof(n, params, rn, torch, storage, steps=200):
+    """Same-bytes reference: the library's streaming-only step (gather of the
+    site's words with the same pull offsets, store at the own site, no
+    arithmetic) on the same lattice and storage format."""
     from paper_2005_04642_amd import lbm
-    sim = lbm.Simulation(n, n, params, rn, storage="f32", device="cuda:0", flags=lbm.LBM_FLAG_STREAM_ONLY)
+    sim = lbm.Simulation(n, n, params, rn, storage=storage, device="cuda:0", flags=lbm.LBM_FLAG_STREAM_ONLY)
     sim.step(10)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -85,7 +94,7 @@ def copy_roof(n, params, rn, torch, steps=200):
     ms = e0.elapsed_time(e1) / steps
     sim.close()
     return {"kernel": "stream_only_kernel (gather + store, no arithmetic)", "ms_per_step": round(ms, 5),
-            "GB_s": round(BYTES_PER_LU["f32"] * n * n / (ms * 1e-3) / 1e9, 1)}
+            "GB_s": round(BYTES_PER_LU[storage] * n * n / (ms * 1e-3) / 1e9, 1)}
 
 
 def main():
@@ -95,6 +104,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--stencil", default="3333")
     ap.add_argument("--size", type=int, default=4096)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"],
+                    help="population storage: FP32, or the 16-bit offset formats (FP32 arithmetic)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy-roof", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
@@ -122,9 +133,10 @@ def main():
     cfg = Wk.config_emulsion(nx=n, ny=n)
     params = dict(cfg["params"], stencil=stencil)
     rn = cfg["rhoN0"] if cfg["rhoN0"] is not None else Wk.emulsion(n, n, 50, 20.0, 80.0, 6.0, 0)
-    sim = lbm.Simulation(n, n, params, rn, storage="f32", device="cuda:0")
-    print("bench: emulsion %dx%d f32 stencil %s, warmup %d, steps %d" % (n, n, args.stencil, args.warmup,
-                                                                         args.steps), file=sys.stderr, flush=True)
+    sim = lbm.Simulation(n, n, params, rn, storage=args.storage, device="cuda:0")
+    print("bench: emulsion %dx%d %s stencil %s, warmup %d, steps %d" % (n, n, args.storage, args.stencil,
+                                                                        args.warmup, args.steps),
+          file=sys.stderr, flush=True)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -141,9 +153,9 @@ def main():
     sites = n * n
     ms_per_step = ms_event / args.steps
     mlups = sites / (ms_per_step * 1e-3) / 1e6
-    bytes_launch = BYTES_PER_LU["f32"] * sites
+    bytes_launch = BYTES_PER_LU[args.storage] * sites
     achieved = bytes_launch / (ms_per_step * 1e-3) / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic(args.storage)
     out = {
         "metric": "MLUPS, D2Q9 chromodynamic MRT step (4096^2 emulsion)",
         "value": round(mlups, 1),
@@ -158,8 +170,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "emulsion %dx%d periodic, 50 drops r~U[20,80], Lambda=10, sigma=0.005, "
-                               "beta=0.67, nu=1/6, stencil radii %s, FP32 storage" % (n, n, args.stencil),
-                   "nx": n, "ny": n, "stencil": list(stencil)},
+                               "beta=0.67, nu=1/6, stencil radii %s, %s storage"
+                               % (n, n, args.stencil, STORAGE_NAME[args.storage]),
+                   "nx": n, "ny": n, "stencil": list(stencil), "storage": args.storage},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic},
         "wall_s": round(wall, 3),
@@ -167,7 +180,7 @@ def main():
     }
     sim.close()
     if not args.no_copy_roof:
-        out["copy_roof"] = copy_roof(n, params, rn, torch)
+        out["copy_roof"] = copy_roof(n, params, rn, torch, args.storage)
         out["roofline"]["frac_of_copy"] = round(achieved / out["copy_roof"]["GB_s"], 4)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

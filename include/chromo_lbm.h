@@ -19,14 +19,29 @@
  * small host-side handle (pointers, parameters, step counter, which of the two
  * population buffers is live).  Nothing here allocates device memory.
  *
- * Populations: two buffers of 18*nx*ny elements, layout [colour 2][link 9][ny][nx]
- * (x fastest, colour 0 = red).  The live buffer holds, for every site r and
- * link i, the post-recolour population of the previous step at its source site
- * (a "pull" layout): the pre-collision population of the current step is
- * f_i(r) = buf_i(r - c_i), or buf_opp(i)(r) when r - c_i is a solid row.
- * Link order: c0=(0,0) c1=(1,1) c2=(0,1) c3=(-1,1) c4=(-1,0) c5=(-1,-1)
- * c6=(0,-1) c7=(1,-1) c8=(1,0)  (odd links are the diagonal ones).
- * Element type: double for LBM_STORAGE_F64, float for LBM_STORAGE_F32.
+ * Populations: two buffers of lbm_pops_bytes() bytes each, holding NW words
+ * per site in NW planes [NW][ny][nx] (x fastest).  The live buffer holds, for
+ * every site r and link i, the post-recolour populations of the previous step
+ * at their source site (a "pull" layout): the pre-collision population of the
+ * current step is C_i(r) = buf_i(r - c_i), or buf_opp(i)(r) when r - c_i is a
+ * solid row.  Link order: c0=(0,0) c1=(1,1) c2=(0,1) c3=(-1,1) c4=(-1,0)
+ * c5=(-1,-1) c6=(0,-1) c7=(1,-1) c8=(1,0) (odd links are the diagonal ones,
+ * opp(i) = i +- 4).  Storage formats:
+ *   LBM_STORAGE_F64 / _F32: NW = 18 words of double / float, word 9 c + i =
+ *     population of colour c (0 red, 1 blue) on link i.
+ *   LBM_STORAGE_F16_OFS / _BF16_OFS (16-bit offsets, FP32 arithmetic): NW = 10
+ *     words of 4 bytes.  Word 0 = R_0, word 1 = B_0 (float).  Word 1 + i
+ *     (i = 1..8) packs link i of both colours: bits 0-15 =
+ *     1024 (f_i - fref_i) / fref_i in FP16 (F16_OFS) or BF16 (BF16_OFS),
+ *     f_i = R_i + B_i, fref_i = (9/5) w_i rho0_R (1 - alpha_R) (the rest value
+ *     of f_i, equal in both pure phases by the density-ratio relation of
+ *     Sec. II); bits 16-31 = the one of R_i, B_i of smaller magnitude,
+ *     divided by 4 fref_i, as FP16 clamped to |.| < 2, with bit 14 (always
+ *     clear in such an FP16 value) set when that colour is blue; the other
+ *     colour is f_i minus it.  Values are rounded to nearest even.  40 bytes
+ *     per site instead of 72 (F32).
+ * rhoN0, force and the field outputs use the arithmetic type: double for
+ * LBM_STORAGE_F64, float for every other format.
  *
  * Streams: every call only enqueues work on the given stream; none of them
  * synchronises, except lbm_masses_host (documented there).
@@ -54,8 +69,10 @@ typedef enum lbm_status {
 } lbm_status;
 
 enum {
-  LBM_STORAGE_F64 = 0,  /* populations and arithmetic in double */
-  LBM_STORAGE_F32 = 1   /* populations and arithmetic in float */
+  LBM_STORAGE_F64 = 0,      /* populations and arithmetic in double */
+  LBM_STORAGE_F32 = 1,      /* populations and arithmetic in float */
+  LBM_STORAGE_F16_OFS = 2,  /* 16-bit FP16 offset words (see above), arithmetic in float */
+  LBM_STORAGE_BF16_OFS = 3  /* as F16_OFS with the f_i offset in BF16 */
 };
 
 enum {
@@ -88,14 +105,19 @@ typedef struct lbm_handle lbm_handle;
 
 /* Host-only check of a parameter set (no GPU call).  LBM_OK or LBM_EINVAL.
  * Rejects: nx, ny < 1; walls with fewer than 1 fluid row; unknown storage;
- * a population buffer of 4 GiB or more (18*nx*ny elements); a stencil radius not in {1, 3}; non-positive densities;
+ * a population buffer of 4 GiB or more; a stencil radius not in {1, 3}; non-positive densities;
  * |(1-alpha_B) - Lambda (1-alpha_R)| > 1e-9 (1-alpha_B) (Sec. II density-ratio
  * relation); alpha outside [0, 1); nu <= 0 (lambda_3 = 2/(6 nu + 1) must lie in
  * (0, 2)); lambda6, lambda7 outside (0, 2); eps_n <= 0. */
 int lbm_validate_params(const lbm_params* p);
 
-/* Number of elements of one population buffer: 18 * nx * ny. */
+/* Words of one population buffer: NW * nx * ny (NW = 18 for F64/F32, 10 for
+ * the 16-bit offset formats); 0 for an empty lattice or unknown storage. */
 size_t lbm_pops_elems(const lbm_params* p);
+
+/* Bytes of one population buffer: lbm_pops_elems() times the word size (8 for
+ * F64, 4 otherwise). */
+size_t lbm_pops_bytes(const lbm_params* p);
 
 /* Bytes of device workspace lbm_init needs (per-block FP64 partial sums of the
  * mass reduction).  0 on invalid parameters. */
@@ -103,11 +125,12 @@ size_t lbm_workspace_bytes(const lbm_params* p);
 
 /* Create a handle and write the initial populations into pops_a (Sec. II
  * equilibrium at rest): rho_R = rho0_R (1 + rho^N)/2, rho_B = rho0_B (1 - rho^N)/2,
- * C_i = rho_C phi_i.  rhoN0: device [ny][nx] array of the storage type, values in
- * [-1, 1] (solid rows ignored).  force: NULL or device [2][ny][nx] per-site body
- * force density (x then y component) added to G every step; it must stay valid
- * and unchanged while the handle is used.  pops_a, pops_b: device buffers of
- * lbm_pops_elems() elements, not overlapping.  workspace: device memory of at
+ * C_i = rho_C phi_i.  rhoN0: device [ny][nx] array of the arithmetic type,
+ * values in [-1, 1] (solid rows ignored).  force: NULL or device [2][ny][nx]
+ * per-site body force density (x then y component, arithmetic type) added to G
+ * every step; it must stay valid and unchanged while the handle is used.
+ * pops_a, pops_b: device buffers of lbm_pops_bytes() bytes, aligned to the word
+ * size, not overlapping.  workspace: device memory of at
  * least lbm_workspace_bytes() bytes, 256-byte aligned.  The handle is written
  * to *out; free it with lbm_destroy.  Enqueued on `stream`. */
 int lbm_init(const lbm_params* p, const void* rhoN0, const void* force,
@@ -123,7 +146,7 @@ int lbm_step(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t str
 
 /* Macroscopic fields of the current state (Sec. II, force-adjusted
  * observables): rho, u = (sum f c + G/2)/rho, rho^N.  Each output is NULL
- * (skipped) or a device [ny][nx] array of the storage type; solid rows are
+ * (skipped) or a device [ny][nx] array of the arithmetic type; solid rows are
  * written as NaN.  mass_RB_dev as in lbm_step.  Enqueued on `stream`. */
 int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN,
                double* mass_RB_dev, hipStream_t stream);

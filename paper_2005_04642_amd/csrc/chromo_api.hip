@@ -10,7 +10,7 @@
 #include <string>
 
 #include "chromo_lbm.h"
-#include "chromo_kernels.hpp"
+#include "chromo_host.hpp"
 
 namespace {
 
@@ -32,35 +32,39 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(LBM_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-constexpr int MASS_BLOCKS = 512;
-// Workgroup shape: NTX lattice columns x NR rows, one thread each.  512
-// threads (8 waves) per CU leave 256 VGPRs per thread for the register ring.
-constexpr int NTX_F32 = 128;
-constexpr int NR_F32 = 4;
-constexpr int NTX_F64 = 64;   // double (validation instantiation)
-constexpr int NR_F64 = 4;
-
-template <typename T>
-struct NtxOf {
-  static constexpr int value = sizeof(T) == 8 ? NTX_F64 : NTX_F32;
-  static constexpr int nr = sizeof(T) == 8 ? NR_F64 : NR_F32;
-};
-
 bool radius_ok(int r) { return r == 1 || r == 3; }
 
 int halo(const lbm_params& p) { return p.stencil[0] + p.stencil[1] + p.stencil[3]; }
 
-int ntx_for(const lbm_params& p) { return p.storage == LBM_STORAGE_F64 ? NTX_F64 : NTX_F32; }
+using chromo::MASS_BLOCKS;
+
+const chromo::Ops* ops_of(int storage) {
+  switch (storage) {
+    case LBM_STORAGE_F64:
+      return &chromo::ops_f64();
+    case LBM_STORAGE_F32:
+      return &chromo::ops_f32();
+    case LBM_STORAGE_F16_OFS:
+      return &chromo::ops_f16o();
+    case LBM_STORAGE_BF16_OFS:
+      return &chromo::ops_bf16o();
+  }
+  return nullptr;
+}
+
+// words per site and bytes per word of each storage format
+int words_of(int storage) { return (storage == LBM_STORAGE_F16_OFS || storage == LBM_STORAGE_BF16_OFS) ? 10 : 18; }
+int word_bytes_of(int storage) { return storage == LBM_STORAGE_F64 ? 8 : 4; }
 
 int validate(const lbm_params* p) {
   if (!p) return fail(LBM_EINVAL, "params is NULL");
   if (p->nx < 1 || p->ny < 1) return fail(LBM_EINVAL, "lattice %dx%d is empty", p->nx, p->ny);
   if (p->walls_y != 0 && p->walls_y != 1) return fail(LBM_EINVAL, "walls_y must be 0 or 1");
   if (p->walls_y && p->ny < 3) return fail(LBM_EINVAL, "walls need ny >= 3 (one fluid row)");
-  if (p->storage != LBM_STORAGE_F32 && p->storage != LBM_STORAGE_F64)
+  if (p->storage < LBM_STORAGE_F64 || p->storage > LBM_STORAGE_BF16_OFS)
     return fail(LBM_EINVAL, "storage %d not provided by this build", p->storage);
-  const double elem = p->storage == LBM_STORAGE_F64 ? 8.0 : 4.0;
-  if (18.0 * (double)p->nx * (double)p->ny * elem >= 4294967296.0)
+  const double bytes = (double)words_of(p->storage) * word_bytes_of(p->storage) * (double)p->nx * (double)p->ny;
+  if (bytes >= 4294967296.0)
     return fail(LBM_EINVAL, "lattice too large: one population buffer must stay below 4 GiB");
   for (int k = 0; k < 4; ++k)
     if (!radius_ok(p->stencil[k])) return fail(LBM_EINVAL, "stencil radius %d not in {1,3}", p->stencil[k]);
@@ -84,35 +88,6 @@ int validate(const lbm_params* p) {
   return LBM_OK;
 }
 
-template <typename T>
-chromo::Coef<T> make_coef(const lbm_params& p) {
-  chromo::Coef<T> c;
-  const double Lam = p.rho0_R / p.rho0_B;
-  c.inv_rho0R = (T)(1.0 / p.rho0_R);
-  c.inv_rho0B = (T)(1.0 / p.rho0_B);
-  c.alphaR = (T)p.alpha_R;
-  c.alphaB = (T)p.alpha_B;
-  c.c1R = (T)(1.0 - p.alpha_R);
-  c.c1B = (T)(1.0 - p.alpha_B);
-  c.c06R = (T)(0.6 * (1.0 - p.alpha_R));
-  c.c06B = (T)(0.6 * (1.0 - p.alpha_B));
-  c.phiB = (T)(0.6 * (1.0 - p.alpha_R) * Lam);
-  c.hnuR = (T)(0.5 * p.nu_R);
-  c.hnuB = (T)(0.5 * p.nu_B);
-  c.half_sigma = (T)(0.5 * p.sigma);
-  c.beta18 = (T)(1.8 * p.beta);
-  c.lambda6 = (T)p.lambda6;
-  c.lambda7 = (T)p.lambda7;
-  c.gx = (T)p.gx;
-  c.gy = (T)p.gy;
-  c.K_fixed = (T)p.K_fixed;
-  c.eps2 = (T)(p.eps_n * p.eps_n);
-  c.ghost_eq = p.ghost_eq;
-  c.fixed_K = (p.flags & LBM_FLAG_FIXED_K) ? 1 : 0;
-  c.recolor = (p.flags & LBM_FLAG_NO_RECOLOR) ? 0 : 1;
-  return c;
-}
-
 // Strips of at most NTX-2H columns; chunks of rows such that all tiles run in
 // a single wave of workgroups (one workgroup fills a CU: its 8 wavefronts use
 // the whole register file), i.e. nstrips * nchunks <= number of CUs, with
@@ -124,7 +99,7 @@ chromo::Geom plan(const lbm_params& p, int ncu) {
   g.walls = p.walls_y;
   g.F = p.walls_y ? p.ny - 2 : p.ny;
   g.plane = p.nx * p.ny;
-  const int txmax = ntx_for(p) - 2 * halo(p);
+  const int txmax = chromo::ntx_for(p.storage) - 2 * halo(p);
   g.nstrips = (p.nx + txmax - 1) / txmax;
   g.TX = (p.nx + g.nstrips - 1) / g.nstrips;
   int nch = ncu / g.nstrips;
@@ -135,44 +110,6 @@ chromo::Geom plan(const lbm_params& p, int ncu) {
   g.TY = (g.F + nch - 1) / nch;
   g.nchunks = (g.F + g.TY - 1) / g.TY;
   return g;
-}
-
-template <typename T, int NTX, int RG, int RK, int RP, int RU, bool FIELDS>
-hipError_t launch_march(const chromo::StepArgs<T>& a, hipStream_t s) {
-  constexpr int NR = NtxOf<T>::nr;
-  const int ntiles = a.g.nstrips * a.g.nchunks;
-  const int nblocks = 8 * ((ntiles + 7) / 8);  // whole rounds over the 8 XCDs (see the kernel)
-  hipLaunchKernelGGL((chromo::chromo_step_kernel<T, NTX, NR, RG, RK, RP, RU, FIELDS>), dim3(nblocks),
-                     dim3(NTX * NR), 0, s, a);
-  return hipGetLastError();
-}
-
-template <typename T, int NTX, bool FIELDS>
-hipError_t dispatch_radii(const chromo::StepArgs<T>& a, const int* r, hipStream_t s) {
-  const int code = (r[0] == 3) * 8 + (r[1] == 3) * 4 + (r[2] == 3) * 2 + (r[3] == 3);
-#define CHROMO_CASE(C, A, B, P, U) \
-  case C:                          \
-    return launch_march<T, NTX, A, B, P, U, FIELDS>(a, s);
-  switch (code) {
-    CHROMO_CASE(0, 1, 1, 1, 1)
-    CHROMO_CASE(1, 1, 1, 1, 3)
-    CHROMO_CASE(2, 1, 1, 3, 1)
-    CHROMO_CASE(3, 1, 1, 3, 3)
-    CHROMO_CASE(4, 1, 3, 1, 1)
-    CHROMO_CASE(5, 1, 3, 1, 3)
-    CHROMO_CASE(6, 1, 3, 3, 1)
-    CHROMO_CASE(7, 1, 3, 3, 3)
-    CHROMO_CASE(8, 3, 1, 1, 1)
-    CHROMO_CASE(9, 3, 1, 1, 3)
-    CHROMO_CASE(10, 3, 1, 3, 1)
-    CHROMO_CASE(11, 3, 1, 3, 3)
-    CHROMO_CASE(12, 3, 3, 1, 1)
-    CHROMO_CASE(13, 3, 3, 1, 3)
-    CHROMO_CASE(14, 3, 3, 3, 1)
-    CHROMO_CASE(15, 3, 3, 3, 3)
-  }
-#undef CHROMO_CASE
-  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -186,66 +123,25 @@ struct lbm_handle {
   const void* force;
   int64_t steps;
   chromo::Geom g;
+  const chromo::Ops* ops;
 };
 
 namespace {
 
-template <typename T>
-chromo::StepArgs<T> args_for(const lbm_handle* h, const T* src, T* dst) {
-  chromo::StepArgs<T> a;
-  a.src = src;
-  a.dst = dst;
-  a.force = static_cast<const T*>(h->force);
-  a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = nullptr;
-  a.g = h->g;
-  a.c = make_coef<T>(h->p);
-  return a;
-}
-
-template <typename T>
 int mass_into(lbm_handle* h, double* out, hipStream_t s) {
-  const T* live = static_cast<const T*>(h->pops[h->live]);
-  double* part = static_cast<double*>(h->ws);
-  hipLaunchKernelGGL(chromo::mass_partial_kernel<T>, dim3(MASS_BLOCKS), dim3(256), 0, s, live, h->g, part);
-  hipLaunchKernelGGL(chromo::mass_final_kernel, dim3(1), dim3(256), 0, s, part, MASS_BLOCKS, out);
-  HIP_TRY(hipGetLastError());
+  HIP_TRY(h->ops->mass(h->p, h->g, h->pops[h->live], static_cast<double*>(h->ws), out, s));
   return LBM_OK;
 }
 
-template <typename T>
 int step_impl(lbm_handle* h, int nsteps, hipStream_t s) {
   for (int k = 0; k < nsteps; ++k) {
-    const T* src = static_cast<const T*>(h->pops[h->live]);
-    T* dst = static_cast<T*>(h->pops[1 - h->live]);
-    if (h->p.flags & LBM_FLAG_STREAM_ONLY) {
-      dim3 grid((h->g.nx + 255) / 256, h->g.F);
-      hipLaunchKernelGGL(chromo::stream_only_kernel<T>, grid, dim3(256), 0, s, src, dst, h->g);
-      HIP_TRY(hipGetLastError());
-    } else {
-      chromo::StepArgs<T> a = args_for<T>(h, src, dst);
-      hipError_t e = dispatch_radii<T, NtxOf<T>::value, false>(a, h->p.stencil, s);
-      if (e != hipSuccess) return fail(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
-    }
+    const void* src = h->pops[h->live];
+    void* dst = h->pops[1 - h->live];
+    hipError_t e = (h->p.flags & LBM_FLAG_STREAM_ONLY) ? h->ops->stream_only(h->g, src, dst, s)
+                                                       : h->ops->step(h->p, h->g, src, dst, h->force, s);
+    if (e != hipSuccess) return fail(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
     h->live = 1 - h->live;
     h->steps += 1;
-  }
-  return LBM_OK;
-}
-
-template <typename T>
-int fields_impl(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN, hipStream_t s) {
-  const T* src = static_cast<const T*>(h->pops[h->live]);
-  chromo::StepArgs<T> a = args_for<T>(h, src, nullptr);
-  a.out_rho = static_cast<T*>(rho);
-  a.out_ux = static_cast<T*>(ux);
-  a.out_uy = static_cast<T*>(uy);
-  a.out_rhoN = static_cast<T*>(rhoN);
-  hipError_t e = dispatch_radii<T, NtxOf<T>::value, true>(a, h->p.stencil, s);
-  if (e != hipSuccess) return fail(LBM_EHIP, "fields launch: %s", hipGetErrorString(e));
-  if (h->g.walls) {
-    hipLaunchKernelGGL(chromo::fill_rows_kernel<T>, dim3((h->g.nx + 255) / 256), dim3(256), 0, s, a.out_rho,
-                       a.out_ux, a.out_uy, a.out_rhoN, h->g.nx, 0, h->g.ny - 1);
-    HIP_TRY(hipGetLastError());
   }
   return LBM_OK;
 }
@@ -260,9 +156,11 @@ int lbm_validate_params(const lbm_params* p) {
 }
 
 size_t lbm_pops_elems(const lbm_params* p) {
-  if (!p || p->nx < 1 || p->ny < 1) return 0;
-  return (size_t)18 * (size_t)p->nx * (size_t)p->ny;
+  if (!p || p->nx < 1 || p->ny < 1 || p->storage < LBM_STORAGE_F64 || p->storage > LBM_STORAGE_BF16_OFS) return 0;
+  return (size_t)words_of(p->storage) * (size_t)p->nx * (size_t)p->ny;
 }
+
+size_t lbm_pops_bytes(const lbm_params* p) { return lbm_pops_elems(p) * (p ? word_bytes_of(p->storage) : 0); }
 
 size_t lbm_workspace_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
@@ -279,8 +177,8 @@ int lbm_init(const lbm_params* p, const void* rhoN0, const void* force, void* po
   if (!rhoN0 || !pops_a || !pops_b || !workspace)
     return fail(LBM_EINVAL, "rhoN0, pops_a, pops_b and workspace must be non-NULL");
   if (pops_a == pops_b) return fail(LBM_EINVAL, "pops_a and pops_b must differ");
-  const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
-  const size_t bytes = lbm_pops_elems(p) * elem;
+  const size_t elem = (size_t)word_bytes_of(p->storage);
+  const size_t bytes = lbm_pops_bytes(p);
   const char* a = static_cast<const char*>(pops_a);
   const char* b = static_cast<const char*>(pops_b);
   if (a < b + bytes && b < a + bytes) return fail(LBM_EINVAL, "pops_a and pops_b overlap");
@@ -305,17 +203,9 @@ int lbm_init(const lbm_params* p, const void* rhoN0, const void* force, void* po
   h->force = force;
   h->steps = 0;
   h->g = plan(*p, ncu > 0 ? ncu : 1);
+  h->ops = ops_of(p->storage);
 
-  dim3 grid((p->nx + 255) / 256, p->ny);
-  if (p->storage == LBM_STORAGE_F64) {
-    hipLaunchKernelGGL(chromo::init_kernel<double>, grid, dim3(256), 0, stream, static_cast<const double*>(rhoN0),
-                       static_cast<double*>(pops_a), h->g, make_coef<double>(*p), p->rho0_R, p->rho0_B);
-  } else {
-    hipLaunchKernelGGL(chromo::init_kernel<float>, grid, dim3(256), 0, stream, static_cast<const float*>(rhoN0),
-                       static_cast<float*>(pops_a), h->g, make_coef<float>(*p), (float)p->rho0_R,
-                       (float)p->rho0_B);
-  }
-  hipError_t e = hipGetLastError();
+  hipError_t e = h->ops->init(*p, h->g, rhoN0, pops_a, stream);
   if (e != hipSuccess) {
     delete h;
     return fail(LBM_EHIP, "init launch: %s", hipGetErrorString(e));
@@ -328,11 +218,9 @@ int lbm_step(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t str
   g_last_error.clear();
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
-  int st = h->p.storage == LBM_STORAGE_F64 ? step_impl<double>(h, nsteps, stream)
-                                           : step_impl<float>(h, nsteps, stream);
+  int st = step_impl(h, nsteps, stream);
   if (st != LBM_OK || !mass_RB_dev) return st;
-  return h->p.storage == LBM_STORAGE_F64 ? mass_into<double>(h, mass_RB_dev, stream)
-                                         : mass_into<float>(h, mass_RB_dev, stream);
+  return mass_into(h, mass_RB_dev, stream);
 }
 
 int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN, double* mass_RB_dev,
@@ -341,19 +229,18 @@ int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN, double*
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   int st = LBM_OK;
   if (rho || ux || uy || rhoN) {
-    st = h->p.storage == LBM_STORAGE_F64 ? fields_impl<double>(h, rho, ux, uy, rhoN, stream)
-                                         : fields_impl<float>(h, rho, ux, uy, rhoN, stream);
+    hipError_t e = h->ops->fields(h->p, h->g, h->pops[h->live], h->force, rho, ux, uy, rhoN, stream);
+    if (e != hipSuccess) st = fail(LBM_EHIP, "fields launch: %s", hipGetErrorString(e));
   }
   if (st != LBM_OK || !mass_RB_dev) return st;
-  return h->p.storage == LBM_STORAGE_F64 ? mass_into<double>(h, mass_RB_dev, stream)
-                                         : mass_into<float>(h, mass_RB_dev, stream);
+  return mass_into(h, mass_RB_dev, stream);
 }
 
 int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream) {
   g_last_error.clear();
   if (!h || !out) return fail(LBM_EINVAL, "handle or out is NULL");
   double* tgt = static_cast<double*>(h->ws) + 2 * MASS_BLOCKS;  // pair after the block partials
-  int st = h->p.storage == LBM_STORAGE_F64 ? mass_into<double>(h, tgt, stream) : mass_into<float>(h, tgt, stream);
+  int st = mass_into(h, tgt, stream);
   if (st != LBM_OK) return st;
   HIP_TRY(hipMemcpyAsync(out, tgt, 2 * sizeof(double), hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));

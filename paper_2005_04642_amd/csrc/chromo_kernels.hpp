@@ -55,6 +55,10 @@ struct Coef {
   T beta18;                // 9/5 beta
   T lambda6, lambda7;      // ghost-mode rates
   T gx, gy, K_fixed, eps2;
+  // 16-bit offset formats, per link class (rest, axis, diagonal; class 0
+  // unused): rest value fref of f_i, the offset unit fref / 2^10 and its
+  // reciprocal, the colour unit 4 fref and its reciprocal
+  T fref[3], fq[3], inv_fq[3], sq[3], inv_sq[3];
   int ghost_eq, fixed_K, recolor;
 };
 
@@ -66,8 +70,8 @@ struct Geom {
 
 template <typename T>
 struct StepArgs {
-  const T* __restrict__ src;
-  T* __restrict__ dst;
+  const void* src;              // population buffers (storage format)
+  void* dst;
   const T* __restrict__ force;  // [2][ny][nx] or null
   T* out_rho;                   // fields mode outputs ([ny][nx] or null)
   T* out_ux;
@@ -78,37 +82,170 @@ struct StepArgs {
 };
 
 // ---------------------------------------------------------------------------
-// memory access through buffer resources: the per-plane and per-row offsets
-// are wave-uniform (SGPR soffset), only the column offset lives in a VGPR.
+// Lattice links (same order as the public header): c0 = (0,0), c1 = (1,1),
+// c2 = (0,1), c3 = (-1,1), c4 = (-1,0), c5 = (-1,-1), c6 = (0,-1),
+// c7 = (1,-1), c8 = (1,0); opp(i) = i +- 4.
 // ---------------------------------------------------------------------------
-template <typename T>
-struct Mem;
+__host__ __device__ constexpr int link_cx(int i) { return (i == 1 || i == 7 || i == 8) ? 1 : ((i >= 3 && i <= 5) ? -1 : 0); }
+__host__ __device__ constexpr int link_cy(int i) { return (i >= 1 && i <= 3) ? 1 : ((i >= 5 && i <= 7) ? -1 : 0); }
+__host__ __device__ constexpr int link_opp(int i) { return i == 0 ? 0 : (i <= 4 ? i + 4 : i - 4); }
+// link class: 0 rest, 1 axis (even i), 2 diagonal (odd i)
+__host__ __device__ constexpr int link_class(int i) { return i == 0 ? 0 : ((i & 1) ? 2 : 1); }
 
-template <>
-struct Mem<float> {
-  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+// ---------------------------------------------------------------------------
+// Population storage formats.  A format keeps the 18 populations of a site as
+// NW words, word q in plane q of the buffer ([plane][ny][nx], x fastest).
+//   F64, F32 : NW = 18, word q = population (colour q / 9, link q % 9).
+//   F16O, BF16O (16-bit offset formats, FP32 arithmetic): NW = 10 words of
+//     4 bytes.  Words 0 and 1 are R_0 and B_0 as float.  Word 1 + i, i = 1..8,
+//     packs the moving link i of both colours:
+//       bits 0-15 : 2^10 (f_i - fref_i) / fref_i in FP16 (F16O) or BF16
+//                   (BF16O), where f_i = R_i + B_i and
+//                   fref_i = (9/5) w_i rho_0C (1 - alpha_C) is the rest value
+//                   of f_i, the same in both pure phases by the density-ratio
+//                   relation (Sec. II); the factor 2^10 keeps relative
+//                   departures down to 6e-8 out of FP16's subnormal range;
+//       bits 16-31: s_i / (4 fref_i) in FP16, clamped to magnitude below 2,
+//                   with bit 14 (clear in every such FP16 value) telling which
+//                   colour s_i is: 0 red, 1 blue.  s_i is the colour of
+//                   smaller magnitude (with its sign), the other colour is
+//                   f_i - s_i; the clamp is reached only when both colours
+//                   exceed 8 fref_i in magnitude.
+//     The minority colour thus keeps FP16's relative precision down to its
+//     smallest tails, and f_i keeps it relative to its departure from rest.
+// Memory access goes through buffer resources: plane and row offsets are
+// wave-uniform (SGPR soffset), only the column offset lives in a VGPR.
+// ---------------------------------------------------------------------------
+struct F64 {
+  using W = double;
+  using math = double;
+  static constexpr int NW = 18;
+};
+struct F32 {
+  using W = float;
+  using math = float;
+  static constexpr int NW = 18;
+};
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// Low-half formats of the 16-bit offset words.  pack(d, z) returns the word
+// with d in the low half and FP16(z) in the high half (round to nearest even).
+struct Half16 {
+  static __device__ __forceinline__ unsigned pack(float d, float z) {
+    const f32x2 v = {d, z};
+    return __builtin_bit_cast(unsigned, __builtin_convertvector(v, f16x2));
   }
-  static __device__ __forceinline__ void store(float v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  static __device__ __forceinline__ float low(unsigned w) {
+    return (float)__builtin_bit_cast(f16x2, w)[0];
+  }
+};
+struct BHalf16 {
+  static __device__ __forceinline__ unsigned pack(float d, float z) {
+    const unsigned lo = __builtin_bit_cast(unsigned short, (__bf16)d);
+    const unsigned hi = __builtin_bit_cast(unsigned short, (_Float16)z);
+    return lo | (hi << 16);
+  }
+  static __device__ __forceinline__ float low(unsigned w) { return __builtin_bit_cast(float, w << 16); }
+};
+template <typename H>
+struct Ofs16 {
+  using W = unsigned;
+  using math = float;
+  using Low = H;
+  static constexpr int NW = 10;
+};
+using F16O = Ofs16<Half16>;
+using BF16O = Ofs16<BHalf16>;
+
+template <typename S>
+struct is_ofs16 {
+  static constexpr bool value = S::NW == 10;
+};
+
+// link carried by word q, and the word holding the reversed link of the
+// same colour(s) at the same site (half-way bounce-back)
+template <typename S>
+__host__ __device__ constexpr int word_link(int q) {
+  return S::NW == 18 ? q % 9 : (q < 2 ? 0 : q - 1);
+}
+template <typename S>
+__host__ __device__ constexpr int word_bounce(int q) {
+  return S::NW == 18 ? (q / 9) * 9 + link_opp(q % 9) : (q < 2 ? q : 1 + link_opp(q - 1));
+}
+
+template <typename W>
+__device__ __forceinline__ W load_word(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(W) == 8) {
+    return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(W, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+}
+template <typename W>
+__device__ __forceinline__ void store_word(W v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  if constexpr (sizeof(W) == 8) {
+    using V = decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V, v), r, voff, soff, 0);
+  } else {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
   }
-};
+}
 
-template <>
-struct Mem<double> {
-  static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+// words -> populations (R_0..R_8, B_0..B_8)
+template <typename S, typename T>
+__device__ __forceinline__ void decode(const typename S::W* w, const Coef<T>& c, T* R, T* B) {
+  if constexpr (!is_ofs16<S>::value) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      R[i] = w[i];
+      B[i] = w[9 + i];
+    }
+  } else {
+    R[0] = __builtin_bit_cast(float, w[0]);
+    B[0] = __builtin_bit_cast(float, w[1]);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int k = link_class(i);
+      const unsigned v = w[1 + i];
+      const float f = __builtin_fmaf(S::Low::low(v), c.fq[k], c.fref[k]);
+      const float s = (float)__builtin_bit_cast(f16x2, v & 0xbfffffffu)[1] * c.sq[k];
+      const float o = f - s;
+      const bool blue = (v & 0x40000000u) != 0u;
+      R[i] = blue ? o : s;
+      B[i] = blue ? s : o;
+    }
   }
-  static __device__ __forceinline__ void store(double v, __amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(decltype(__builtin_amdgcn_raw_buffer_load_b64(r, 0, 0, 0)), v),
-                                          r, voff, soff, 0);
-  }
-};
+}
 
-template <typename T>
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const T* p, int plane) {
-  // raw buffer over the 18 planes; gfx9 dword3 = 0x00020000
-  const unsigned bytes = 18u * (unsigned)plane * (unsigned)sizeof(T);  // < 2^32 (checked on the host)
+// populations -> words
+template <typename S, typename T>
+__device__ __forceinline__ void encode(const T* R, const T* B, const Coef<T>& c, typename S::W* w) {
+  if constexpr (!is_ofs16<S>::value) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      w[i] = R[i];
+      w[9 + i] = B[i];
+    }
+  } else {
+    w[0] = __builtin_bit_cast(unsigned, R[0]);
+    w[1] = __builtin_bit_cast(unsigned, B[0]);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int k = link_class(i);
+      const float f = R[i] + B[i];
+      const bool blue = __builtin_fabsf(B[i]) < __builtin_fabsf(R[i]);
+      const float s = blue ? B[i] : R[i];
+      const float z = __builtin_amdgcn_fmed3f(s * c.inv_sq[k], -1.9990234375f, 1.9990234375f);
+      w[1 + i] = S::Low::pack((f - c.fref[k]) * c.inv_fq[k], z) | (blue ? 0x40000000u : 0u);
+    }
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int plane) {
+  // < 2^32 bytes (checked on the host)
+  const unsigned bytes = (unsigned)S::NW * (unsigned)plane * (unsigned)sizeof(typename S::W);
   return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
 }
 
@@ -138,14 +275,14 @@ struct Cols {
   int m, o, p;
 };
 
-// Pull-streaming gather of the 18 pre-collision populations of site (x, p):
-// f_i(r) = buf_i(r - c_i), or buf_opp(i)(r) when r - c_i is a solid row
-// (half-way bounce-back).  Link order c0..c8 as in the public header.
-// p is wave-uniform; every plane / row offset is scalar.
-template <typename T>
-__device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
-                                       T R[9], T B[9]) {
-  const unsigned E = sizeof(T);
+// Pull-streaming gather of the words of site (x, p): the word of link i comes
+// from the source site r - c_i, or, when r - c_i is a solid row, from the
+// reversed link's word at r itself (half-way bounce-back).  p is wave-uniform,
+// so every plane / row offset is scalar.
+template <typename S>
+__device__ __forceinline__ void gather_words(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
+                                             typename S::W out[S::NW]) {
+  const unsigned E = sizeof(typename S::W);
   const unsigned PB = (unsigned)g.plane * E;  // plane bytes
   int rm = p - 1, rp = p + 1;
   bool bm = false, bp = false;
@@ -157,31 +294,24 @@ __device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t src, const Geom& g
     if (rp >= g.ny) rp -= g.ny;
   }
   const unsigned ro = (unsigned)p * g.nx * E, rom = (unsigned)rm * g.nx * E, rop = (unsigned)rp * g.nx * E;
-  // (plane, row) scalar offsets and column vector offsets of links 0..8
-  const unsigned s0 = ro, s4 = 4 * PB + ro, s8 = 8 * PB + ro;
-  const unsigned s1 = bm ? 5 * PB + ro : 1 * PB + rom;
-  const unsigned s2 = bm ? 6 * PB + ro : 2 * PB + rom;
-  const unsigned s3 = bm ? 7 * PB + ro : 3 * PB + rom;
-  const unsigned s5 = bp ? 1 * PB + ro : 5 * PB + rop;
-  const unsigned s6 = bp ? 2 * PB + ro : 6 * PB + rop;
-  const unsigned s7 = bp ? 3 * PB + ro : 7 * PB + rop;
-  const int v1 = bm ? x.o : x.m, v3 = bm ? x.o : x.p;
-  const int v5 = bp ? x.o : x.p, v7 = bp ? x.o : x.m;
-  const unsigned CB = 9 * PB;
 #pragma unroll
-  for (int col = 0; col < 2; ++col) {
-    T* out = col ? B : R;
-    const unsigned c = col * CB;
-    out[0] = Mem<T>::load(src, x.o, (int)(c + s0));
-    out[1] = Mem<T>::load(src, v1, (int)(c + s1));
-    out[2] = Mem<T>::load(src, x.o, (int)(c + s2));
-    out[3] = Mem<T>::load(src, v3, (int)(c + s3));
-    out[4] = Mem<T>::load(src, x.p, (int)(c + s4));
-    out[5] = Mem<T>::load(src, v5, (int)(c + s5));
-    out[6] = Mem<T>::load(src, x.o, (int)(c + s6));
-    out[7] = Mem<T>::load(src, v7, (int)(c + s7));
-    out[8] = Mem<T>::load(src, x.m, (int)(c + s8));
+  for (int q = 0; q < S::NW; ++q) {
+    const int i = word_link<S>(q);
+    const int dy = link_cy(i), dx = link_cx(i);
+    const bool bounce = (dy == 1 && bm) || (dy == -1 && bp);
+    const unsigned soff = bounce ? (unsigned)word_bounce<S>(q) * PB + ro
+                                 : (unsigned)q * PB + (dy == 1 ? rom : (dy == -1 ? rop : ro));
+    const int voff = bounce ? x.o : (dx == 1 ? x.m : (dx == -1 ? x.p : x.o));
+    out[q] = load_word<typename S::W>(src, voff, (int)soff);
   }
+}
+
+template <typename S, typename T>
+__device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
+                                       const Coef<T>& c, T R[9], T B[9]) {
+  typename S::W w[S::NW];
+  gather_words<S>(src, g, p, x, w);
+  decode<S>(w, c, R, B);
 }
 
 template <int RING>
@@ -255,14 +385,16 @@ struct Smem {
 
 // Register state of one thread: the colour densities and the nine total
 // populations of the rows it gathered (one slot per iteration, read again
-// 2 and 3 iterations later) and the populations prefetched for the next
-// band-M row.
-template <typename T>
+// 2 and 3 iterations later) and the storage words prefetched for the next
+// band-M row (decoded only when used, so the loads stay in flight for a
+// whole iteration).
+template <typename S>
 struct March {
+  using T = typename S::math;
   T rf[4][11];   // rho_R, rho_B, f_0 .. f_8
   T gn[2][2];    // grad rho^N, band N -> band U (next iteration)
   T gr[2][2];    // force G, band U -> band O (next iteration)
-  T pr[9], pb[9];
+  typename S::W pw[S::NW];
 };
 
 struct Thread {
@@ -285,7 +417,7 @@ __device__ __forceinline__ T colour_index(T a0, T b0) {
 }
 
 // Collision, recolour and store of one site (band O).
-template <typename T, bool FIELDS>
+template <typename S, typename T, bool FIELDS>
 __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buffer_rsrc_t dst, const T* rf,
                                               T ux, T uy, T Gx, T Gy, T dPx, T dPy, T theta, T rhoN, T mx, T my,
                                               int p, const Thread& t) {
@@ -377,20 +509,20 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
   R[6] = aR * fp[6] - t2; B[6] = aB * fp[6] + t2;
   R[8] = aR * fp[8] + t8; B[8] = aB * fp[8] - t8;
   R[4] = aR * fp[4] - t8; B[4] = aB * fp[4] + t8;
-  const unsigned E = sizeof(T);
+  typename S::W w[S::NW];
+  encode<S>(R, B, c, w);
+  const unsigned E = sizeof(typename S::W);
   const unsigned PB = (unsigned)a.g.plane * E;
   const unsigned ro = (unsigned)p * a.g.nx * E;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) Mem<T>::store(R[i], dst, t.cols.o, (int)(i * PB + ro));
-#pragma unroll
-  for (int i = 0; i < 9; ++i) Mem<T>::store(B[i], dst, t.cols.o, (int)((9 + i) * PB + ro));
+  for (int q = 0; q < S::NW; ++q) store_word<typename S::W>(w[q], dst, t.cols.o, (int)(q * PB + ro));
 }
 
 // One march iteration; S = it mod 4 selects the register-ring slots.
-template <int S, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool FIELDS>
+template <int S, typename ST, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool FIELDS>
 __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgpu_buffer_rsrc_t src,
                                            __amdgpu_buffer_rsrc_t dst, Smem<T, NTX, Pipe<NR>::RING>& sm,
-                                           March<T>& st, const Thread& t) {
+                                           March<ST>& st, const Thread& t) {
   using PP = Pipe<NR>;
   constexpr int RING = PP::RING;
   const Geom& g = a.g;
@@ -406,18 +538,20 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   // ---- band M: colour densities, total populations, colour index ----------
   {
     T* rf = st.rf[sM];
-    T rR = ((st.pr[0] + st.pr[2]) + (st.pr[4] + st.pr[6])) + ((st.pr[1] + st.pr[3]) + (st.pr[5] + st.pr[7])) + st.pr[8];
-    T rB = ((st.pb[0] + st.pb[2]) + (st.pb[4] + st.pb[6])) + ((st.pb[1] + st.pb[3]) + (st.pb[5] + st.pb[7])) + st.pb[8];
+    T pr[9], pb[9];
+    decode<ST>(st.pw, c, pr, pb);
+    T rR = ((pr[0] + pr[2]) + (pr[4] + pr[6])) + ((pr[1] + pr[3]) + (pr[5] + pr[7])) + pr[8];
+    T rB = ((pb[0] + pb[2]) + (pb[4] + pb[6])) + ((pb[1] + pb[3]) + (pb[5] + pb[7])) + pb[8];
     rf[0] = rR;
     rf[1] = rB;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) rf[2 + i] = st.pr[i] + st.pb[i];
+    for (int i = 0; i < 9; ++i) rf[2 + i] = pr[i] + pb[i];
     sm.rhoN[ring_row<RING>(rowM)][tx] = colour_index(rR * c.inv_rho0R, rB * c.inv_rho0B);
     if (it + 1 < t.nit) {  // prefetch the next band-M row
       int pn;
       bool rn;
       virt_row(base + PP::LM + NR, g, pn, rn);
-      gather(src, g, pn, t.cols, st.pr, st.pb);
+      gather_words<ST>(src, g, pn, t.cols, st.pw);
     }
   }
   __syncthreads();
@@ -477,14 +611,15 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
     const T theta = ring_div<RU, RING, NTX>(sm.ux, sm.uy, rowO, tx);
     const int ro = ring_row<RING>(rowO);
     const int p = g.walls ? base + 1 : base;
-    collide_store<T, FIELDS>(a, dst, st.rf[sO], sm.ux[ro][tx], sm.uy[ro][tx], st.gr[(S + 1) & 1][0],
+    collide_store<ST, T, FIELDS>(a, dst, st.rf[sO], sm.ux[ro][tx], sm.uy[ro][tx], st.gr[(S + 1) & 1][0],
                              st.gr[(S + 1) & 1][1], dPx, dPy, theta, sm.rhoN[ro][tx], sm.mx[ro][tx],
                              sm.my[ro][tx], p, t);
   }
 }
 
-template <typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool FIELDS>
-__global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<T> a) {
+template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool FIELDS>
+__global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typename ST::math> a) {
+  using T = typename ST::math;
   using PP = Pipe<NR>;
   constexpr int H = RG + RK + RU;
   static_assert(NTX > 2 * H, "strip must be wider than its halo");
@@ -498,8 +633,8 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<T> a)
   const int per_xcd = (ntiles + 7) / 8;
   const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (tile >= ntiles) return;
-  const __amdgpu_buffer_rsrc_t src = make_rsrc(a.src, g.plane);
-  const __amdgpu_buffer_rsrc_t dst = make_rsrc(FIELDS ? a.src : a.dst, g.plane);
+  const __amdgpu_buffer_rsrc_t src = make_rsrc<ST>(a.src, g.plane);
+  const __amdgpu_buffer_rsrc_t dst = make_rsrc<ST>(FIELDS ? a.src : a.dst, g.plane);
   Thread t;
   t.tx = threadIdx.x % NTX;
   t.ty = __builtin_amdgcn_readfirstlane(threadIdx.x / NTX);
@@ -511,7 +646,7 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<T> a)
   int xg = (x0 + col) % g.nx;
   if (xg < 0) xg += g.nx;
   t.xg = xg;
-  const int E = (int)sizeof(T);
+  const int E = (int)sizeof(typename ST::W);
   t.cols.o = xg * E;
   t.cols.m = (xg == 0 ? g.nx - 1 : xg - 1) * E;
   t.cols.p = (xg == g.nx - 1 ? 0 : xg + 1) * E;
@@ -520,42 +655,41 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<T> a)
   t.yb = min(g.F, t.ya + g.TY);
   t.nit = PP::IT0 + (t.yb - t.ya + NR - 1) / NR;
 
-  March<T> st;
+  March<ST> st;
   {
     int p;
     bool refl;
     virt_row(t.ya - NR * PP::IT0 + PP::LM + t.ty, g, p, refl);
-    gather(src, g, p, t.cols, st.pr, st.pb);
+    gather_words<ST>(src, g, p, t.cols, st.pw);
   }
   for (int it = 0; it < t.nit; it += 4) {
-    march_iter<0, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it, a, src, dst, sm, st, t);
-    if (it + 1 < t.nit) march_iter<1, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 1, a, src, dst, sm, st, t);
-    if (it + 2 < t.nit) march_iter<2, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 2, a, src, dst, sm, st, t);
-    if (it + 3 < t.nit) march_iter<3, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 3, a, src, dst, sm, st, t);
+    march_iter<0, ST, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it, a, src, dst, sm, st, t);
+    if (it + 1 < t.nit) march_iter<1, ST, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 1, a, src, dst, sm, st, t);
+    if (it + 2 < t.nit) march_iter<2, ST, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 2, a, src, dst, sm, st, t);
+    if (it + 3 < t.nit) march_iter<3, ST, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 3, a, src, dst, sm, st, t);
   }
 }
 
 // ---------------------------------------------------------------------------
 // streaming only (test mode): buf'_i(r) = f_i(r)
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) stream_only_kernel(const T* __restrict__ src, T* __restrict__ dst, Geom g) {
+template <typename S>
+__global__ void __launch_bounds__(256) stream_only_kernel(const void* src, void* dst, Geom g) {
+  using W = typename S::W;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int k = blockIdx.y;  // fluid row index
   if (x >= g.nx) return;
   const int p = g.walls ? k + 1 : k;
-  const int E = (int)sizeof(T);
+  const int E = (int)sizeof(W);
   Cols cols;
   cols.o = x * E;
   cols.m = (x == 0 ? g.nx - 1 : x - 1) * E;
   cols.p = (x == g.nx - 1 ? 0 : x + 1) * E;
-  T R[9], B[9];
-  gather(make_rsrc(src, g.plane), g, p, cols, R, B);
-  T* d = dst + p * g.nx + x;
+  W v[S::NW];
+  gather_words<S>(make_rsrc<S>(src, g.plane), g, p, cols, v);
+  W* d = static_cast<W*>(dst) + p * g.nx + x;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) d[i * g.plane] = R[i];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) d[(9 + i) * g.plane] = B[i];
+  for (int q = 0; q < S::NW; ++q) d[q * g.plane] = v[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -581,33 +715,41 @@ __device__ __forceinline__ void rest_state(const T* __restrict__ rhoN0, const Co
   b = rB * phi;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) init_kernel(const T* __restrict__ rhoN0, T* __restrict__ dst, Geom g,
-                                                   Coef<T> c, T rho0R, T rho0B) {
+template <typename S>
+__global__ void __launch_bounds__(256) init_kernel(const typename S::math* __restrict__ rhoN0, void* dstv, Geom g,
+                                                   Coef<typename S::math> c, typename S::math rho0R,
+                                                   typename S::math rho0B) {
+  using T = typename S::math;
+  using W = typename S::W;
+  W* dst = static_cast<W*>(dstv);
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
-  constexpr int CX[9] = {0, 1, 0, -1, -1, -1, 0, 1, 1};
-  constexpr int CY[9] = {0, 1, 1, 1, 0, -1, -1, -1, 0};
-  constexpr int OPP[9] = {0, 5, 6, 7, 8, 1, 2, 3, 4};
   const bool solid = g.walls && (y == 0 || y == g.ny - 1);
+  W w[S::NW];
+  if (solid) {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    T r = T(0), b = T(0);
-    if (!solid) {
-      int yd = y + CY[i];
-      int xd = x + CX[i];
+    for (int q = 0; q < S::NW; ++q) w[q] = W(0);
+  } else {
+    // value stored for link i at r: the rest population of link i at r + c_i
+    // (pull layout), or of link opp(i) at r itself when r + c_i is solid
+    T R[9], B[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      int yd = y + link_cy(i);
+      int xd = x + link_cx(i);
       xd = xd < 0 ? xd + g.nx : (xd >= g.nx ? xd - g.nx : xd);
       if (g.walls && (yd == 0 || yd == g.ny - 1)) {
-        rest_state(rhoN0, c, rho0R, rho0B, y * g.nx + x, OPP[i], r, b);  // returns on link opp(i)
+        rest_state(rhoN0, c, rho0R, rho0B, y * g.nx + x, link_opp(i), R[i], B[i]);
       } else {
         yd = yd < 0 ? yd + g.ny : (yd >= g.ny ? yd - g.ny : yd);
-        rest_state(rhoN0, c, rho0R, rho0B, yd * g.nx + xd, i, r, b);
+        rest_state(rhoN0, c, rho0R, rho0B, yd * g.nx + xd, i, R[i], B[i]);
       }
     }
-    dst[i * g.plane + y * g.nx + x] = r;
-    dst[(9 + i) * g.plane + y * g.nx + x] = b;
+    encode<S>(R, B, c, w);
   }
+#pragma unroll
+  for (int q = 0; q < S::NW; ++q) dst[q * g.plane + y * g.nx + x] = w[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -619,18 +761,26 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) mass_partial_kernel(const T* __restrict__ pops, Geom g, double* partial) {
+template <typename S>
+__global__ void __launch_bounds__(256) mass_partial_kernel(const void* popsv, Geom g, Coef<typename S::math> c,
+                                                           double* partial) {
+  using T = typename S::math;
+  const typename S::W* pops = static_cast<const typename S::W*>(popsv);
   const int row0 = g.walls ? 1 : 0;
   const long long nsite = (long long)g.F * g.nx;
   double sr = 0.0, sb = 0.0;
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < nsite;
        s += (long long)gridDim.x * blockDim.x) {
     const int off = (int)(row0 * g.nx + s);
+    typename S::W w[S::NW];
+#pragma unroll
+    for (int q = 0; q < S::NW; ++q) w[q] = pops[q * g.plane + off];
+    T R[9], B[9];
+    decode<S>(w, c, R, B);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      sr += (double)pops[i * g.plane + off];
-      sb += (double)pops[(9 + i) * g.plane + off];
+      sr += (double)R[i];
+      sb += (double)B[i];
     }
   }
   sr = wave_sum(sr);
@@ -648,7 +798,7 @@ __global__ void __launch_bounds__(256) mass_partial_kernel(const T* __restrict__
   }
 }
 
-__global__ void __launch_bounds__(256) mass_final_kernel(const double* partial, int nblocks, double* out) {
+static __global__ void __launch_bounds__(256) mass_final_kernel(const double* partial, int nblocks, double* out) {
   double sr = 0.0, sb = 0.0;
   for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
     sr += partial[2 * b];

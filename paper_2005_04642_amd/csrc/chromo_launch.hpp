@@ -1,0 +1,169 @@
+// Launchers of the step, field, streaming, initial-state and mass kernels for
+// one storage format S.  Included once per format by chromo_<format>.hip, so
+// the formats compile as separate translation units.
+#pragma once
+
+#include "chromo_host.hpp"
+
+namespace chromo {
+namespace launch {
+
+// Per-site constants of the scheme (Sec. II, App. A) in the arithmetic type.
+template <typename S>
+Coef<typename S::math> make_coef(const lbm_params& p) {
+  using T = typename S::math;
+  Coef<T> c;
+  const double Lam = p.rho0_R / p.rho0_B;
+  c.inv_rho0R = (T)(1.0 / p.rho0_R);
+  c.inv_rho0B = (T)(1.0 / p.rho0_B);
+  c.alphaR = (T)p.alpha_R;
+  c.alphaB = (T)p.alpha_B;
+  c.c1R = (T)(1.0 - p.alpha_R);
+  c.c1B = (T)(1.0 - p.alpha_B);
+  c.c06R = (T)(0.6 * (1.0 - p.alpha_R));
+  c.c06B = (T)(0.6 * (1.0 - p.alpha_B));
+  c.phiB = (T)(0.6 * (1.0 - p.alpha_R) * Lam);
+  c.hnuR = (T)(0.5 * p.nu_R);
+  c.hnuB = (T)(0.5 * p.nu_B);
+  c.half_sigma = (T)(0.5 * p.sigma);
+  c.beta18 = (T)(1.8 * p.beta);
+  c.lambda6 = (T)p.lambda6;
+  c.lambda7 = (T)p.lambda7;
+  c.gx = (T)p.gx;
+  c.gy = (T)p.gy;
+  c.K_fixed = (T)p.K_fixed;
+  c.eps2 = (T)(p.eps_n * p.eps_n);
+  // rest value of f_i on axis and diagonal links: (9/5) w_i rho_0R (1 - alpha_R)
+  const double moving = p.rho0_R * (1.0 - p.alpha_R);
+  const double fr[3] = {1.0, 0.2 * moving, 0.05 * moving};
+  for (int k = 0; k < 3; ++k) {
+    const double f = (double)(T)fr[k];
+    c.fref[k] = (T)f;
+    c.fq[k] = (T)(f / 1024.0);
+    c.inv_fq[k] = (T)(1024.0 / f);
+    c.sq[k] = (T)(4.0 * f);
+    c.inv_sq[k] = (T)(0.25 / f);
+  }
+  c.ghost_eq = p.ghost_eq;
+  c.fixed_K = (p.flags & LBM_FLAG_FIXED_K) ? 1 : 0;
+  c.recolor = (p.flags & LBM_FLAG_NO_RECOLOR) ? 0 : 1;
+  return c;
+}
+
+template <typename S>
+struct Shape {
+  static constexpr int ntx = sizeof(typename S::math) == 8 ? NTX_F64 : NTX_F32;
+  static constexpr int nr = sizeof(typename S::math) == 8 ? NR_F64 : NR_F32;
+};
+
+template <typename S, int RG, int RK, int RP, int RU, bool FIELDS>
+hipError_t march(const StepArgs<typename S::math>& a, hipStream_t s) {
+  constexpr int NTX = Shape<S>::ntx, NR = Shape<S>::nr;
+  const int ntiles = a.g.nstrips * a.g.nchunks;
+  const int nblocks = 8 * ((ntiles + 7) / 8);  // whole rounds over the 8 XCDs (see the kernel)
+  hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, FIELDS>), dim3(nblocks), dim3(NTX * NR), 0,
+                     s, a);
+  return hipGetLastError();
+}
+
+template <typename S, bool FIELDS>
+hipError_t dispatch_radii(const StepArgs<typename S::math>& a, const int* r, hipStream_t s) {
+  const int code = (r[0] == 3) * 8 + (r[1] == 3) * 4 + (r[2] == 3) * 2 + (r[3] == 3);
+#define CHROMO_CASE(C, A, B, P, U) \
+  case C:                          \
+    return march<S, A, B, P, U, FIELDS>(a, s);
+  switch (code) {
+    CHROMO_CASE(0, 1, 1, 1, 1)
+    CHROMO_CASE(1, 1, 1, 1, 3)
+    CHROMO_CASE(2, 1, 1, 3, 1)
+    CHROMO_CASE(3, 1, 1, 3, 3)
+    CHROMO_CASE(4, 1, 3, 1, 1)
+    CHROMO_CASE(5, 1, 3, 1, 3)
+    CHROMO_CASE(6, 1, 3, 3, 1)
+    CHROMO_CASE(7, 1, 3, 3, 3)
+    CHROMO_CASE(8, 3, 1, 1, 1)
+    CHROMO_CASE(9, 3, 1, 1, 3)
+    CHROMO_CASE(10, 3, 1, 3, 1)
+    CHROMO_CASE(11, 3, 1, 3, 3)
+    CHROMO_CASE(12, 3, 3, 1, 1)
+    CHROMO_CASE(13, 3, 3, 1, 3)
+    CHROMO_CASE(14, 3, 3, 3, 1)
+    CHROMO_CASE(15, 3, 3, 3, 3)
+  }
+#undef CHROMO_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename S>
+StepArgs<typename S::math> args(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force) {
+  using T = typename S::math;
+  StepArgs<T> a;
+  a.src = src;
+  a.dst = dst;
+  a.force = static_cast<const T*>(force);
+  a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = nullptr;
+  a.g = g;
+  a.c = make_coef<S>(p);
+  return a;
+}
+
+template <typename S>
+hipError_t step(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force, hipStream_t s) {
+  return dispatch_radii<S, false>(args<S>(p, g, src, dst, force), p.stencil, s);
+}
+
+template <typename S>
+hipError_t fields(const lbm_params& p, const Geom& g, const void* src, const void* force, void* rho, void* ux,
+                  void* uy, void* rhoN, hipStream_t s) {
+  using T = typename S::math;
+  StepArgs<T> a = args<S>(p, g, src, nullptr, force);
+  a.out_rho = static_cast<T*>(rho);
+  a.out_ux = static_cast<T*>(ux);
+  a.out_uy = static_cast<T*>(uy);
+  a.out_rhoN = static_cast<T*>(rhoN);
+  hipError_t e = dispatch_radii<S, true>(a, p.stencil, s);
+  if (e != hipSuccess || !g.walls) return e;
+  hipLaunchKernelGGL(fill_rows_kernel<T>, dim3((g.nx + 255) / 256), dim3(256), 0, s, a.out_rho, a.out_ux, a.out_uy,
+                     a.out_rhoN, g.nx, 0, g.ny - 1);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t stream_only(const Geom& g, const void* src, void* dst, hipStream_t s) {
+  dim3 grid((g.nx + 255) / 256, g.F);
+  hipLaunchKernelGGL(stream_only_kernel<S>, grid, dim3(256), 0, s, src, dst, g);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t init(const lbm_params& p, const Geom& g, const void* rhoN0, void* dst, hipStream_t s) {
+  using T = typename S::math;
+  dim3 grid((g.nx + 255) / 256, g.ny);
+  hipLaunchKernelGGL(init_kernel<S>, grid, dim3(256), 0, s, static_cast<const T*>(rhoN0), dst, g, make_coef<S>(p),
+                     (T)p.rho0_R, (T)p.rho0_B);
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t mass(const lbm_params& p, const Geom& g, const void* pops, double* partial, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(mass_partial_kernel<S>, dim3(MASS_BLOCKS), dim3(256), 0, s, pops, g, make_coef<S>(p), partial);
+  hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(256), 0, s, partial, MASS_BLOCKS, out);
+  return hipGetLastError();
+}
+
+template <typename S>
+Ops make_ops() {
+  Ops o;
+  o.step = step<S>;
+  o.fields = fields<S>;
+  o.stream_only = stream_only<S>;
+  o.init = init<S>;
+  o.mass = mass<S>;
+  o.words = S::NW;
+  o.word_bytes = (int)sizeof(typename S::W);
+  o.math_bytes = (int)sizeof(typename S::math);
+  return o;
+}
+
+}  // namespace launch
+}  // namespace chromo

@@ -17,11 +17,13 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libchromo_lbm.so")
 
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENOTIMPL, LBM_ENONFINITE = 0, -1, -2, -3, -4
-LBM_STORAGE_F64, LBM_STORAGE_F32 = 0, 1
+LBM_STORAGE_F64, LBM_STORAGE_F32, LBM_STORAGE_F16_OFS, LBM_STORAGE_BF16_OFS = 0, 1, 2, 3
+STORAGE = {"f64": LBM_STORAGE_F64, "f32": LBM_STORAGE_F32, "f16": LBM_STORAGE_F16_OFS, "bf16": LBM_STORAGE_BF16_OFS}
+WORDS_PER_SITE = {"f64": 18, "f32": 18, "f16": 10, "bf16": 10}
 LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR = 1, 2, 4
 
 # every symbol the header declares
-EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_workspace_bytes", "lbm_init", "lbm_step",
+EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_workspace_bytes", "lbm_init", "lbm_step",
             "lbm_fields", "lbm_masses_host", "lbm_adjoint_step", "lbm_current_pops", "lbm_step_count",
             "lbm_destroy", "lbm_last_error")
 
@@ -63,6 +65,8 @@ def load_library(path=None):
     lib.lbm_validate_params.restype = ctypes.c_int
     lib.lbm_pops_elems.argtypes = [P]
     lib.lbm_pops_elems.restype = sz
+    lib.lbm_pops_bytes.argtypes = [P]
+    lib.lbm_pops_bytes.restype = sz
     lib.lbm_workspace_bytes.argtypes = [P]
     lib.lbm_workspace_bytes.restype = sz
     lib.lbm_init.argtypes = [P, vp, vp, vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
@@ -99,7 +103,7 @@ def make_params(nx, ny, storage="f32", **kw):
     p = lbm_params()
     p.nx, p.ny = nx, ny
     p.walls_y = 1 if kw.get("walls", False) else 0
-    p.storage = {"f64": LBM_STORAGE_F64, "f32": LBM_STORAGE_F32}[storage]
+    p.storage = STORAGE[storage]
     st = kw.get("stencil", (3, 3, 3, 3))
     for k in range(4):
         p.stencil[k] = int(st[k])
@@ -129,6 +133,10 @@ def lbm_validate_params(p):
 
 def lbm_pops_elems(p):
     return load_library().lbm_pops_elems(ctypes.byref(p))
+
+
+def lbm_pops_bytes(p):
+    return load_library().lbm_pops_bytes(ctypes.byref(p))
 
 
 def lbm_workspace_bytes(p):
@@ -189,8 +197,10 @@ class Simulation:
     """Buffers and handle of one lattice.
 
     params: dict of physical parameters (see ``workloads.base_params``);
-    rhoN0: [ny, nx] initial colour index (numpy or torch); storage 'f32'/'f64';
-    force: optional [2, ny, nx] per-site body force density.
+    rhoN0: [ny, nx] initial colour index (numpy or torch); storage 'f64',
+    'f32', or the 16-bit offset formats 'f16' / 'bf16' (FP32 arithmetic);
+    force: optional [2, ny, nx] per-site body force density.  Fields, rhoN0
+    and force use the arithmetic type (float64 for 'f64', else float32).
     """
 
     def __init__(self, nx, ny, params, rhoN0, storage="f32", force=None, device="cuda:0", flags=0):
@@ -203,12 +213,14 @@ class Simulation:
         kw = dict(params)
         kw["flags"] = kw.get("flags", 0) | flags
         self.params = make_params(nx, ny, storage, **kw)
+        self.storage = storage
         self.dtype = torch.float64 if storage == "f64" else torch.float32
+        self.word_dtype = {"f64": torch.float64, "f32": torch.float32}.get(storage, torch.int32)
         code, msg = lbm_validate_params(self.params)
         if code != LBM_OK:
             raise LbmError(code, msg)
         n = lbm_pops_elems(self.params)
-        self.pops = [torch.empty(n, dtype=self.dtype, device=self.device) for _ in range(2)]
+        self.pops = [torch.empty(n, dtype=self.word_dtype, device=self.device) for _ in range(2)]
         wsb = lbm_workspace_bytes(self.params)
         self.ws = torch.zeros(wsb, dtype=torch.uint8, device=self.device)
         self.rhoN0 = torch.as_tensor(np.asarray(rhoN0), dtype=self.dtype).to(self.device).contiguous()
@@ -239,8 +251,14 @@ class Simulation:
     def masses(self):
         return lbm_masses_host(self.h, self.stream())
 
+    def live_words(self):
+        """View [NW, ny, nx] of the live buffer (storage words, pull layout)."""
+        return self.pops[lbm_current_pops(self.h)].view(-1, self.ny, self.nx)
+
     def live_pops(self):
-        """View [2, 9, ny, nx] of the live buffer (post-recolour, pull layout)."""
+        """View [2, 9, ny, nx] of the live buffer (F64/F32 storage only)."""
+        if self.storage not in ("f32", "f64"):
+            raise ValueError("live_pops() needs F32/F64 storage; use live_words() for %s" % self.storage)
         return self.pops[lbm_current_pops(self.h)].view(2, 9, self.ny, self.nx)
 
     @property

@@ -33,7 +33,7 @@ def good():
 
 
 def test_validate_accepts_workload_parameters():
-    for storage in ("f32", "f64"):
+    for storage in ("f32", "f64", "f16", "bf16"):
         for cfg in (Wk.config_static_drop(), Wk.config_layered_channel()):
             p = lbm.make_params(cfg["nx"], cfg["ny"], storage, **cfg["params"])
             assert lbm.lbm_validate_params(p)[0] == lbm.LBM_OK
@@ -63,9 +63,22 @@ def test_validate_rejects_bad_stencil_and_huge_and_wall_height():
     assert lbm.lbm_validate_params(p)[0] == lbm.LBM_EINVAL
 
 
+def test_16bit_formats_allow_larger_lattices():
+    """One population buffer must stay below 4 GiB: 72 B per site (F32) versus
+    40 B per site (16-bit offset formats)."""
+    for storage, ok in (("f32", False), ("f16", True), ("bf16", True), ("f64", False)):
+        p = lbm.make_params(10240, 10240, storage, **Wk.base_params(Lambda=10.0))
+        assert (lbm.lbm_validate_params(p)[0] == lbm.LBM_OK) == ok, storage
+
+
 def test_sizes():
     p = good()
     assert lbm.lbm_pops_elems(p) == 18 * 64 * 64
+    assert lbm.lbm_pops_bytes(p) == 4 * 18 * 64 * 64
+    for storage, words, nbytes in (("f64", 18, 8), ("f16", 10, 4), ("bf16", 10, 4)):
+        q = lbm.make_params(64, 32, storage, **Wk.base_params(Lambda=10.0))
+        assert lbm.lbm_pops_elems(q) == words * 64 * 32
+        assert lbm.lbm_pops_bytes(q) == nbytes * words * 64 * 32
     assert lbm.lbm_workspace_bytes(p) > 0
     p.nx = 0
     assert lbm.lbm_workspace_bytes(p) == 0

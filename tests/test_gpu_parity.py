@@ -116,6 +116,28 @@ def test_one_step_random_state_f64(stencil, walls, shape):
     sim.close()
 
 
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (1, 1, 1, 1)])
+@pytest.mark.parametrize("walls", [False, True])
+@pytest.mark.parametrize("shape", [(8, 8), (47, 29), (100, 60)])
+def test_one_step_random_state_f32(stencil, walls, shape):
+    """FP32 storage and arithmetic: one step within 2e-6 of the largest
+    population of the FP64 oracle's result, from the same FP32 state."""
+    nx, ny = shape
+    params = Wk.base_params(Lambda=10.0, sigma=0.02, stencil=stencil)
+    params.update(walls=walls, gx=3e-5, gy=-2e-5, nu_B=0.4)
+    rng = np.random.default_rng(7)
+    rn = np.clip(np.tanh(2.0 * rng.standard_normal((ny, nx))), -1, 1)
+    sim = sim_for(nx, ny, params, rn, "f32")
+    S = host(perturbed_buffer(sim, 0.05, seed=3)).astype(np.float64)
+    ref = oracle_post_collision(S, nx, ny, params)
+    sim.step(1)
+    got = fluid(host(sim.live_pops()), walls).astype(np.float64)
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    print("f32 one step %s walls=%s %s: %.3e" % (shape, walls, stencil, err))
+    assert err < 2e-6, err
+    sim.close()
+
+
 @pytest.mark.parametrize("walls", [False, True])
 def test_one_step_options_f64(walls):
     """Fixed curvature, literal ghost equilibrium, no recolour, per-site force."""
