@@ -13,9 +13,10 @@ namespace chromo {
 constexpr int MASS_BLOCKS = 512;
 
 // Workgroup shape of the step kernel: NTX lattice columns x NR rows, one
-// thread each.  512 threads (8 waves) per CU leave 256 VGPRs per thread for
-// the register ring.
-constexpr int NTX_F32 = 128;  // every format with FP32 arithmetic
+// thread each, one workgroup per CU.  FP32 arithmetic: 768 threads (12
+// waves, 3 per SIMD) within 168 VGPRs and the whole 160 KB of LDS; wider
+// strips re-read fewer halo columns.
+constexpr int NTX_F32 = 192;  // every format with FP32 arithmetic
 constexpr int NR_F32 = 4;
 constexpr int NTX_F64 = 64;   // double (validation format)
 constexpr int NR_F64 = 4;

@@ -37,10 +37,15 @@ struct Pipe {
   static constexpr int LN = 2 * LU;
   static constexpr int LM = 3 * LU;
   static constexpr int RING = 4 * NR;                   // LDS ring depth in rows
-  static constexpr int IT0 = (LM + 9 + NR - 1) / NR;    // prologue iterations
-  static constexpr int ITN = (LU + 3 + NR - 1) / NR;    // first iteration of band N
-  static constexpr int ITU = 2 * ITN;                    // first iteration of band U
+  // Iterations from the start of one band to the start of the next: a band
+  // at row v needs its producer's rows up to v + 3, and the producer runs LU
+  // rows ahead.  Band N starts at ITN, band U at ITU, band O at IT0.
+  static constexpr int GAP = (LU + 3 + NR - 1) / NR;
+  static constexpr int ITN = GAP;
+  static constexpr int ITU = 2 * GAP;
+  static constexpr int IT0 = 3 * GAP;
   static_assert(LN == NR + LU && LU == NR * (LU / NR), "band hand-over must stay within one thread");
+  static_assert(LU >= 3 && RING >= LM + NR, "ring must hold every row a band still reads");
 };
 
 template <typename T>
@@ -66,6 +71,10 @@ struct Geom {
   int nx, ny, walls, F;    // F = fluid rows: ny, or ny - 2 with walls
   int TX, nstrips, TY, nchunks;
   int plane;               // nx * ny
+  // set per storage format and workgroup shape at launch:
+  unsigned pb, rb;         // bytes of one plane and of one row of a plane
+  int period;              // period of the virtual row index: ny, or 2 F with walls
+  int nr_mod;              // rows per march iteration, modulo period
 };
 
 template <typename T>
@@ -249,27 +258,6 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int p
   return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
 }
 
-// Wave-uniform row of the march: virtual row v (fluid-row index, any integer)
-// -> physical lattice row, and whether it is a mirror image.  y periodic:
-// plain wrap.  Walls: the fluid strip is reflected about the two wall planes,
-// which is the picture every stencil near a wall sees.
-__device__ __forceinline__ void virt_row(int v, const Geom& g, int& phys, bool& refl) {
-  if (!g.walls) {
-    int r = v;
-    while (r < 0) r += g.ny;
-    while (r >= g.ny) r -= g.ny;
-    phys = r;
-    refl = false;
-  } else {
-    const int P = 2 * g.F;
-    int t = v;
-    while (t < 0) t += P;
-    while (t >= P) t -= P;
-    refl = t >= g.F;
-    phys = refl ? g.F - t + g.F : 1 + t;  // 1 + (2F - 1 - t) when reflected
-  }
-}
-
 // Column byte offsets of one thread: x - 1, x, x + 1 (periodic).
 struct Cols {
   int m, o, p;
@@ -278,41 +266,61 @@ struct Cols {
 // Pull-streaming gather of the words of site (x, p): the word of link i comes
 // from the source site r - c_i, or, when r - c_i is a solid row, from the
 // reversed link's word at r itself (half-way bounce-back).  p is wave-uniform,
-// so every plane / row offset is scalar.
-template <typename S>
+// so every plane / row offset is scalar.  WALLS: rows 0 and ny - 1 are solid
+// (else y is periodic).
+template <typename S, bool WALLS>
 __device__ __forceinline__ void gather_words(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
                                              typename S::W out[S::NW]) {
-  const unsigned E = sizeof(typename S::W);
-  const unsigned PB = (unsigned)g.plane * E;  // plane bytes
   int rm = p - 1, rp = p + 1;
   bool bm = false, bp = false;
-  if (g.walls) {
+  if (WALLS) {
     bm = (rm == 0);
     bp = (rp == g.ny - 1);
   } else {
     if (rm < 0) rm += g.ny;
     if (rp >= g.ny) rp -= g.ny;
   }
-  const unsigned ro = (unsigned)p * g.nx * E, rom = (unsigned)rm * g.nx * E, rop = (unsigned)rp * g.nx * E;
+  const unsigned ro = (unsigned)p * g.rb, rom = (unsigned)rm * g.rb, rop = (unsigned)rp * g.rb;
 #pragma unroll
   for (int q = 0; q < S::NW; ++q) {
     const int i = word_link<S>(q);
     const int dy = link_cy(i), dx = link_cx(i);
-    const bool bounce = (dy == 1 && bm) || (dy == -1 && bp);
-    const unsigned soff = bounce ? (unsigned)word_bounce<S>(q) * PB + ro
-                                 : (unsigned)q * PB + (dy == 1 ? rom : (dy == -1 ? rop : ro));
+    const bool bounce = WALLS && ((dy == 1 && bm) || (dy == -1 && bp));
+    const unsigned soff = bounce ? (unsigned)word_bounce<S>(q) * g.pb + ro
+                                 : (unsigned)q * g.pb + (dy == 1 ? rom : (dy == -1 ? rop : ro));
     const int voff = bounce ? x.o : (dx == 1 ? x.m : (dx == -1 ? x.p : x.o));
     out[q] = load_word<typename S::W>(src, voff, (int)soff);
   }
 }
 
-template <typename S, typename T>
-__device__ __forceinline__ void gather(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
-                                       const Coef<T>& c, T R[9], T B[9]) {
-  typename S::W w[S::NW];
-  gather_words<S>(src, g, p, x, w);
-  decode<S>(w, c, R, B);
+template <typename S>
+__device__ __forceinline__ void gather_words_any(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
+                                                 typename S::W out[S::NW]) {
+  if (g.walls) {
+    gather_words<S, true>(src, g, p, x, out);
+  } else {
+    gather_words<S, false>(src, g, p, x, out);
+  }
 }
+
+// Wave-uniform virtual row of the march, kept modulo its period (ny, or the
+// 2 F rows of the fluid strip and its mirror image with walls) and advanced
+// by one march iteration at a time.
+template <bool WALLS>
+struct RowTrack {
+  int t;
+  __device__ __forceinline__ void init(int v, const Geom& g) {
+    t = v % g.period;
+    if (t < 0) t += g.period;
+  }
+  __device__ __forceinline__ void advance(const Geom& g) {
+    t += g.nr_mod;
+    if (t >= g.period) t -= g.period;
+  }
+  // physical row; with walls the strip is reflected about the two wall planes
+  __device__ __forceinline__ int phys(const Geom& g) const { return WALLS ? (t >= g.F ? 2 * g.F - t : 1 + t) : t; }
+  __device__ __forceinline__ bool refl(const Geom& g) const { return WALLS && t >= g.F; }
+};
 
 template <int RING>
 __device__ __forceinline__ int ring_row(int r) {
@@ -375,25 +383,28 @@ __device__ __forceinline__ T ring_div(const T (*sx)[NTX], const T (*sy)[NTX], in
 
 template <typename T, int NTX, int RING>
 struct Smem {
+  // stencil operands
   T rhoN[RING][NTX];
   T mx[RING][NTX];
   T my[RING][NTX];
   T ux[RING][NTX];
   T uy[RING][NTX];
   T phi[RING][NTX];
+  // values handed from one band to a later one at the same site
+  T rR[RING][NTX], rB[RING][NTX];    // colour densities, band M -> bands U, O
+  T gnx[RING][NTX], gny[RING][NTX];  // grad rho^N, band N -> band U
+  T Gx[RING][NTX], Gy[RING][NTX];    // force G, band U -> band O
+  T irho[RING][NTX];                 // 1/rho, band U -> band O
 };
 
-// Register state of one thread: the colour densities and the nine total
-// populations of the rows it gathered (one slot per iteration, read again
-// 2 and 3 iterations later) and the storage words prefetched for the next
-// band-M row (decoded only when used, so the loads stay in flight for a
-// whole iteration).
+// Register state of one thread: the nine total populations of the rows it
+// gathered (one slot per iteration, read again 2 and 3 iterations later) and
+// the storage words prefetched for the next band-M row (decoded only when
+// used, so the loads stay in flight for a whole iteration).
 template <typename S>
 struct March {
   using T = typename S::math;
-  T rf[4][11];   // rho_R, rho_B, f_0 .. f_8
-  T gn[2][2];    // grad rho^N, band N -> band U (next iteration)
-  T gr[2][2];    // force G, band U -> band O (next iteration)
+  T rf[4][9];
   typename S::W pw[S::NW];
 };
 
@@ -410,20 +421,32 @@ __device__ __forceinline__ void momenta(const T* f, T& jx, T& jy) {
   jy = (d15 + d37) + (f[2] - f[6]);
 }
 
-// Colour index (Sec. II); exactly +-1 in the pure phases.
+// Colour index (Sec. II); exactly +-1 in the pure phases (IEEE division).
 template <typename T>
 __device__ __forceinline__ T colour_index(T a0, T b0) {
   return (a0 - b0) / (a0 + b0);
 }
 
+// 1/x and 1/sqrt(x) where no exact value is needed: in float the hardware
+// estimate refined by one Newton step (within about one unit in the last
+// place), in double the IEEE operations.
+__device__ __forceinline__ float recip(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(r, __builtin_fmaf(-x, r, 1.0f), r);
+}
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsqrt_pos(float x) {
+  const float r = __builtin_amdgcn_rsqf(x);
+  return r * __builtin_fmaf(-0.5f * x * r, r, 1.5f);
+}
+__device__ __forceinline__ double rsqrt_pos(double x) { return 1.0 / sqrt(x); }
+
 // Collision, recolour and store of one site (band O).
 template <typename S, typename T, bool FIELDS>
-__device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buffer_rsrc_t dst, const T* rf,
-                                              T ux, T uy, T Gx, T Gy, T dPx, T dPy, T theta, T rhoN, T mx, T my,
-                                              int p, const Thread& t) {
+__device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buffer_rsrc_t dst, const T* f, T rR,
+                                              T rB, T ux, T uy, T Gx, T Gy, T inv_rho, T dPx, T dPy, T theta,
+                                              T rhoN, T mx, T my, int p, const Thread& t) {
   const Coef<T>& c = a.c;
-  const T rR = rf[0], rB = rf[1];
-  const T* f = rf + 2;
   const T rho = rR + rB;
   if (FIELDS) {
     const int site = p * a.g.nx + t.xg;
@@ -444,7 +467,7 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
   const T Jy = T(4) * (d15 + d37) - T(2) * d26;
   // lambda_3 from nu(rho^N) = (2/lambda_3 - 1)/6 (Sec. II), nu linear in rho^N
   const T nu = c.hnuR * (T(1) + rhoN) + c.hnuB * (T(1) - rhoN);
-  const T l3 = T(2) / (T(6) * nu + T(1));
+  const T l3 = T(2) * recip(T(6) * nu + T(1));
   // correction tensor C_ab (App. A, eq. Correction)
   const T k = T(1) - T(0.5) * l3;
   const T iso = ux * dPx + uy * dPy - rho * theta * T(1.0 / 3.0);
@@ -483,13 +506,16 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
   fp[5] = f[5] + (dsp - a15);
   fp[7] = f[7] + (dsm + a73);
   fp[3] = f[3] + (dsm - a73);
-  // d'Ortona recolour (Sec. II): t_i = beta phi_i rho_R rho_B / rho (m . c_hat_i);
-  // the split factors are exactly 1 / 0 in the pure phases
-  const T aR = rR / rho;
-  const T aB = rB / rho;
+  // d'Ortona recolour (Sec. II): t_i = beta phi_i rho_R rho_B / rho (m . c_hat_i).
+  // The split factors sum to one; the smaller is a product with 1/rho and the
+  // larger its complement, so they are exactly 1 and 0 in the pure phases.
+  const bool red_major = rB <= rR;
+  const T amin = (red_major ? rB : rR) * inv_rho;
+  const T aR = red_major ? T(1) - amin : amin;
+  const T aB = red_major ? amin : T(1) - amin;
   T t1 = T(0), t3 = T(0), t2 = T(0), t8 = T(0);
   if (c.recolor) {
-    const T moving = (c.c1R * rR + c.c1B * rB) / rho;
+    const T moving = (c.c1R * rR + c.c1B * rB) * inv_rho;
     const T q = c.beta18 * (aR * rB) * moving;
     const T qa = q * T(1.0 / 9.0);
     const T qd = q * T(1.0 / 36.0) * T(0.70710678118654752440);
@@ -511,23 +537,28 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
   R[4] = aR * fp[4] - t8; B[4] = aB * fp[4] + t8;
   typename S::W w[S::NW];
   encode<S>(R, B, c, w);
-  const unsigned E = sizeof(typename S::W);
-  const unsigned PB = (unsigned)a.g.plane * E;
-  const unsigned ro = (unsigned)p * a.g.nx * E;
+  const unsigned ro = (unsigned)p * a.g.rb;
 #pragma unroll
-  for (int q = 0; q < S::NW; ++q) store_word<typename S::W>(w[q], dst, t.cols.o, (int)(q * PB + ro));
+  for (int q = 0; q < S::NW; ++q) store_word<typename S::W>(w[q], dst, t.cols.o, (int)(q * a.g.pb + ro));
 }
 
-// One march iteration; S = it mod 4 selects the register-ring slots.
-template <int S, typename ST, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool FIELDS>
+// One march iteration; S = it mod 4 selects the register-ring slots.  tM and
+// tU track the virtual rows of the next band-M gather and of band U.
+template <int S, typename ST, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, bool FIELDS>
 __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgpu_buffer_rsrc_t src,
                                            __amdgpu_buffer_rsrc_t dst, Smem<T, NTX, Pipe<NR>::RING>& sm,
-                                           March<ST>& st, const Thread& t) {
+                                           March<ST>& st, const Thread& t, RowTrack<WALLS>& tM,
+                                           RowTrack<WALLS>& tU) {
   using PP = Pipe<NR>;
   constexpr int RING = PP::RING;
   const Geom& g = a.g;
   const Coef<T>& c = a.c;
-  const int tx = t.tx, ty = t.ty;
+  // ty passes through an opaque scalar move each iteration, so the ring-row
+  // addresses derived from it are formed when used rather than hoisted out of
+  // the loop for all four unrolled copies (which exhausts the VGPR budget)
+  const int tx = t.tx;
+  int ty;
+  asm volatile("s_mov_b32 %0, %1" : "=s"(ty) : "s"(t.ty));
   // band-O virtual row of this thread (wave-uniform)
   const int base = t.ya - NR * PP::IT0 + NR * it + ty;
   constexpr int sM = S, sU = (S + 2) & 3, sO = (S + 1) & 3;
@@ -542,17 +573,15 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
     decode<ST>(st.pw, c, pr, pb);
     T rR = ((pr[0] + pr[2]) + (pr[4] + pr[6])) + ((pr[1] + pr[3]) + (pr[5] + pr[7])) + pr[8];
     T rB = ((pb[0] + pb[2]) + (pb[4] + pb[6])) + ((pb[1] + pb[3]) + (pb[5] + pb[7])) + pb[8];
-    rf[0] = rR;
-    rf[1] = rB;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) rf[2 + i] = pr[i] + pb[i];
-    sm.rhoN[ring_row<RING>(rowM)][tx] = colour_index(rR * c.inv_rho0R, rB * c.inv_rho0B);
-    if (it + 1 < t.nit) {  // prefetch the next band-M row
-      int pn;
-      bool rn;
-      virt_row(base + PP::LM + NR, g, pn, rn);
-      gather_words<ST>(src, g, pn, t.cols, st.pw);
-    }
+    for (int i = 0; i < 9; ++i) rf[i] = pr[i] + pb[i];
+    const int rm = ring_row<RING>(rowM);
+    sm.rR[rm][tx] = rR;
+    sm.rB[rm][tx] = rB;
+    sm.rhoN[rm][tx] = colour_index(rR * c.inv_rho0R, rB * c.inv_rho0B);
+    // prefetch the next band-M row (after the last iteration: a row never used)
+    gather_words<ST, WALLS>(src, g, tM.phys(g), t.cols, st.pw);
+    tM.advance(g);
   }
   __syncthreads();
 
@@ -560,32 +589,32 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   if (it >= PP::ITN && tx >= RG && tx < NTX - RG) {
     T gx, gy;
     ring_grad<RG, RING, NTX>(sm.rhoN, rowN, tx, gx, gy);
-    const T s = sqrt(gx * gx + gy * gy + c.eps2);
+    const T is = rsqrt_pos(gx * gx + gy * gy + c.eps2);
     const int rn = ring_row<RING>(rowN);
-    sm.mx[rn][tx] = gx / s;
-    sm.my[rn][tx] = gy / s;
-    st.gn[S & 1][0] = gx;
-    st.gn[S & 1][1] = gy;
+    sm.mx[rn][tx] = gx * is;
+    sm.my[rn][tx] = gy * is;
+    sm.gnx[rn][tx] = gx;
+    sm.gny[rn][tx] = gy;
   }
   __syncthreads();
 
   // ---- band U: Phi', curvature, force and velocity -------------------------
   if (it >= PP::ITU) {
     const T* rf = st.rf[sU];
-    const T rho = rf[0] + rf[1];
     const int ru = ring_row<RING>(rowU);
-    sm.phi[ru][tx] = c.c06R * rf[0] + c.phiB * rf[1] - rho * T(1.0 / 3.0);
+    const T rR = sm.rR[ru][tx], rB = sm.rB[ru][tx];
+    const T rho = rR + rB;
+    sm.phi[ru][tx] = c.c06R * rR + c.phiB * rB - rho * T(1.0 / 3.0);
     if (tx >= RG + RK && tx < NTX - RG - RK) {
-      int p;
-      bool refl;
-      virt_row(base + PP::LU, g, p, refl);
+      const int p = tU.phys(g);
+      const bool refl = tU.refl(g);
       T K;
       if (c.fixed_K) {
         K = c.K_fixed;
       } else {
         K = -ring_div<RK, RING, NTX>(sm.mx, sm.my, rowU, tx);  // K = div n, n = -m
       }
-      const T gnx = st.gn[(S + 1) & 1][0], gny = st.gn[(S + 1) & 1][1];
+      const T gnx = sm.gnx[ru][tx], gny = sm.gny[ru][tx];
       T Gx = c.half_sigma * K * gnx + c.gx;
       T Gy = c.half_sigma * K * gny + (refl ? -c.gy : c.gy);
       if (a.force) {
@@ -594,30 +623,35 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
         Gy += refl ? -a.force[g.plane + site] : a.force[g.plane + site];
       }
       T jx, jy;
-      momenta(rf + 2, jx, jy);
+      momenta(rf, jx, jy);
       if (refl) jy = -jy;   // mirror image: the y-momentum changes sign
-      sm.ux[ru][tx] = (jx + T(0.5) * Gx) / rho;
-      sm.uy[ru][tx] = (jy + T(0.5) * Gy) / rho;
-      st.gr[S & 1][0] = Gx;
-      st.gr[S & 1][1] = Gy;
+      const T ir = recip(rho);
+      sm.ux[ru][tx] = (jx + T(0.5) * Gx) * ir;
+      sm.uy[ru][tx] = (jy + T(0.5) * Gy) * ir;
+      sm.Gx[ru][tx] = Gx;
+      sm.Gy[ru][tx] = Gy;
+      sm.irho[ru][tx] = ir;
     }
   }
+  tU.advance(g);
   __syncthreads();
 
   // ---- band O: correction, collision, recolour, store ----------------------
   if (it >= PP::IT0 && t.own && base < t.yb) {
     T dPx, dPy;
     ring_grad<RP, RING, NTX>(sm.phi, rowO, tx, dPx, dPy);
+    __builtin_amdgcn_sched_barrier(0);  // bound register pressure: finish one stencil before the next
     const T theta = ring_div<RU, RING, NTX>(sm.ux, sm.uy, rowO, tx);
+    __builtin_amdgcn_sched_barrier(0);
     const int ro = ring_row<RING>(rowO);
-    const int p = g.walls ? base + 1 : base;
-    collide_store<ST, T, FIELDS>(a, dst, st.rf[sO], sm.ux[ro][tx], sm.uy[ro][tx], st.gr[(S + 1) & 1][0],
-                             st.gr[(S + 1) & 1][1], dPx, dPy, theta, sm.rhoN[ro][tx], sm.mx[ro][tx],
-                             sm.my[ro][tx], p, t);
+    const int p = WALLS ? base + 1 : base;
+    collide_store<ST, T, FIELDS>(a, dst, st.rf[sO], sm.rR[ro][tx], sm.rB[ro][tx], sm.ux[ro][tx], sm.uy[ro][tx],
+                                 sm.Gx[ro][tx], sm.Gy[ro][tx], sm.irho[ro][tx], dPx, dPy, theta,
+                                 sm.rhoN[ro][tx], sm.mx[ro][tx], sm.my[ro][tx], p, t);
   }
 }
 
-template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool FIELDS>
+template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, bool FIELDS>
 __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typename ST::math> a) {
   using T = typename ST::math;
   using PP = Pipe<NR>;
@@ -656,17 +690,20 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typen
   t.nit = PP::IT0 + (t.yb - t.ya + NR - 1) / NR;
 
   March<ST> st;
-  {
-    int p;
-    bool refl;
-    virt_row(t.ya - NR * PP::IT0 + PP::LM + t.ty, g, p, refl);
-    gather_words<ST>(src, g, p, t.cols, st.pw);
-  }
+  const int v0 = t.ya - NR * PP::IT0 + t.ty;  // band-O virtual row of iteration 0
+  RowTrack<WALLS> tM, tU;
+  tM.init(v0 + PP::LM, g);
+  gather_words<ST, WALLS>(src, g, tM.phys(g), t.cols, st.pw);
+  tM.advance(g);
+  tU.init(v0 + PP::LU, g);
   for (int it = 0; it < t.nit; it += 4) {
-    march_iter<0, ST, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it, a, src, dst, sm, st, t);
-    if (it + 1 < t.nit) march_iter<1, ST, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 1, a, src, dst, sm, st, t);
-    if (it + 2 < t.nit) march_iter<2, ST, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 2, a, src, dst, sm, st, t);
-    if (it + 3 < t.nit) march_iter<3, ST, T, NTX, NR, RG, RK, RP, RU, FIELDS>(it + 3, a, src, dst, sm, st, t);
+    march_iter<0, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, FIELDS>(it, a, src, dst, sm, st, t, tM, tU);
+    if (it + 1 < t.nit)
+      march_iter<1, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, FIELDS>(it + 1, a, src, dst, sm, st, t, tM, tU);
+    if (it + 2 < t.nit)
+      march_iter<2, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, FIELDS>(it + 2, a, src, dst, sm, st, t, tM, tU);
+    if (it + 3 < t.nit)
+      march_iter<3, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, FIELDS>(it + 3, a, src, dst, sm, st, t, tM, tU);
   }
 }
 
@@ -686,7 +723,7 @@ __global__ void __launch_bounds__(256) stream_only_kernel(const void* src, void*
   cols.m = (x == 0 ? g.nx - 1 : x - 1) * E;
   cols.p = (x == g.nx - 1 ? 0 : x + 1) * E;
   W v[S::NW];
-  gather_words<S>(make_rsrc<S>(src, g.plane), g, p, cols, v);
+  gather_words_any<S>(make_rsrc<S>(src, g.plane), g, p, cols, v);
   W* d = static_cast<W*>(dst) + p * g.nx + x;
 #pragma unroll
   for (int q = 0; q < S::NW; ++q) d[q * g.plane] = v[q];

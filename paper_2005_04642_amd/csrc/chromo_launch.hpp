@@ -8,6 +8,12 @@
 namespace chromo {
 namespace launch {
 
+template <typename S>
+struct Shape {
+  static constexpr int ntx = sizeof(typename S::math) == 8 ? NTX_F64 : NTX_F32;
+  static constexpr int nr = sizeof(typename S::math) == 8 ? NR_F64 : NR_F32;
+};
+
 // Per-site constants of the scheme (Sec. II, App. A) in the arithmetic type.
 template <typename S>
 Coef<typename S::math> make_coef(const lbm_params& p) {
@@ -50,19 +56,31 @@ Coef<typename S::math> make_coef(const lbm_params& p) {
   return c;
 }
 
+
+// Per-format geometry: byte strides of the storage words and the row period
+// of the march.
 template <typename S>
-struct Shape {
-  static constexpr int ntx = sizeof(typename S::math) == 8 ? NTX_F64 : NTX_F32;
-  static constexpr int nr = sizeof(typename S::math) == 8 ? NR_F64 : NR_F32;
-};
+Geom geom_for(const Geom& g0) {
+  Geom g = g0;
+  g.pb = (unsigned)g.plane * (unsigned)sizeof(typename S::W);
+  g.rb = (unsigned)g.nx * (unsigned)sizeof(typename S::W);
+  g.period = g.walls ? 2 * g.F : g.ny;
+  g.nr_mod = Shape<S>::nr % g.period;
+  return g;
+}
 
 template <typename S, int RG, int RK, int RP, int RU, bool FIELDS>
 hipError_t march(const StepArgs<typename S::math>& a, hipStream_t s) {
   constexpr int NTX = Shape<S>::ntx, NR = Shape<S>::nr;
   const int ntiles = a.g.nstrips * a.g.nchunks;
   const int nblocks = 8 * ((ntiles + 7) / 8);  // whole rounds over the 8 XCDs (see the kernel)
-  hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, FIELDS>), dim3(nblocks), dim3(NTX * NR), 0,
-                     s, a);
+  if (a.g.walls) {
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, true, FIELDS>), dim3(nblocks),
+                       dim3(NTX * NR), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, false, FIELDS>), dim3(nblocks),
+                       dim3(NTX * NR), 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -102,7 +120,7 @@ StepArgs<typename S::math> args(const lbm_params& p, const Geom& g, const void* 
   a.dst = dst;
   a.force = static_cast<const T*>(force);
   a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = nullptr;
-  a.g = g;
+  a.g = geom_for<S>(g);
   a.c = make_coef<S>(p);
   return a;
 }
@@ -131,7 +149,7 @@ hipError_t fields(const lbm_params& p, const Geom& g, const void* src, const voi
 template <typename S>
 hipError_t stream_only(const Geom& g, const void* src, void* dst, hipStream_t s) {
   dim3 grid((g.nx + 255) / 256, g.F);
-  hipLaunchKernelGGL(stream_only_kernel<S>, grid, dim3(256), 0, s, src, dst, g);
+  hipLaunchKernelGGL(stream_only_kernel<S>, grid, dim3(256), 0, s, src, dst, geom_for<S>(g));
   return hipGetLastError();
 }
 
@@ -139,14 +157,16 @@ template <typename S>
 hipError_t init(const lbm_params& p, const Geom& g, const void* rhoN0, void* dst, hipStream_t s) {
   using T = typename S::math;
   dim3 grid((g.nx + 255) / 256, g.ny);
-  hipLaunchKernelGGL(init_kernel<S>, grid, dim3(256), 0, s, static_cast<const T*>(rhoN0), dst, g, make_coef<S>(p),
+  hipLaunchKernelGGL(init_kernel<S>, grid, dim3(256), 0, s, static_cast<const T*>(rhoN0), dst, geom_for<S>(g),
+                     make_coef<S>(p),
                      (T)p.rho0_R, (T)p.rho0_B);
   return hipGetLastError();
 }
 
 template <typename S>
 hipError_t mass(const lbm_params& p, const Geom& g, const void* pops, double* partial, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(mass_partial_kernel<S>, dim3(MASS_BLOCKS), dim3(256), 0, s, pops, g, make_coef<S>(p), partial);
+  hipLaunchKernelGGL(mass_partial_kernel<S>, dim3(MASS_BLOCKS), dim3(256), 0, s, pops, geom_for<S>(g),
+                     make_coef<S>(p), partial);
   hipLaunchKernelGGL(mass_final_kernel, dim3(1), dim3(256), 0, s, partial, MASS_BLOCKS, out);
   return hipGetLastError();
 }
