@@ -155,10 +155,40 @@ int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN,
  * two masses to host out[2].  Returns LBM_ENONFINITE if either is not finite. */
 int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream);
 
-/* Adjoint of one step (gradient back-propagation through lbm_step).  Not
- * provided by this build: always returns LBM_ENOTIMPL. */
-int lbm_adjoint_step(lbm_handle* h, const void* pops_t, void* adj_pops,
-                     double* dL_dsigma_dev, void* dL_dforce_dev, hipStream_t stream);
+/* ---- adjoint (reverse-mode derivative of lbm_step) ------------------------
+ * Provided for LBM_STORAGE_F64 and LBM_STORAGE_F32 on periodic lattices
+ * (walls_y = 0); other cases return LBM_ENOTIMPL.  Adjoint buffers have the
+ * layout of an F64/F32 population buffer ([colour 2][link 9][ny][nx], the
+ * arithmetic type), aligned with the pull layout: adj[C][i](s) is dL/d of the
+ * stored word buf[C][i](s).  The step that is differentiated is the one
+ * lbm_step performs with the handle's parameters and force field. */
+
+/* Bytes of device workspace lbm_adjoint_step needs (256-byte aligned): the
+ * saved intermediates and adjoint fields (39 planes of nx*ny values of the
+ * arithmetic type) and the FP64 partial sums of dL/dsigma.  0 if the adjoint is
+ * not provided for these parameters. */
+size_t lbm_adjoint_workspace_bytes(const lbm_params* p);
+
+/* One step backwards.  pops_t: the state the step starts from (a population
+ * buffer in the handle's storage format).  adj_next: dL/d(state after the
+ * step).  adj_out: receives dL/d(pops_t) (overwritten; must differ from
+ * adj_next).  dL_dsigma_dev: NULL or one device double to which dL/dsigma of
+ * this step is added (FP64 reduction).  dL_dforce_dev: NULL or a device
+ * [2][ny][nx] array (arithmetic type) to which dL/dG_ext of this step is added,
+ * G_ext being the per-site force density of lbm_init (the derivative exists
+ * whether or not a force field was given).  Enqueued on `stream`. */
+int lbm_adjoint_step(lbm_handle* h, const void* pops_t, const void* adj_next, void* adj_out, void* workspace,
+                     size_t ws_bytes, double* dL_dsigma_dev, void* dL_dforce_dev, hipStream_t stream);
+
+/* Adjoint of the colour index that lbm_fields reports for the state pops:
+ * adj_out (overwritten) = dL/dpops given dL_drhoN, a device [ny][nx] array
+ * (arithmetic type).  Starts the backward pass of a loss on rho^N. */
+int lbm_rhoN_adjoint(lbm_handle* h, const void* pops, const void* dL_drhoN, void* adj_out, hipStream_t stream);
+
+/* Adjoint of lbm_init's rest state: adds to dL_drhoN0 (device [ny][nx],
+ * arithmetic type) the derivative of the loss with respect to the initial
+ * colour index rhoN0, given adj_pops0 = dL/d(initial populations). */
+int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, void* dL_drhoN0, hipStream_t stream);
 
 /* 0 if pops_a holds the live state, 1 if pops_b does. */
 int lbm_current_pops(const lbm_handle* h);

@@ -17,7 +17,8 @@ LIB = os.path.join(PKG, "libchromo_lbm.so")
 CSRC = os.path.join(PKG, "csrc")
 SOURCES = [os.path.join(CSRC, f) for f in
            ("chromo_api.hip", "chromo_f32.hip", "chromo_f64.hip", "chromo_f16o.hip", "chromo_bf16o.hip")]
-HEADERS = [os.path.join(CSRC, f) for f in ("chromo_kernels.hpp", "chromo_host.hpp", "chromo_launch.hpp")] + \
+HEADERS = [os.path.join(CSRC, f) for f in ("chromo_kernels.hpp", "chromo_host.hpp", "chromo_launch.hpp",
+                                           "chromo_adjoint.hpp")] + \
           [os.path.join(ROOT, "include", "chromo_lbm.h")]
 
 HIPCC_FLAGS = [

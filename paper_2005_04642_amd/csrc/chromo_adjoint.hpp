@@ -1,0 +1,513 @@
+// Adjoint of one time step (reverse-mode derivative of the step of
+// chromo_kernels.hpp) on periodic lattices.
+//
+// The step maps the stored populations buf_t (post-recolour, pull layout) to
+// buf_{t+1}.  Given lambda_{t+1} = dL/dbuf_{t+1} (same layout, arithmetic
+// type), the passes below compute lambda_t = (d buf_{t+1} / d buf_t)^T
+// lambda_{t+1}, and add dL/dsigma (FP64) and dL/dG_ext (per-site force) to
+// their outputs.  The chain is walked backwards:
+//   pass 1 (local)  : the step kernel in MODE_ADJ recomputes the forward
+//                     quantities of each site and, instead of storing the new
+//                     populations, runs local_backward: recolour,
+//                     reconstruction, relaxation, correction tensor (App. A)
+//                     -> adjoints of f_i, rho_R, rho_B, u, G, grad Phi', div u,
+//                     rho^N, director m; it also saves rho_C, u, K, grad rho^N;
+//   pass 2 (stencil): div u and grad Phi' transposed, then u = (j + G/2)/rho,
+//                     Phi' and G = sigma K grad(rho^N)/2 + G_ext (Sec. II);
+//   pass 3 (stencil): K = -div m transposed, then m = g/sqrt(|g|^2 + eps^2);
+//   pass 4 (stencil): g = grad rho^N transposed, then the colour index;
+//   pass 5 (gather) : pre-collision populations from rho_C, f_i, j, and the
+//                     pull-streaming gather transposed (a push).
+// Every App. B stencil D is a sum of antisymmetric pair differences, so on a
+// periodic lattice its transpose is -D.
+#pragma once
+
+#include "chromo_kernels.hpp"
+
+namespace chromo {
+namespace adj {
+
+// planes of the adjoint workspace after the SV_N save planes
+enum {
+  A_F = 0,  // 9 planes: adjoint of f_i through the collision
+  A_RR = 9, A_RB, A_UX, A_UY, A_GX, A_GY, A_DPX, A_DPY, A_TH, A_RN, A_MX, A_MY,
+  A_END
+};
+static_assert(A_END == A_N, "local adjoint count");
+enum { B_RR, B_RB, B_JX, B_JY, B_K, B_GX, B_GY, B_N };
+enum { C_GX, C_GY, C_N };
+enum { D_RR, D_RB, D_N };
+constexpr int WS_PLANES = SV_N + A_N + B_N + C_N + D_N;
+// FP64 partial sums of dL/dsigma: one per 256-site block of a row
+__host__ __device__ inline int red_blocks(int nx, int ny) { return ((nx + 255) / 256) * ny; }
+
+// App. B first-derivative stencil of radius R applied to a periodic global
+// field at (x, y): (d/dx, d/dy), the same sums as the forward ring stencils.
+template <int R, typename T>
+__device__ __forceinline__ void grad_at(const T* f, int nx, int ny, int x, int y, T& gx, T& gy) {
+  const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
+  gx = T(0);
+  gy = T(0);
+#pragma unroll
+  for (int n = 1; n <= R; ++n) {
+    const T b = stencil_b<R, T>(n);
+    const int xp = (x + n) % nx, xm = (x - n + nx) % nx;
+    const int yp = (y + n) % ny, ym = (y - n + ny) % ny;
+    const T d1 = f[yp * nx + xp] - f[ym * nx + xm];
+    const T d3 = f[yp * nx + xm] - f[ym * nx + xp];
+    const T d8 = f[y * nx + xp] - f[y * nx + xm];
+    const T d2 = f[yp * nx + x] - f[ym * nx + x];
+    gx += b * (wd * (d1 - d3) + wa * d8);
+    gy += b * (wd * (d1 + d3) + wa * d2);
+  }
+}
+
+template <int R, typename T>
+__device__ __forceinline__ T div_at(const T* fx, const T* fy, int nx, int ny, int x, int y) {
+  T ax, ay, bx, by;
+  grad_at<R>(fx, nx, ny, x, y, ax, ay);
+  grad_at<R>(fy, nx, ny, x, y, bx, by);
+  return ax + by;
+}
+
+template <typename T>
+__device__ __forceinline__ void grad_r(int r, const T* f, int nx, int ny, int x, int y, T& gx, T& gy) {
+  if (r == 3) {
+    grad_at<3>(f, nx, ny, x, y, gx, gy);
+  } else {
+    grad_at<1>(f, nx, ny, x, y, gx, gy);
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ T div_r(int r, const T* fx, const T* fy, int nx, int ny, int x, int y) {
+  return r == 3 ? div_at<3>(fx, fy, nx, ny, x, y) : div_at<1>(fx, fy, nx, ny, x, y);
+}
+
+struct Radii {
+  int g, k, p, u;
+};
+
+// ---------------------------------------------------------------------------
+// pass 1: local adjoint of correction tensor, relaxation, reconstruction and
+// recolour at one site.  Inputs: pre-collision totals f_i, colour densities,
+// the site's u, G, grad Phi', div u, rho^N, director m, and lR, lB = dL/d of
+// the site's post-recolour populations.  out[A_*] receives the adjoints.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void local_backward(const Coef<T>& c, const T* f, T rR, T rB, T ux, T uy, T Gx, T Gy, T dPx, T dPy,
+                               T theta, T rhoN, T mx, T my, const T* lR, const T* lB, T* out) {
+  // ---- forward, as in the step (App. A, Sec. II) --------------------------
+  const T rho = rR + rB;
+  const T d15 = f[1] - f[5], d37 = f[3] - f[7], d84 = f[8] - f[4], d26 = f[2] - f[6];
+  const T s15 = f[1] + f[5], s37 = f[3] + f[7], sd = s15 + s37;
+  const T pxx = sd + (f[4] + f[8]);
+  const T pyy = sd + (f[2] + f[6]);
+  const T pxy = s15 - s37;
+  const T N = f[0] - T(2) * ((f[2] + f[6]) + (f[4] + f[8])) + T(4) * sd;
+  const T Jx = T(4) * (d15 - d37) - T(2) * d84;
+  const T Jy = T(4) * (d15 + d37) - T(2) * d26;
+  const T nu = c.hnuR * (T(1) + rhoN) + c.hnuB * (T(1) - rhoN);
+  const T l3 = T(2) / (T(6) * nu + T(1));
+  const T k = T(1) - T(0.5) * l3;
+  const T iso = ux * dPx + uy * dPy - rho * theta * T(1.0 / 3.0);
+  const T ex = Gx - dPx, ey = Gy - dPy;
+  const T Cxx = k * (T(2) * ux * ex - iso);
+  const T Cyy = k * (T(2) * uy * ey - iso);
+  const T Cxy = k * (ux * ey + uy * ex);
+  const T P0 = c.c06R * rR + c.c06B * rB;
+  const T qxx = (pxx - P0) - rho * ux * ux;
+  const T qyy = (pyy - P0) - rho * uy * uy;
+  const T qxy = pxy - rho * ux * uy;
+  const T dxx = Cxx - l3 * qxx;
+  const T dyy = Cyy - l3 * qyy;
+  const T dxy = Cxy - l3 * qxy;
+  const T N0 = c.ghost_eq ? T(0) : T(1.8) * (c.alphaR * rR + c.alphaB * rB) - T(0.8) * rho;
+  const T dN = -c.lambda6 * (N - N0);
+  const T dJx = -c.lambda7 * Jx;
+  const T dJy = -c.lambda7 * Jy;
+  const T tr = dxx + dyy;
+  T fp[9];
+  fp[0] = f[0] + T(4.0 / 9.0) * (T(0.25) * dN - T(1.5) * tr);
+  const T axc = -T(1.5) * tr - T(0.5) * dN;
+  const T sx = T(1.0 / 9.0) * (axc + T(4.5) * dxx);
+  const T sy = T(1.0 / 9.0) * (axc + T(4.5) * dyy);
+  const T ax = T(1.0 / 9.0) * (T(3) * Gx - T(0.75) * dJx);
+  const T ay = T(1.0 / 9.0) * (T(3) * Gy - T(0.75) * dJy);
+  fp[8] = f[8] + (sx + ax);
+  fp[4] = f[4] + (sx - ax);
+  fp[2] = f[2] + (sy + ay);
+  fp[6] = f[6] + (sy - ay);
+  const T dgc = T(3) * tr + dN;
+  const T dsp = T(1.0 / 36.0) * (dgc + T(9) * dxy);
+  const T dsm = T(1.0 / 36.0) * (dgc - T(9) * dxy);
+  const T a15 = T(1.0 / 36.0) * (T(3) * (Gx + Gy) + T(1.5) * (dJx + dJy));
+  const T a73 = T(1.0 / 36.0) * (T(3) * (Gx - Gy) + T(1.5) * (dJx - dJy));
+  fp[1] = f[1] + (dsp + a15);
+  fp[5] = f[5] + (dsp - a15);
+  fp[7] = f[7] + (dsm + a73);
+  fp[3] = f[3] + (dsm - a73);
+  const T irho = T(1) / rho;
+  const T aR = rR * irho, aB = rB * irho;
+  const T moving = (c.c1R * rR + c.c1B * rB) * irho;
+  const T X = rR * rB * irho;
+  const T q = c.recolor ? c.beta18 * X * moving : T(0);
+  const T qa = q * T(1.0 / 9.0);
+  const T qd = q * T(1.0 / 36.0) * T(0.70710678118654752440);
+
+  // ---- backward ------------------------------------------------------------
+  // recolour: R_i = aR fp_i + t_i, B_i = aB fp_i - t_i (t_0 = 0)
+  T lfp[9];
+  T laR = T(0), laB = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    lfp[i] = aR * lR[i] + aB * lB[i];
+    laR += fp[i] * lR[i];
+    laB += fp[i] * lB[i];
+  }
+  const T lt1 = (lR[1] - lB[1]) - (lR[5] - lB[5]);
+  const T lt3 = (lR[3] - lB[3]) - (lR[7] - lB[7]);
+  const T lt2 = (lR[2] - lB[2]) - (lR[6] - lB[6]);
+  const T lt8 = (lR[8] - lB[8]) - (lR[4] - lB[4]);
+  T lmx = T(0), lmy = T(0), lq = T(0);
+  if (c.recolor) {
+    // t8 = qa mx, t2 = qa my, t1 = qd (mx + my), t3 = qd (my - mx)
+    lmx = qa * lt8 + qd * (lt1 - lt3);
+    lmy = qa * lt2 + qd * (lt1 + lt3);
+    lq = (lt8 * mx + lt2 * my) * T(1.0 / 9.0) +
+         (lt1 * (mx + my) + lt3 * (my - mx)) * (T(1.0 / 36.0) * T(0.70710678118654752440));
+  }
+  // q = beta18 X moving, X = rR rB / rho, moving = (c1R rR + c1B rB) / rho
+  T lrR = T(0), lrB = T(0), lrho = T(0);
+  {
+    const T lX = lq * c.beta18 * moving;
+    const T lmv = lq * c.beta18 * X;
+    lrR += lX * rB * irho + lmv * c.c1R * irho;
+    lrB += lX * rR * irho + lmv * c.c1B * irho;
+    lrho -= (lX * X + lmv * moving) * irho;
+    lrR += laR * irho;
+    lrB += laB * irho;
+    lrho -= (laR * aR + laB * aB) * irho;
+  }
+  // reconstruction f+ = f + M^{-1}(m+ - m)
+  T lf[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) lf[i] = lfp[i];
+  T ltr = T(0), ldxx = T(0), ldyy = T(0), ldxy = T(0), ldN = T(0), ldJx = T(0), ldJy = T(0);
+  T lGx = T(0), lGy = T(0);
+  ldN += lfp[0] * T(1.0 / 9.0);
+  ltr -= lfp[0] * T(2.0 / 3.0);
+  const T lsx = lfp[8] + lfp[4], lsy = lfp[2] + lfp[6];
+  const T lax = lfp[8] - lfp[4], lay = lfp[2] - lfp[6];
+  const T laxc = (lsx + lsy) * T(1.0 / 9.0);
+  ldxx += lsx * T(0.5);
+  ldyy += lsy * T(0.5);
+  ltr -= T(1.5) * laxc;
+  ldN -= T(0.5) * laxc;
+  lGx += lax * T(1.0 / 3.0);
+  ldJx -= lax * T(1.0 / 12.0);
+  lGy += lay * T(1.0 / 3.0);
+  ldJy -= lay * T(1.0 / 12.0);
+  const T ldsp = lfp[1] + lfp[5], ldsm = lfp[7] + lfp[3];
+  const T la15 = lfp[1] - lfp[5], la73 = lfp[7] - lfp[3];
+  const T ldgc = (ldsp + ldsm) * T(1.0 / 36.0);
+  ldxy += (ldsp - ldsm) * T(0.25);
+  lGx += (la15 + la73) * T(1.0 / 12.0);
+  lGy += (la15 - la73) * T(1.0 / 12.0);
+  ldJx += (la15 + la73) * T(1.0 / 24.0);
+  ldJy += (la15 - la73) * T(1.0 / 24.0);
+  ltr += T(3) * ldgc;
+  ldN += ldgc;
+  ldxx += ltr;
+  ldyy += ltr;
+  // relaxation
+  const T lJx = -c.lambda7 * ldJx, lJy = -c.lambda7 * ldJy;
+  const T lN = -c.lambda6 * ldN;
+  if (!c.ghost_eq) {
+    const T lN0 = c.lambda6 * ldN;
+    lrR += T(1.8) * c.alphaR * lN0;
+    lrB += T(1.8) * c.alphaB * lN0;
+    lrho -= T(0.8) * lN0;
+  }
+  // d = C - l3 q
+  T lCxx = ldxx, lCyy = ldyy, lCxy = ldxy;
+  T ll3 = -(ldxx * qxx + ldyy * qyy + ldxy * qxy);
+  const T lpxx = -l3 * ldxx, lpyy = -l3 * ldyy, lpxy = -l3 * ldxy;
+  const T lP = l3 * (ldxx + ldyy);
+  lrho += l3 * (ldxx * ux * ux + ldyy * uy * uy + ldxy * ux * uy);
+  T lux = l3 * rho * (T(2) * ux * ldxx + uy * ldxy);
+  T luy = l3 * rho * (T(2) * uy * ldyy + ux * ldxy);
+  lrR += c.c06R * lP;
+  lrB += c.c06B * lP;
+  // correction tensor
+  T lk = lCxx * (T(2) * ux * ex - iso) + lCyy * (T(2) * uy * ey - iso) + lCxy * (ux * ey + uy * ex);
+  lux += k * (T(2) * ex * lCxx + ey * lCxy);
+  luy += k * (T(2) * ey * lCyy + ex * lCxy);
+  const T lex = k * (T(2) * ux * lCxx + uy * lCxy);
+  const T ley = k * (T(2) * uy * lCyy + ux * lCxy);
+  lGx += lex;
+  lGy += ley;
+  T ldPx = -lex, ldPy = -ley;
+  const T liso = -k * (lCxx + lCyy);
+  lux += dPx * liso;
+  luy += dPy * liso;
+  ldPx += ux * liso;
+  ldPy += uy * liso;
+  lrho -= theta * liso * T(1.0 / 3.0);
+  const T lth = -rho * liso * T(1.0 / 3.0);
+  ll3 -= T(0.5) * lk;
+  // l3 = 2 / (6 nu + 1), nu linear in rho^N
+  const T lnu = -T(3) * l3 * l3 * ll3;
+  const T lrN = (c.hnuR - c.hnuB) * lnu;
+  // modes of f
+  lf[0] += lN;
+  {
+    const T e = lpxx + lpyy + T(4) * lN;  // common to the diagonal links
+    lf[1] += e + lpxy + T(4) * (lJx + lJy);
+    lf[5] += e + lpxy - T(4) * (lJx + lJy);
+    lf[3] += e - lpxy + T(4) * (lJy - lJx);
+    lf[7] += e - lpxy - T(4) * (lJy - lJx);
+    lf[8] += lpxx - T(2) * lN - T(2) * lJx;
+    lf[4] += lpxx - T(2) * lN + T(2) * lJx;
+    lf[2] += lpyy - T(2) * lN - T(2) * lJy;
+    lf[6] += lpyy - T(2) * lN + T(2) * lJy;
+  }
+  lrR += lrho;
+  lrB += lrho;
+
+#pragma unroll
+  for (int i = 0; i < 9; ++i) out[A_F + i] = lf[i];
+  out[A_RR] = lrR;
+  out[A_RB] = lrB;
+  out[A_UX] = lux;
+  out[A_UY] = luy;
+  out[A_GX] = lGx;
+  out[A_GY] = lGy;
+  out[A_DPX] = ldPx;
+  out[A_DPY] = ldPy;
+  out[A_TH] = lth;
+  out[A_RN] = lrN;
+  out[A_MX] = lmx;
+  out[A_MY] = lmy;
+}
+
+static __device__ __forceinline__ double block_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  __shared__ double red[4];
+  const int w = threadIdx.x / 64, l = threadIdx.x % 64;
+  if (l == 0) red[w] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// ---------------------------------------------------------------------------
+// pass 2: div u and grad Phi' transposed; u, Phi', G local
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, Radii r, const T* __restrict__ sv,
+                                                    const T* __restrict__ A, T* __restrict__ B,
+                                                    T* __restrict__ dforce, double* __restrict__ part) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  const int P = g.plane, site = y * g.nx + x;
+  double acc = 0.0;
+  if (x < g.nx) {
+    T tx, ty;
+    grad_r(r.u, A + A_TH * P, g.nx, g.ny, x, y, tx, ty);
+    const T lux = A[A_UX * P + site] - tx;  // theta = div u: transpose -grad
+    const T luy = A[A_UY * P + site] - ty;
+    const T lphi = -div_r(r.p, A + A_DPX * P, A + A_DPY * P, g.nx, g.ny, x, y);
+    const T rR = sv[SV_RR * P + site], rB = sv[SV_RB * P + site];
+    const T rho = rR + rB;
+    const T ux = sv[SV_UX * P + site], uy = sv[SV_UY * P + site];
+    const T K = sv[SV_K * P + site];
+    const T gx = sv[SV_GNX * P + site], gy = sv[SV_GNY * P + site];
+    // Phi' = c06R rR + phiB rB - rho / 3
+    T lrR = A[A_RR * P + site] + (c.c06R - T(1.0 / 3.0)) * lphi;
+    T lrB = A[A_RB * P + site] + (c.phiB - T(1.0 / 3.0)) * lphi;
+    // u = (j + G/2) / rho
+    const T irho = T(1) / rho;
+    const T ljx = lux * irho, ljy = luy * irho;
+    const T lrho = -(lux * ux + luy * uy) * irho;
+    lrR += lrho;
+    lrB += lrho;
+    const T lGx = A[A_GX * P + site] + T(0.5) * ljx;
+    const T lGy = A[A_GY * P + site] + T(0.5) * ljy;
+    // G = sigma K g / 2 + G_ext
+    if (dforce) {
+      dforce[site] += lGx;
+      dforce[P + site] += lGy;
+    }
+    const T lGg = lGx * gx + lGy * gy;
+    acc = 0.5 * (double)K * (double)lGg;
+    T* b = B + site;
+    b[B_RR * P] = lrR;
+    b[B_RB * P] = lrB;
+    b[B_JX * P] = ljx;
+    b[B_JY * P] = ljy;
+    b[B_K * P] = c.fixed_K ? T(0) : T(0.5) * sigma * lGg;
+    b[B_GX * P] = T(0.5) * sigma * K * lGx;
+    b[B_GY * P] = T(0.5) * sigma * K * lGy;
+  }
+  const double tot = block_sum(acc);
+  if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+}
+
+static __global__ void __launch_bounds__(256) sum_into_kernel(const double* __restrict__ part, int n, double* out) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+  const double tot = block_sum(v);
+  if (threadIdx.x == 0) *out += tot;
+}
+
+// ---------------------------------------------------------------------------
+// pass 3: K = -div m transposed; m = g / sqrt(|g|^2 + eps^2)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii r, const T* __restrict__ sv,
+                                                       const T* __restrict__ A, const T* __restrict__ B,
+                                                       T* __restrict__ C) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= g.nx) return;
+  const int P = g.plane, site = y * g.nx + x;
+  T kx, ky;
+  grad_r(r.k, B + B_K * P, g.nx, g.ny, x, y, kx, ky);
+  const T lmx = A[A_MX * P + site] + kx;  // -(-D)^T = D
+  const T lmy = A[A_MY * P + site] + ky;
+  const T gx = sv[SV_GNX * P + site], gy = sv[SV_GNY * P + site];
+  const T s2 = gx * gx + gy * gy + c.eps2;
+  const T is = T(1) / sqrt(s2);
+  const T dot = (lmx * gx + lmy * gy) * is * is * is;
+  C[C_GX * P + site] = B[B_GX * P + site] + lmx * is - gx * dot;
+  C[C_GY * P + site] = B[B_GY * P + site] + lmy * is - gy * dot;
+}
+
+// ---------------------------------------------------------------------------
+// pass 4: grad rho^N transposed; colour index
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) colour_kernel(Geom g, Coef<T> c, Radii r, const T* __restrict__ sv,
+                                                     const T* __restrict__ A, const T* __restrict__ B,
+                                                     const T* __restrict__ C, T* __restrict__ D) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= g.nx) return;
+  const int P = g.plane, site = y * g.nx + x;
+  const T lrN = A[A_RN * P + site] - div_r(r.g, C + C_GX * P, C + C_GY * P, g.nx, g.ny, x, y);
+  const T a = sv[SV_RR * P + site] * c.inv_rho0R, b = sv[SV_RB * P + site] * c.inv_rho0B;
+  const T is = T(1) / (a + b);
+  const T w = T(2) * lrN * is * is;
+  D[D_RR * P + site] = B[B_RR * P + site] + w * b * c.inv_rho0R;
+  D[D_RB * P + site] = B[B_RB * P + site] - w * a * c.inv_rho0B;
+}
+
+// ---------------------------------------------------------------------------
+// pass 5: pre-collision adjoints and the transposed pull gather:
+// lambda_t[C][i](s) = dL/dC_i(s + c_i), dL/dC_i = lambda_f_i + lambda_rho_C + lambda_j . c_i
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) push_kernel(Geom g, const T* __restrict__ A, const T* __restrict__ B,
+                                                   const T* __restrict__ D, T* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= g.nx) return;
+  const int P = g.plane, site = y * g.nx + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cx = link_cx(i), cy = link_cy(i);
+    int xs = x + cx, ys = y + cy;
+    xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+    ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+    const int r = ys * g.nx + xs;
+    const T common = A[(A_F + i) * P + r] + T(cx) * B[B_JX * P + r] + T(cy) * B[B_JY * P + r];
+    out[i * P + site] = common + D[D_RR * P + r];
+    out[(9 + i) * P + site] = common + D[D_RB * P + r];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the colour-index field of the pre-collision state:
+// lambda[C][i](s) = dL/drho^N(s + c_i) * drho^N/drho_C(s + c_i)
+// ---------------------------------------------------------------------------
+template <typename S>
+__global__ void __launch_bounds__(256) rhoN_adjoint_kernel(const void* popsv, Geom g, Coef<typename S::math> c,
+                                                           const typename S::math* __restrict__ lrN,
+                                                           typename S::math* __restrict__ out) {
+  using T = typename S::math;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= g.nx) return;
+  const int P = g.plane;
+  const int E = (int)sizeof(typename S::W);
+  // every site needs rho_R, rho_B of its 9 neighbours r = s + c_i
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int xs = x + link_cx(i), ys = y + link_cy(i);
+    xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+    ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+    Cols cols;
+    cols.o = xs * E;
+    cols.m = (xs == 0 ? g.nx - 1 : xs - 1) * E;
+    cols.p = (xs == g.nx - 1 ? 0 : xs + 1) * E;
+    typename S::W w[S::NW];
+    gather_words<S, false>(make_rsrc<S>(popsv, g.plane), g, ys, cols, w);
+    T R[9], B[9];
+    decode<S>(w, c, R, B);
+    T rR = T(0), rB = T(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      rR += R[k];
+      rB += B[k];
+    }
+    const T a = rR * c.inv_rho0R, b = rB * c.inv_rho0B;
+    const T is = T(1) / (a + b);
+    const T wgt = T(2) * lrN[ys * g.nx + xs] * is * is;
+    out[i * P + y * g.nx + x] = wgt * b * c.inv_rho0R;
+    out[(9 + i) * P + y * g.nx + x] = -wgt * a * c.inv_rho0B;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint of the initial state (rest state of rho^N_0, written un-streamed):
+// dL/drho^N_0(r) = sum_{C,i} lambda_0[C][i](r - c_i) d(rho_C phi_i)(r)/drho^N_0
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256) init_adjoint_kernel(const T* __restrict__ rhoN0, const T* __restrict__ lam0,
+                                                           Geom g, Coef<T> c, T rho0R, T rho0B,
+                                                           T* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= g.nx) return;
+  const int P = g.plane, site = y * g.nx + x;
+  const T rn = rhoN0[site];
+  const T rR = rho0R * (T(1) + rn) * T(0.5), rB = rho0B * (T(1) - rn) * T(0.5);
+  const T dR = rho0R * T(0.5), dB = -rho0B * T(0.5);
+  const T rho = rR + rB, drho = dR + dB;
+  const T irho = T(1) / rho;
+  const T a0 = c.alphaR * rR + c.alphaB * rB, da0 = c.alphaR * dR + c.alphaB * dB;
+  const T mv = c.c1R * rR + c.c1B * rB, dmv = c.c1R * dR + c.c1B * dB;
+  T acc = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int xs = x - link_cx(i), ys = y - link_cy(i);
+    xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+    ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+    const int s = ys * g.nx + xs;
+    T phi, dphi;
+    if (i == 0) {
+      phi = a0 * irho;
+      dphi = (da0 - phi * drho) * irho;
+    } else {
+      const T wt = (i & 1) ? T(1.8 / 36.0) : T(1.8 / 9.0);
+      phi = wt * mv * irho;
+      dphi = wt * (dmv - mv * irho * drho) * irho;
+    }
+    acc += lam0[i * P + s] * (dR * phi + rR * dphi) + lam0[(9 + i) * P + s] * (dB * phi + rB * dphi);
+  }
+  out[site] += acc;
+}
+
+}  // namespace adj
+}  // namespace chromo

@@ -10,6 +10,7 @@
 #include <string>
 
 #include "chromo_lbm.h"
+#include "chromo_adjoint.hpp"
 #include "chromo_host.hpp"
 
 namespace {
@@ -92,14 +93,14 @@ int validate(const lbm_params* p) {
 // a single wave of workgroups (one workgroup fills a CU: its 8 wavefronts use
 // the whole register file), i.e. nstrips * nchunks <= number of CUs, with
 // chunks no shorter than 24 rows.
-chromo::Geom plan(const lbm_params& p, int ncu) {
+chromo::Geom plan(const lbm_params& p, int ncu, int ntx) {
   chromo::Geom g;
   g.nx = p.nx;
   g.ny = p.ny;
   g.walls = p.walls_y;
   g.F = p.walls_y ? p.ny - 2 : p.ny;
   g.plane = p.nx * p.ny;
-  const int txmax = chromo::ntx_for(p.storage) - 2 * halo(p);
+  const int txmax = ntx - 2 * halo(p);
   g.nstrips = (p.nx + txmax - 1) / txmax;
   g.TX = (p.nx + g.nstrips - 1) / g.nstrips;
   int nch = ncu / g.nstrips;
@@ -122,7 +123,8 @@ struct lbm_handle {
   size_t ws_bytes;
   const void* force;
   int64_t steps;
-  chromo::Geom g;
+  chromo::Geom g;      // forward step kernel
+  chromo::Geom g_adj;  // adjoint pass 1 (workgroup shape ntx_for(storage, true))
   const chromo::Ops* ops;
 };
 
@@ -202,7 +204,8 @@ int lbm_init(const lbm_params* p, const void* rhoN0, const void* force, void* po
   h->ws_bytes = ws_bytes;
   h->force = force;
   h->steps = 0;
-  h->g = plan(*p, ncu > 0 ? ncu : 1);
+  h->g = plan(*p, ncu > 0 ? ncu : 1, chromo::ntx_for(p->storage));
+  h->g_adj = plan(*p, ncu > 0 ? ncu : 1, chromo::ntx_for(p->storage, true));
   h->ops = ops_of(p->storage);
 
   hipError_t e = h->ops->init(*p, h->g, rhoN0, pops_a, stream);
@@ -249,15 +252,60 @@ int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream) {
   return LBM_OK;
 }
 
-int lbm_adjoint_step(lbm_handle* h, const void* pops_t, void* adj_pops, double* dL_dsigma_dev,
-                     void* dL_dforce_dev, hipStream_t stream) {
-  (void)h;
-  (void)pops_t;
-  (void)adj_pops;
-  (void)dL_dsigma_dev;
-  (void)dL_dforce_dev;
-  (void)stream;
-  return fail(LBM_ENOTIMPL, "lbm_adjoint_step is not provided by this build");
+size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
+  if (validate(p) != LBM_OK) return 0;
+  if (p->walls_y || !ops_of(p->storage)->adjoint) return 0;
+  const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
+  size_t bytes = (size_t)chromo::adj::WS_PLANES * (size_t)p->nx * (size_t)p->ny * elem;
+  bytes = (bytes + 255) / 256 * 256;
+  return bytes + (size_t)chromo::adj::red_blocks(p->nx, p->ny) * sizeof(double);
+}
+
+static int adjoint_supported(const lbm_handle* h) {
+  if (!h->ops->adjoint) return fail(LBM_ENOTIMPL, "the adjoint is provided for F64 and F32 storage only");
+  if (h->p.walls_y) return fail(LBM_ENOTIMPL, "the adjoint is provided for periodic lattices only");
+  if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no adjoint of the streaming-only test mode");
+  return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_handle* h, const void* pops_t, const void* adj_next, void* adj_out, void* workspace,
+                     size_t ws_bytes, double* dL_dsigma_dev, void* dL_dforce_dev, hipStream_t stream) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  int st = adjoint_supported(h);
+  if (st != LBM_OK) return st;
+  if (!pops_t || !adj_next || !adj_out || !workspace)
+    return fail(LBM_EINVAL, "pops_t, adj_next, adj_out and workspace must be non-NULL");
+  if (adj_next == adj_out) return fail(LBM_EINVAL, "adj_next and adj_out must differ");
+  if (ws_bytes < lbm_adjoint_workspace_bytes(&h->p))
+    return fail(LBM_EINVAL, "adjoint workspace too small: %zu < %zu", ws_bytes, lbm_adjoint_workspace_bytes(&h->p));
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
+  hipError_t e = h->ops->adjoint(h->p, h->g_adj, pops_t, h->force, adj_next, adj_out, workspace, dL_dsigma_dev,
+                                 dL_dforce_dev, stream);
+  if (e != hipSuccess) return fail(LBM_EHIP, "adjoint launch: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int lbm_rhoN_adjoint(lbm_handle* h, const void* pops, const void* dL_drhoN, void* adj_out, hipStream_t stream) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  int st = adjoint_supported(h);
+  if (st != LBM_OK) return st;
+  if (!pops || !dL_drhoN || !adj_out) return fail(LBM_EINVAL, "pops, dL_drhoN and adj_out must be non-NULL");
+  hipError_t e = h->ops->rhoN_adjoint(h->p, h->g, pops, dL_drhoN, adj_out, stream);
+  if (e != hipSuccess) return fail(LBM_EHIP, "rhoN adjoint launch: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, void* dL_drhoN0, hipStream_t stream) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  int st = adjoint_supported(h);
+  if (st != LBM_OK) return st;
+  if (!rhoN0 || !adj_pops0 || !dL_drhoN0) return fail(LBM_EINVAL, "rhoN0, adj_pops0 and dL_drhoN0 must be non-NULL");
+  hipError_t e = h->ops->init_adjoint(h->p, h->g, rhoN0, adj_pops0, dL_drhoN0, stream);
+  if (e != hipSuccess) return fail(LBM_EHIP, "init adjoint launch: %s", hipGetErrorString(e));
+  return LBM_OK;
 }
 
 int lbm_current_pops(const lbm_handle* h) { return h ? h->live : -1; }

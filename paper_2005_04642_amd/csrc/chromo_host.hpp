@@ -20,8 +20,13 @@ constexpr int NTX_F32 = 192;  // every format with FP32 arithmetic
 constexpr int NR_F32 = 4;
 constexpr int NTX_F64 = 64;   // double (validation format)
 constexpr int NR_F64 = 4;
+// The adjoint's first pass (the step kernel in MODE_ADJ) holds the forward
+// and backward values of a site at once: 512 threads leave 256 VGPRs.
+constexpr int NTX_ADJ_F32 = 128;
 
-inline int ntx_for(int storage) { return storage == LBM_STORAGE_F64 ? NTX_F64 : NTX_F32; }
+inline int ntx_for(int storage, bool adjoint = false) {
+  return storage == LBM_STORAGE_F64 ? NTX_F64 : (adjoint ? NTX_ADJ_F32 : NTX_F32);
+}
 
 // Launchers of one storage format.  Pointers are device pointers in that
 // format (populations) or in its arithmetic type (fields, rho^N, force).
@@ -34,6 +39,14 @@ struct Ops {
   hipError_t (*init)(const lbm_params& p, const Geom& g, const void* rhoN0, void* dst, hipStream_t s);
   hipError_t (*mass)(const lbm_params& p, const Geom& g, const void* pops, double* partial, double* out,
                      hipStream_t s);
+  // adjoint (periodic lattices; null for formats without it)
+  // g: geometry planned for the adjoint workgroup shape (ntx_for(storage, true))
+  hipError_t (*adjoint)(const lbm_params& p, const Geom& g, const void* pops, const void* force,
+                        const void* lam_next, void* lam_out, void* ws, double* dsigma, void* dforce, hipStream_t s);
+  hipError_t (*rhoN_adjoint)(const lbm_params& p, const Geom& g, const void* pops, const void* lrN, void* out,
+                             hipStream_t s);
+  hipError_t (*init_adjoint)(const lbm_params& p, const Geom& g, const void* rhoN0, const void* lam0, void* out,
+                             hipStream_t s);
   int words;        // words per site
   int word_bytes;   // bytes per word
   int math_bytes;   // bytes of the arithmetic type (fields, rho^N, force)

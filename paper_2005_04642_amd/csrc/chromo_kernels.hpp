@@ -86,9 +86,29 @@ struct StepArgs {
   T* out_ux;
   T* out_uy;
   T* out_rhoN;
+  // adjoint mode: dL/d(next state) at the own site ([18][ny][nx]), and the
+  // outputs: forward intermediates (planes SV_*) and local adjoints (planes
+  // adj::A_*), each [ny][nx]
+  const T* lam_next;
+  T* out_save;
+  T* out_adj;
   Geom g;
   Coef<T> c;
 };
+
+// Launch modes of the step kernel: advance one step, write the macroscopic
+// fields, or run the first (local) pass of the adjoint.
+enum { MODE_STEP = 0, MODE_FIELDS = 1, MODE_ADJ = 3 };
+
+// Forward intermediates the later adjoint passes read.
+enum { SV_RR, SV_RB, SV_UX, SV_UY, SV_K, SV_GNX, SV_GNY, SV_N };
+
+namespace adj {
+constexpr int A_N = 21;  // local adjoints per site (see chromo_adjoint.hpp)
+template <typename T>
+__device__ void local_backward(const Coef<T>& c, const T* f, T rR, T rB, T ux, T uy, T Gx, T Gy, T dPx, T dPy,
+                               T theta, T rhoN, T mx, T my, const T* lR, const T* lB, T* out);
+}  // namespace adj
 
 // ---------------------------------------------------------------------------
 // Lattice links (same order as the public header): c0 = (0,0), c1 = (1,1),
@@ -442,18 +462,37 @@ __device__ __forceinline__ float rsqrt_pos(float x) {
 __device__ __forceinline__ double rsqrt_pos(double x) { return 1.0 / sqrt(x); }
 
 // Collision, recolour and store of one site (band O).
-template <typename S, typename T, bool FIELDS>
+template <typename S, typename T, int MODE>
 __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buffer_rsrc_t dst, const T* f, T rR,
                                               T rB, T ux, T uy, T Gx, T Gy, T inv_rho, T dPx, T dPy, T theta,
                                               T rhoN, T mx, T my, int p, const Thread& t) {
   const Coef<T>& c = a.c;
   const T rho = rR + rB;
-  if (FIELDS) {
+  if (MODE == MODE_FIELDS) {
     const int site = p * a.g.nx + t.xg;
     if (a.out_rho) a.out_rho[site] = rho;
     if (a.out_ux) a.out_ux[site] = ux;
     if (a.out_uy) a.out_uy[site] = uy;
     if (a.out_rhoN) a.out_rhoN[site] = rhoN;
+    return;
+  }
+  if (MODE == MODE_ADJ) {
+    const int P = a.g.plane;
+    const int site = p * a.g.nx + t.xg;
+    T lR[9], lB[9], out[adj::A_N];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      lR[i] = a.lam_next[i * P + site];
+      lB[i] = a.lam_next[(9 + i) * P + site];
+    }
+    adj::local_backward(c, f, rR, rB, ux, uy, Gx, Gy, dPx, dPy, theta, rhoN, mx, my, lR, lB, out);
+#pragma unroll
+    for (int q = 0; q < adj::A_N; ++q) a.out_adj[q * P + site] = out[q];
+    T* sv = a.out_save + site;
+    sv[SV_RR * P] = rR;
+    sv[SV_RB * P] = rB;
+    sv[SV_UX * P] = ux;
+    sv[SV_UY * P] = uy;
     return;
   }
   // modes of f (App. A projectors), summed with antisymmetric pair differences
@@ -544,7 +583,7 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
 
 // One march iteration; S = it mod 4 selects the register-ring slots.  tM and
 // tU track the virtual rows of the next band-M gather and of band U.
-template <int S, typename ST, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, bool FIELDS>
+template <int S, typename ST, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE>
 __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgpu_buffer_rsrc_t src,
                                            __amdgpu_buffer_rsrc_t dst, Smem<T, NTX, Pipe<NR>::RING>& sm,
                                            March<ST>& st, const Thread& t, RowTrack<WALLS>& tM,
@@ -614,6 +653,10 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
       } else {
         K = -ring_div<RK, RING, NTX>(sm.mx, sm.my, rowU, tx);  // K = div n, n = -m
       }
+      if (MODE == MODE_ADJ) {
+        const int v = base + PP::LU;  // virtual row of band U
+        if (t.own && v >= t.ya && v < t.yb) a.out_save[SV_K * g.plane + p * g.nx + t.xg] = K;
+      }
       const T gnx = sm.gnx[ru][tx], gny = sm.gny[ru][tx];
       T Gx = c.half_sigma * K * gnx + c.gx;
       T Gy = c.half_sigma * K * gny + (refl ? -c.gy : c.gy);
@@ -645,13 +688,18 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
     __builtin_amdgcn_sched_barrier(0);
     const int ro = ring_row<RING>(rowO);
     const int p = WALLS ? base + 1 : base;
-    collide_store<ST, T, FIELDS>(a, dst, st.rf[sO], sm.rR[ro][tx], sm.rB[ro][tx], sm.ux[ro][tx], sm.uy[ro][tx],
+    if (MODE == MODE_ADJ) {
+      T* sv = a.out_save + p * g.nx + t.xg;
+      sv[SV_GNX * g.plane] = sm.gnx[ro][tx];
+      sv[SV_GNY * g.plane] = sm.gny[ro][tx];
+    }
+    collide_store<ST, T, MODE>(a, dst, st.rf[sO], sm.rR[ro][tx], sm.rB[ro][tx], sm.ux[ro][tx], sm.uy[ro][tx],
                                  sm.Gx[ro][tx], sm.Gy[ro][tx], sm.irho[ro][tx], dPx, dPy, theta,
                                  sm.rhoN[ro][tx], sm.mx[ro][tx], sm.my[ro][tx], p, t);
   }
 }
 
-template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, bool FIELDS>
+template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE>
 __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typename ST::math> a) {
   using T = typename ST::math;
   using PP = Pipe<NR>;
@@ -668,7 +716,7 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typen
   const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (tile >= ntiles) return;
   const __amdgpu_buffer_rsrc_t src = make_rsrc<ST>(a.src, g.plane);
-  const __amdgpu_buffer_rsrc_t dst = make_rsrc<ST>(FIELDS ? a.src : a.dst, g.plane);
+  const __amdgpu_buffer_rsrc_t dst = make_rsrc<ST>(MODE != MODE_STEP ? a.src : a.dst, g.plane);
   Thread t;
   t.tx = threadIdx.x % NTX;
   t.ty = __builtin_amdgcn_readfirstlane(threadIdx.x / NTX);
@@ -697,13 +745,13 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typen
   tM.advance(g);
   tU.init(v0 + PP::LU, g);
   for (int it = 0; it < t.nit; it += 4) {
-    march_iter<0, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, FIELDS>(it, a, src, dst, sm, st, t, tM, tU);
+    march_iter<0, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it, a, src, dst, sm, st, t, tM, tU);
     if (it + 1 < t.nit)
-      march_iter<1, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, FIELDS>(it + 1, a, src, dst, sm, st, t, tM, tU);
+      march_iter<1, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it + 1, a, src, dst, sm, st, t, tM, tU);
     if (it + 2 < t.nit)
-      march_iter<2, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, FIELDS>(it + 2, a, src, dst, sm, st, t, tM, tU);
+      march_iter<2, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it + 2, a, src, dst, sm, st, t, tM, tU);
     if (it + 3 < t.nit)
-      march_iter<3, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, FIELDS>(it + 3, a, src, dst, sm, st, t, tM, tU);
+      march_iter<3, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it + 3, a, src, dst, sm, st, t, tM, tU);
   }
 }
 

@@ -3,15 +3,17 @@
 // the formats compile as separate translation units.
 #pragma once
 
+#include "chromo_adjoint.hpp"
 #include "chromo_host.hpp"
 
 namespace chromo {
 namespace launch {
 
-template <typename S>
+template <typename S, int MODE = MODE_STEP>
 struct Shape {
-  static constexpr int ntx = sizeof(typename S::math) == 8 ? NTX_F64 : NTX_F32;
-  static constexpr int nr = sizeof(typename S::math) == 8 ? NR_F64 : NR_F32;
+  static constexpr bool f64 = sizeof(typename S::math) == 8;
+  static constexpr int ntx = f64 ? NTX_F64 : (MODE == MODE_ADJ ? NTX_ADJ_F32 : NTX_F32);
+  static constexpr int nr = f64 ? NR_F64 : NR_F32;
 };
 
 // Per-site constants of the scheme (Sec. II, App. A) in the arithmetic type.
@@ -69,27 +71,31 @@ Geom geom_for(const Geom& g0) {
   return g;
 }
 
-template <typename S, int RG, int RK, int RP, int RU, bool FIELDS>
+template <typename S, int RG, int RK, int RP, int RU, int MODE>
 hipError_t march(const StepArgs<typename S::math>& a, hipStream_t s) {
-  constexpr int NTX = Shape<S>::ntx, NR = Shape<S>::nr;
+  constexpr int NTX = Shape<S, MODE>::ntx, NR = Shape<S, MODE>::nr;
   const int ntiles = a.g.nstrips * a.g.nchunks;
   const int nblocks = 8 * ((ntiles + 7) / 8);  // whole rounds over the 8 XCDs (see the kernel)
-  if (a.g.walls) {
-    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, true, FIELDS>), dim3(nblocks),
+  if constexpr (MODE == MODE_ADJ) {  // the adjoint supports periodic lattices only
+    if (a.g.walls) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, false, MODE>), dim3(nblocks),
+                       dim3(NTX * NR), 0, s, a);
+  } else if (a.g.walls) {
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, true, MODE>), dim3(nblocks),
                        dim3(NTX * NR), 0, s, a);
   } else {
-    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, false, FIELDS>), dim3(nblocks),
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, false, MODE>), dim3(nblocks),
                        dim3(NTX * NR), 0, s, a);
   }
   return hipGetLastError();
 }
 
-template <typename S, bool FIELDS>
+template <typename S, int MODE>
 hipError_t dispatch_radii(const StepArgs<typename S::math>& a, const int* r, hipStream_t s) {
   const int code = (r[0] == 3) * 8 + (r[1] == 3) * 4 + (r[2] == 3) * 2 + (r[3] == 3);
 #define CHROMO_CASE(C, A, B, P, U) \
   case C:                          \
-    return march<S, A, B, P, U, FIELDS>(a, s);
+    return march<S, A, B, P, U, MODE>(a, s);
   switch (code) {
     CHROMO_CASE(0, 1, 1, 1, 1)
     CHROMO_CASE(1, 1, 1, 1, 3)
@@ -119,7 +125,8 @@ StepArgs<typename S::math> args(const lbm_params& p, const Geom& g, const void* 
   a.src = src;
   a.dst = dst;
   a.force = static_cast<const T*>(force);
-  a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = nullptr;
+  a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = a.out_save = a.out_adj = nullptr;
+  a.lam_next = nullptr;
   a.g = geom_for<S>(g);
   a.c = make_coef<S>(p);
   return a;
@@ -127,7 +134,7 @@ StepArgs<typename S::math> args(const lbm_params& p, const Geom& g, const void* 
 
 template <typename S>
 hipError_t step(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force, hipStream_t s) {
-  return dispatch_radii<S, false>(args<S>(p, g, src, dst, force), p.stencil, s);
+  return dispatch_radii<S, MODE_STEP>(args<S>(p, g, src, dst, force), p.stencil, s);
 }
 
 template <typename S>
@@ -139,7 +146,7 @@ hipError_t fields(const lbm_params& p, const Geom& g, const void* src, const voi
   a.out_ux = static_cast<T*>(ux);
   a.out_uy = static_cast<T*>(uy);
   a.out_rhoN = static_cast<T*>(rhoN);
-  hipError_t e = dispatch_radii<S, true>(a, p.stencil, s);
+  hipError_t e = dispatch_radii<S, MODE_FIELDS>(a, p.stencil, s);
   if (e != hipSuccess || !g.walls) return e;
   hipLaunchKernelGGL(fill_rows_kernel<T>, dim3((g.nx + 255) / 256), dim3(256), 0, s, a.out_rho, a.out_ux, a.out_uy,
                      a.out_rhoN, g.nx, 0, g.ny - 1);
@@ -171,6 +178,67 @@ hipError_t mass(const lbm_params& p, const Geom& g, const void* pops, double* pa
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// adjoint: save pass of the step kernel, then the five passes of
+// chromo_adjoint.hpp.  ws holds adj::WS_PLANES planes of the arithmetic type
+// followed, at the next multiple of 256 bytes, by adj::red_blocks() doubles.
+// ---------------------------------------------------------------------------
+template <typename S>
+hipError_t adjoint(const lbm_params& p, const Geom& g0, const void* pops, const void* force, const void* lam_next,
+                   void* lam_out, void* ws, double* dsigma, void* dforce, hipStream_t s) {
+  using T = typename S::math;
+  StepArgs<T> a = args<S>(p, g0, pops, nullptr, force);
+  const Geom& g = a.g;
+  T* sv = static_cast<T*>(ws);
+  T* A = sv + (size_t)SV_N * g.plane;
+  T* B = A + (size_t)adj::A_N * g.plane;
+  T* C = B + (size_t)adj::B_N * g.plane;
+  T* D = C + (size_t)adj::C_N * g.plane;
+  const size_t plane_bytes = ((size_t)adj::WS_PLANES * g.plane * sizeof(T) + 255) / 256 * 256;
+  double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + plane_bytes);
+  a.out_save = sv;
+  a.out_adj = A;
+  a.lam_next = static_cast<const T*>(lam_next);
+  hipError_t e = dispatch_radii<S, MODE_ADJ>(a, p.stencil, s);
+  if (e != hipSuccess) return e;
+  const dim3 grid((g.nx + 255) / 256, g.ny);
+  const adj::Radii r = {p.stencil[0], p.stencil[1], p.stencil[2], p.stencil[3]};
+  hipLaunchKernelGGL(adj::force_kernel<T>, grid, dim3(256), 0, s, g, a.c, (T)p.sigma, r, (const T*)sv,
+                     (const T*)A, B, static_cast<T*>(dforce), part);
+  if (dsigma) hipLaunchKernelGGL(adj::sum_into_kernel, dim3(1), dim3(256), 0, s, (const double*)part,
+                                 adj::red_blocks(g.nx, g.ny), dsigma);
+  hipLaunchKernelGGL(adj::director_kernel<T>, grid, dim3(256), 0, s, g, a.c, r, (const T*)sv, (const T*)A,
+                     (const T*)B, C);
+  hipLaunchKernelGGL(adj::colour_kernel<T>, grid, dim3(256), 0, s, g, a.c, r, (const T*)sv, (const T*)A,
+                     (const T*)B, (const T*)C, D);
+  hipLaunchKernelGGL(adj::push_kernel<T>, grid, dim3(256), 0, s, g, (const T*)A, (const T*)B, (const T*)D,
+                     static_cast<T*>(lam_out));
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t rhoN_adjoint(const lbm_params& p, const Geom& g0, const void* pops, const void* lrN, void* out,
+                        hipStream_t s) {
+  using T = typename S::math;
+  const Geom g = geom_for<S>(g0);
+  const dim3 grid((g.nx + 255) / 256, g.ny);
+  hipLaunchKernelGGL(adj::rhoN_adjoint_kernel<S>, grid, dim3(256), 0, s, pops, g, make_coef<S>(p),
+                     static_cast<const T*>(lrN), static_cast<T*>(out));
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t init_adjoint(const lbm_params& p, const Geom& g0, const void* rhoN0, const void* lam0, void* out,
+                        hipStream_t s) {
+  using T = typename S::math;
+  const Geom g = geom_for<S>(g0);
+  const dim3 grid((g.nx + 255) / 256, g.ny);
+  hipLaunchKernelGGL(adj::init_adjoint_kernel<T>, grid, dim3(256), 0, s, static_cast<const T*>(rhoN0),
+                     static_cast<const T*>(lam0), g, make_coef<S>(p), (T)p.rho0_R, (T)p.rho0_B,
+                     static_cast<T*>(out));
+  return hipGetLastError();
+}
+
 template <typename S>
 Ops make_ops() {
   Ops o;
@@ -179,6 +247,15 @@ Ops make_ops() {
   o.stream_only = stream_only<S>;
   o.init = init<S>;
   o.mass = mass<S>;
+  if constexpr (is_ofs16<S>::value) {
+    o.adjoint = nullptr;
+    o.rhoN_adjoint = nullptr;
+    o.init_adjoint = nullptr;
+  } else {
+    o.adjoint = adjoint<S>;
+    o.rhoN_adjoint = rhoN_adjoint<S>;
+    o.init_adjoint = init_adjoint<S>;
+  }
   o.words = S::NW;
   o.word_bytes = (int)sizeof(typename S::W);
   o.math_bytes = (int)sizeof(typename S::math);

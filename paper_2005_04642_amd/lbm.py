@@ -23,9 +23,10 @@ WORDS_PER_SITE = {"f64": 18, "f32": 18, "f16": 10, "bf16": 10}
 LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR = 1, 2, 4
 
 # every symbol the header declares
-EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_workspace_bytes", "lbm_init", "lbm_step",
-            "lbm_fields", "lbm_masses_host", "lbm_adjoint_step", "lbm_current_pops", "lbm_step_count",
-            "lbm_destroy", "lbm_last_error")
+EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_workspace_bytes", "lbm_init",
+            "lbm_step", "lbm_fields", "lbm_masses_host", "lbm_adjoint_workspace_bytes", "lbm_adjoint_step",
+            "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_current_pops", "lbm_step_count", "lbm_destroy",
+            "lbm_last_error")
 
 
 class LbmError(RuntimeError):
@@ -77,8 +78,14 @@ def load_library(path=None):
     lib.lbm_fields.restype = ctypes.c_int
     lib.lbm_masses_host.argtypes = [vp, dp, vp]
     lib.lbm_masses_host.restype = ctypes.c_int
-    lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.lbm_adjoint_workspace_bytes.argtypes = [P]
+    lib.lbm_adjoint_workspace_bytes.restype = sz
+    lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp]
     lib.lbm_adjoint_step.restype = ctypes.c_int
+    lib.lbm_rhoN_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    lib.lbm_rhoN_adjoint.restype = ctypes.c_int
+    lib.lbm_init_adjoint.argtypes = [vp, vp, vp, vp, vp]
+    lib.lbm_init_adjoint.restype = ctypes.c_int
     lib.lbm_current_pops.argtypes = [vp]
     lib.lbm_current_pops.restype = ctypes.c_int
     lib.lbm_step_count.argtypes = [vp]
@@ -168,9 +175,24 @@ def lbm_masses_host(h, stream):
     return out[0], out[1]
 
 
-def lbm_adjoint_step(h, pops_t_ptr, adj_ptr, dsigma_ptr, dforce_ptr, stream):
+def lbm_adjoint_workspace_bytes(p):
+    return load_library().lbm_adjoint_workspace_bytes(ctypes.byref(p))
+
+
+def lbm_adjoint_step(h, pops_t_ptr, adj_next_ptr, adj_out_ptr, ws_ptr, ws_bytes, dsigma_ptr, dforce_ptr, stream):
     lib = load_library()
-    return _check(lib, lib.lbm_adjoint_step(h, pops_t_ptr, adj_ptr, dsigma_ptr, dforce_ptr, stream))
+    return _check(lib, lib.lbm_adjoint_step(h, pops_t_ptr, adj_next_ptr, adj_out_ptr, ws_ptr, ws_bytes, dsigma_ptr,
+                                            dforce_ptr, stream))
+
+
+def lbm_rhoN_adjoint(h, pops_ptr, dL_drhoN_ptr, adj_out_ptr, stream):
+    lib = load_library()
+    return _check(lib, lib.lbm_rhoN_adjoint(h, pops_ptr, dL_drhoN_ptr, adj_out_ptr, stream))
+
+
+def lbm_init_adjoint(h, rhoN0_ptr, adj0_ptr, dL_drhoN0_ptr, stream):
+    lib = load_library()
+    return _check(lib, lib.lbm_init_adjoint(h, rhoN0_ptr, adj0_ptr, dL_drhoN0_ptr, stream))
 
 
 def lbm_current_pops(h):
@@ -223,10 +245,12 @@ class Simulation:
         self.pops = [torch.empty(n, dtype=self.word_dtype, device=self.device) for _ in range(2)]
         wsb = lbm_workspace_bytes(self.params)
         self.ws = torch.zeros(wsb, dtype=torch.uint8, device=self.device)
-        self.rhoN0 = torch.as_tensor(np.asarray(rhoN0), dtype=self.dtype).to(self.device).contiguous()
-        self.force = None
-        if force is not None:
-            self.force = torch.as_tensor(np.asarray(force), dtype=self.dtype).to(self.device).contiguous()
+        def dev(a):
+            t = a if torch.is_tensor(a) else torch.as_tensor(np.asarray(a))
+            return t.to(device=self.device, dtype=self.dtype).contiguous()
+
+        self.rhoN0 = dev(rhoN0)
+        self.force = None if force is None else dev(force)
         self.mass = torch.zeros(2, dtype=torch.float64, device=self.device)
         self.h = lbm_init(self.params, self.rhoN0.data_ptr(),
                           None if self.force is None else self.force.data_ptr(),
@@ -250,6 +274,32 @@ class Simulation:
 
     def masses(self):
         return lbm_masses_host(self.h, self.stream())
+
+    # -- adjoint (F64/F32 storage, periodic lattices) ---------------------------
+    def adjoint_workspace(self):
+        """Device workspace of lbm_adjoint_step (allocated on first use)."""
+        if getattr(self, "_adj_ws", None) is None:
+            n = lbm_adjoint_workspace_bytes(self.params)
+            if n == 0:
+                raise LbmError(LBM_ENOTIMPL, "no adjoint for these parameters (needs F64/F32 storage, periodic y)")
+            self._adj_ws = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
+        return self._adj_ws
+
+    def adjoint_step(self, pops_t, adj_next, adj_out, dsigma=None, dforce=None):
+        """adj_out = dL/dpops_t given adj_next = dL/dpops_{t+1}; adds dL/dsigma
+        into dsigma (float64 device tensor of one element) and dL/dG_ext into
+        dforce ([2, ny, nx]) when given."""
+        ws = self.adjoint_workspace()
+        lbm_adjoint_step(self.h, pops_t.data_ptr(), adj_next.data_ptr(), adj_out.data_ptr(), ws.data_ptr(),
+                         ws.numel(), None if dsigma is None else dsigma.data_ptr(),
+                         None if dforce is None else dforce.data_ptr(), self.stream())
+
+    def rhoN_adjoint(self, pops, dL_drhoN, adj_out):
+        lbm_rhoN_adjoint(self.h, pops.data_ptr(), dL_drhoN.contiguous().data_ptr(), adj_out.data_ptr(),
+                         self.stream())
+
+    def init_adjoint(self, adj0, dL_drhoN0):
+        lbm_init_adjoint(self.h, self.rhoN0.data_ptr(), adj0.data_ptr(), dL_drhoN0.data_ptr(), self.stream())
 
     def live_words(self):
         """View [NW, ny, nx] of the live buffer (storage words, pull layout)."""

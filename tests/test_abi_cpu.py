@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "chromo_lbm.h")
 def declared_functions():
     src = open(HEADER).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(lbm_[A-Za-z_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -94,7 +94,19 @@ def test_init_argument_errors_before_any_gpu_call():
     assert code == lbm.LBM_EINVAL
 
 
-def test_adjoint_is_reported_not_implemented():
+def test_adjoint_availability_and_argument_errors():
+    """The adjoint exists for F64/F32 storage on periodic lattices; its
+    workspace size is 0 elsewhere, and NULL arguments fail before any GPU call."""
     lib = lbm.load_library()
-    assert lib.lbm_adjoint_step(None, None, None, None, None, None) == lbm.LBM_ENOTIMPL
-    assert "not provided" in lbm.lbm_last_error()
+    prm = Wk.base_params(Lambda=10.0)
+    for storage, walls, ok in (("f32", False, True), ("f64", False, True), ("f16", False, False),
+                               ("bf16", False, False), ("f32", True, False)):
+        p = lbm.make_params(64, 48, storage, **dict(prm, walls=walls))
+        n = lbm.lbm_adjoint_workspace_bytes(p)
+        assert (n > 0) == ok, (storage, walls)
+        if ok:
+            elem = 8 if storage == "f64" else 4
+            assert n >= 39 * 64 * 48 * elem
+    assert lib.lbm_adjoint_step(None, None, None, None, None, 0, None, None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_rhoN_adjoint(None, None, None, None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_init_adjoint(None, None, None, None, None) == lbm.LBM_EINVAL

@@ -1,0 +1,230 @@
+"""The hand-written adjoint of the step (lbm_adjoint_step and the checkpointed
+rollout built on it) against reverse-mode differentiation of the FP64 oracle
+(torch autograd through its own operations) and against finite differences.
+
+* one step, FP64: dL/dpops_t, dL/dsigma and dL/dG_ext for a random linear
+  functional of the next state, every stencil profile and option;
+* one step, FP32 against FP64 (the same state);
+* colour-index and initial-state adjoints against autograd;
+* multi-step rollout (32^2 drop): gradients with respect to sigma, the force
+  field and the initial colour index against central finite differences of the
+  GPU forward, and checkpointing leaves them unchanged.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import chromo as O
+from oracle.lattice import C
+from paper_2005_04642_amd import adjoint, lbm, workloads as Wk
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def torch_pull(S):
+    """Pre-collision populations of a periodic pull-layout buffer S [2, 9, ny, nx]:
+    C_i(r) = S_i(r - c_i)."""
+    return torch.stack([torch.roll(S[:, i], shifts=(C[i][1], C[i][0]), dims=(-2, -1)) for i in range(9)], dim=1)
+
+
+def state_and_params(nx, ny, seed, stencil=(3, 3, 3, 3), **extra):
+    params = Wk.base_params(Lambda=10.0, sigma=0.02, stencil=stencil)
+    params.update(gx=3e-5, gy=-2e-5, nu_B=0.4)
+    params.update(extra)
+    rng = np.random.default_rng(seed)
+    rn = np.clip(np.tanh(2.0 * rng.standard_normal((ny, nx))), -1, 1)
+    sim = lbm.Simulation(nx, ny, params, rn, storage="f64", device=DEV)
+    torch.cuda.synchronize()
+    S = sim.live_pops().cpu().numpy()
+    sim.close()
+    S = S * Wk.random_state_perturbation(S.shape, 0.05, seed + 1)
+    lam = rng.standard_normal(S.shape)
+    force = 1e-4 * rng.standard_normal((2, ny, nx))
+    return params, rn, S, lam, force
+
+
+def oracle_vjp(params, S, lam, force):
+    """Autograd of L = <lam, step(S)> through the oracle (FP64)."""
+    ny, nx = S.shape[-2:]
+    p = O.Params(nx=nx, ny=ny, **params)
+    S_t = torch.tensor(S, dtype=torch.float64, requires_grad=True)
+    sig = torch.tensor(float(params["sigma"]), dtype=torch.float64, requires_grad=True)
+    p.sigma = sig
+    F_t = None if force is None else torch.tensor(force, dtype=torch.float64, requires_grad=True)
+    P = torch_pull(S_t)
+    R, B = O.collide_and_recolour(P[0], P[1], p, force=F_t)
+    lam_t = torch.tensor(lam, dtype=torch.float64)
+    L = (R * lam_t[0]).sum() + (B * lam_t[1]).sum()
+    L.backward()
+    return S_t.grad.numpy(), float(sig.grad), None if F_t is None else F_t.grad.numpy()
+
+
+def gpu_vjp(params, rn, S, lam, force, storage="f64"):
+    ny, nx = S.shape[-2:]
+    sim = lbm.Simulation(nx, ny, params, rn, storage=storage, device=DEV, force=force)
+    T = sim.dtype
+    S_d = torch.tensor(S, dtype=T, device=DEV)
+    lam_d = torch.tensor(lam, dtype=T, device=DEV)
+    out = torch.empty_like(lam_d)
+    dsig = torch.zeros(1, dtype=torch.float64, device=DEV)
+    dforce = torch.zeros((2, ny, nx), dtype=T, device=DEV)
+    sim.adjoint_step(S_d, lam_d, out, dsig, dforce)
+    torch.cuda.synchronize()
+    res = out.double().cpu().numpy(), float(dsig.item()), dforce.double().cpu().numpy()
+    sim.close()
+    return res
+
+
+def rel(a, b):
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+STENCILS = [(3, 3, 3, 3), (1, 1, 1, 1), (3, 1, 3, 1), (1, 3, 1, 3)]
+
+
+@pytest.mark.parametrize("stencil", STENCILS)
+@pytest.mark.parametrize("shape", [(12, 10), (40, 33)])
+def test_adjoint_one_step_f64_matches_oracle_autograd(stencil, shape):
+    nx, ny = shape
+    params, rn, S, lam, force = state_and_params(nx, ny, seed=nx + ny, stencil=stencil)
+    gS, gsig, gF = oracle_vjp(params, S, lam, force)
+    aS, asig, aF = gpu_vjp(params, rn, S, lam, force)
+    e = (rel(aS, gS), abs(asig - gsig) / abs(gsig), rel(aF, gF))
+    print("adjoint f64 %s %s: pops %.2e sigma %.2e force %.2e" % (shape, stencil, *e))
+    assert e[0] < 1e-11 and e[1] < 1e-10 and e[2] < 1e-11
+
+
+@pytest.mark.parametrize("extra", [dict(ghost_eq=1), dict(fixed_K=0.05), dict(recolor=False)])
+def test_adjoint_one_step_options_f64(extra):
+    nx, ny = 24, 20
+    params, rn, S, lam, force = state_and_params(nx, ny, seed=5, **extra)
+    gS, gsig, gF = oracle_vjp(params, S, lam, force)
+    aS, asig, aF = gpu_vjp(params, rn, S, lam, force)
+    e = (rel(aS, gS), abs(asig - gsig) / max(abs(gsig), 1e-300), rel(aF, gF))
+    print("adjoint f64 %s: pops %.2e sigma %.2e force %.2e" % (extra, *e))
+    assert e[0] < 1e-11 and e[2] < 1e-11
+    assert e[1] < 1e-10 or abs(asig - gsig) < 1e-14
+
+
+def test_adjoint_one_step_f32_against_f64():
+    nx, ny = 40, 33
+    params, rn, S, lam, force = state_and_params(nx, ny, seed=9)
+    S32 = S.astype(np.float32).astype(np.float64)
+    a64 = gpu_vjp(params, rn, S32, lam, force, "f64")
+    a32 = gpu_vjp(params, rn, S32, lam, force, "f32")
+    e = (rel(a32[0], a64[0]), abs(a32[1] - a64[1]) / abs(a64[1]), rel(a32[2], a64[2]))
+    print("adjoint f32 vs f64: pops %.2e sigma %.2e force %.2e" % e)
+    assert e[0] < 1e-4 and e[1] < 1e-4 and e[2] < 1e-4
+
+
+def test_rhoN_and_init_adjoints_match_autograd():
+    nx, ny = 20, 16
+    params, rn, S, lam, force = state_and_params(nx, ny, seed=3)
+    rng = np.random.default_rng(4)
+    w = rng.standard_normal((ny, nx))
+    # colour index of the pre-collision state of S
+    S_t = torch.tensor(S, requires_grad=True)
+    P = torch_pull(S_t)
+    p = O.Params(nx=nx, ny=ny, **params)
+    rhoN = O.colour_index(P[0].sum(0), P[1].sum(0), p)
+    (rhoN * torch.tensor(w)).sum().backward()
+    sim = lbm.Simulation(nx, ny, params, rn, storage="f64", device=DEV)
+    out = torch.empty((2, 9, ny, nx), dtype=torch.float64, device=DEV)
+    sim.rhoN_adjoint(torch.tensor(S, device=DEV), torch.tensor(w, device=DEV), out)
+    torch.cuda.synchronize()
+    e1 = rel(out.cpu().numpy(), S_t.grad.numpy())
+    # initial rest state (un-streamed) as a function of rho^N_0
+    rn_t = torch.tensor(rn, requires_grad=True)
+    rhoR = p.rho0_R * (1.0 + rn_t) / 2.0
+    rhoB = p.rho0_B * (1.0 - rn_t) / 2.0
+    phi = O.rest_fractions(rhoR, rhoB, p)
+    pre = torch.stack([rhoR * phi, rhoB * phi])               # pre-collision at each site
+    buf = torch.stack([torch.roll(pre[:, i], shifts=(-C[i][1], -C[i][0]), dims=(-2, -1)) for i in range(9)], dim=1)
+    (buf * torch.tensor(lam)).sum().backward()
+    g0 = torch.zeros((ny, nx), dtype=torch.float64, device=DEV)
+    sim.init_adjoint(torch.tensor(lam, device=DEV), g0)
+    torch.cuda.synchronize()
+    e2 = rel(g0.cpu().numpy(), rn_t.grad.numpy())
+    sim.close()
+    print("rhoN adjoint %.2e, init adjoint %.2e" % (e1, e2))
+    assert e1 < 1e-12 and e2 < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# multi-step rollout: finite differences and checkpointing
+# ---------------------------------------------------------------------------
+
+def fd_case():
+    n, R, steps = 32, 8.0, 24
+    params = Wk.base_params(Lambda=10.0, sigma=0.01)
+    yy, xx = np.mgrid[0:n, 0:n]
+    d = np.hypot(xx - 15.5, yy - 15.5)
+    rn0 = np.tanh(0.8 * (R - d))
+    target = np.tanh(0.8 * (R - np.hypot((xx - 15.5) / 1.2, (yy - 15.5) * 1.2)))
+    rng = np.random.default_rng(2)
+    force = np.zeros((2, n, n))
+    for _ in range(3):
+        cx, cy = rng.uniform(0, n, 2)
+        ang = rng.uniform(0, 2 * np.pi)
+        bump = 1e-3 * np.exp(-((xx - cx) ** 2 + (yy - cy) ** 2) / (2 * 4.0 ** 2))
+        force[0] += bump * np.cos(ang)
+        force[1] += bump * np.sin(ang)
+    return n, steps, params, rn0, target, force
+
+
+def loss_of(rn0, sigma, force, params, steps, target, checkpoint=100):
+    out = adjoint.rollout(rn0, sigma, force, params, steps, checkpoint=checkpoint, storage="f64", device=DEV)
+    return ((out - target) ** 2).sum()
+
+
+def test_rollout_gradients_match_finite_differences():
+    n, steps, params, rn0, target, force = fd_case()
+    tgt = torch.tensor(target, device=DEV)
+    rn_t = torch.tensor(rn0, device=DEV, requires_grad=True)
+    sig_t = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
+    f_t = torch.tensor(force, device=DEV, requires_grad=True)
+    L = loss_of(rn_t, sig_t, f_t, params, steps, tgt, checkpoint=7)
+    L.backward()
+
+    def L_at(rn=rn0, sigma=0.01, frc=force):
+        with torch.no_grad():
+            return float(loss_of(torch.tensor(rn, device=DEV), sigma, torch.tensor(frc, device=DEV), params,
+                                 steps, tgt))
+
+    h = 1e-5
+    fd_sig = (L_at(sigma=0.01 + h) - L_at(sigma=0.01 - h)) / (2 * h)
+    e_sig = abs(float(sig_t.grad) - fd_sig) / abs(fd_sig)
+    errs = []
+    for (y, x) in [(15, 23), (8, 16), (20, 10)]:
+        hr = 1e-6
+        a = rn0.copy(); a[y, x] += hr
+        b = rn0.copy(); b[y, x] -= hr
+        fd = (L_at(rn=a) - L_at(rn=b)) / (2 * hr)
+        errs.append(abs(float(rn_t.grad[y, x]) - fd) / max(abs(fd), 1e-12))
+    for (c, y, x) in [(0, 15, 24), (1, 9, 15)]:
+        hf = 1e-5
+        a = force.copy(); a[c, y, x] += hf
+        b = force.copy(); b[c, y, x] -= hf
+        fd = (L_at(frc=a) - L_at(frc=b)) / (2 * hf)
+        errs.append(abs(float(f_t.grad[c, y, x]) - fd) / max(abs(fd), 1e-12))
+    print("rollout FD: sigma %.2e (grad %.6e fd %.6e); rhoN0/force %s" % (e_sig, float(sig_t.grad), fd_sig,
+                                                                          ["%.2e" % v for v in errs]))
+    assert e_sig < 1e-5
+    assert max(errs) < 1e-4
+
+
+def test_checkpointing_does_not_change_gradients():
+    n, steps, params, rn0, target, force = fd_case()
+    tgt = torch.tensor(target, device=DEV)
+    grads = []
+    for ck in (5, 100):
+        rn_t = torch.tensor(rn0, device=DEV, requires_grad=True)
+        sig_t = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
+        f_t = torch.tensor(force, device=DEV, requires_grad=True)
+        loss_of(rn_t, sig_t, f_t, params, steps, tgt, checkpoint=ck).backward()
+        grads.append((rn_t.grad.cpu().numpy(), float(sig_t.grad), f_t.grad.cpu().numpy()))
+    assert np.array_equal(grads[0][0], grads[1][0])
+    assert grads[0][1] == grads[1][1]
+    assert np.array_equal(grads[0][2], grads[1][2])
