@@ -7,8 +7,10 @@ Prints one JSON line: MLUPS of the whole step (all stages: gather, fields,
 stencils, force, collision, recolour, store) with the populations resident in
 HBM, the roofline of the step kernel (HBM bound: algorithmic bytes per lattice
 update = read + write of one site's population words: 144 B for FP32 storage,
-80 B for the 16-bit offset formats) and the CPU oracle timed on a bounded
-sample of the same workload.
+80 B for the 16-bit offset formats), the CPU oracle timed on a bounded
+sample of the same workload, and the adjoint: one lbm_adjoint_step against one
+forward step on the same lattice, and the gradient of an interface-shape loss
+over a checkpointed 512^2 rollout of 2000 steps (forward vs backward time).
 """
 import argparse
 import hashlib
@@ -97,6 +99,84 @@ def copy_roof(n, params, rn, torch, storage, steps=200):
             "GB_s": round(BYTES_PER_LU[storage] * n * n / (ms * 1e-3) / 1e9, 1)}
 
 
+def adjoint_measure(n, params, rn, torch, steps=20):
+    """Adjoint step (lbm_adjoint_step, FP32 storage, FP64 dL/dsigma) against the
+    forward step on the same lattice and state."""
+    from paper_2005_04642_amd import lbm
+    sim = lbm.Simulation(n, n, params, rn, storage="f32", device="cuda:0")
+    sim.step(20)
+    S = sim.live_pops().clone()
+    lam = torch.full_like(S, 1e-3)
+    out = torch.empty_like(S)
+    ds = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    df = torch.zeros((2, n, n), dtype=torch.float32, device="cuda:0")
+    sim.adjoint_step(S, lam, out, ds, df)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        sim.adjoint_step(S, lam, out, ds, df)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_adj = e0.elapsed_time(e1) / steps
+    e0.record()
+    sim.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1) / steps
+    sim.close()
+    return {"ms_forward": round(ms_fwd, 5), "ms_adjoint": round(ms_adj, 5),
+            "MLUPS_forward": round(n * n / ms_fwd / 1e3, 1), "MLUPS_adjoint": round(n * n / ms_adj / 1e3, 1),
+            "ratio": round(ms_fwd / ms_adj, 4)}
+
+
+def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
+    """Gradient of an interface-shape loss over a checkpointed rollout: 512^2
+    periodic, circle of radius 128 to a seeded ellipse target of equal area,
+    8 Gaussian force bumps (amplitude 1e-6); FP32 storage, FP64 dL/dsigma.
+    Returns forward and backward (recompute + adjoint) times."""
+    import numpy as np
+    from paper_2005_04642_amd import adjoint, workloads as Wk
+    rng = np.random.default_rng(2)
+    yy, xx = np.mgrid[0:n, 0:n]
+    c = (n - 1) / 2.0
+    rn0 = np.where(np.hypot(xx - c, yy - c) < n / 4, 1.0, -1.0)
+    ar = rng.uniform(1.0, 1.5)
+    ang = rng.uniform(0, np.pi)
+    xr = (xx - c) * np.cos(ang) + (yy - c) * np.sin(ang)
+    yr = -(xx - c) * np.sin(ang) + (yy - c) * np.cos(ang)
+    target = np.where(np.hypot(xr / np.sqrt(ar), yr * np.sqrt(ar)) < n / 4, 1.0, -1.0)
+    force = np.zeros((2, n, n))
+    for _ in range(8):
+        bx, by = rng.uniform(0, n, 2)
+        th = rng.uniform(0, 2 * np.pi)
+        bump = 1e-6 * np.exp(-((xx - bx) ** 2 + (yy - by) ** 2) / (2 * 24.0 ** 2))
+        force[0] += bump * np.cos(th)
+        force[1] += bump * np.sin(th)
+    params = Wk.base_params(Lambda=10.0, sigma=0.01)
+    dev = "cuda:0"
+    rn_t = torch.tensor(rn0, dtype=torch.float32, device=dev, requires_grad=True)
+    f_t = torch.tensor(force, dtype=torch.float32, device=dev, requires_grad=True)
+    sig = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
+    tgt = torch.tensor(target, dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    out = adjoint.rollout(rn_t, sig, f_t, params, steps, checkpoint=checkpoint, storage="f32", device=dev)
+    loss = ((out - tgt) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.time()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.time()
+    lups = n * n * steps
+    return {"workload": "%d^2 periodic drop R=%d to an ellipse target, %d steps, checkpoint every %d, FP32"
+                        % (n, n // 4, steps, checkpoint),
+            "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
+            "MLUPS_forward": round(lups / (t1 - t0) / 1e6, 1), "MLUPS_backward": round(lups / (t2 - t1) / 1e6, 1),
+            "ratio": round((t1 - t0) / (t2 - t1), 4), "loss": float(loss.detach()), "dL_dsigma": float(sig.grad)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +188,7 @@ def main():
                     help="population storage: FP32, or the 16-bit offset formats (FP32 arithmetic)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy-roof", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one plain 1 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -182,6 +263,10 @@ def main():
     if not args.no_copy_roof:
         out["copy_roof"] = copy_roof(n, params, rn, torch, args.storage)
         out["roofline"]["frac_of_copy"] = round(achieved / out["copy_roof"]["GB_s"], 4)
+    if not args.no_adjoint:
+        out["adjoint"] = dict({"workload": "same lattice and state, one adjoint step vs one forward step, FP32"},
+                              **adjoint_measure(n, params, rn, torch))
+        out["adjoint_rollout"] = adjoint_rollout(torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -26,10 +26,9 @@ class _Rollout(torch.autograd.Function):
         sim = lbm.Simulation(nx, ny, p, rhoN0.detach(), storage=storage, device=device,
                              force=None if force is None else force.detach())
         ckpts = {}
-        for t in range(nsteps):
-            if t % checkpoint == 0:
-                ckpts[t] = sim.live_pops().clone()
-            sim.step(1)
+        for t in range(0, nsteps, checkpoint):
+            ckpts[t] = sim.live_pops().clone()
+            sim.step(min(checkpoint, nsteps - t))
         out = sim.fields()["rhoN"]
         ctx.sim = sim
         ctx.ckpts = ckpts
