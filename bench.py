@@ -9,8 +9,9 @@ HBM, the roofline of the step kernel (HBM bound: algorithmic bytes per lattice
 update = read + write of one site's population words: 144 B for FP32 storage,
 80 B for the 16-bit offset formats), the CPU oracle timed on a bounded
 sample of the same workload, and the adjoint: one lbm_adjoint_step against one
-forward step on the same lattice, and the gradient of an interface-shape loss
-over a checkpointed 512^2 rollout of 2000 steps (forward vs backward time).
+forward step on the same lattice, the gradient of an interface-shape loss
+over a checkpointed 512^2 rollout of 2000 steps (forward vs backward time), and
+a batch of 256 uneven lattices in one launch per step.
 """
 import argparse
 import hashlib
@@ -177,6 +178,52 @@ def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
             "ratio": round((t1 - t0) / (t2 - t1), 4), "loss": float(loss.detach()), "dL_dsigma": float(sig.grad)}
 
 
+def batch_measure(torch, nsim=256, steps=20):
+    """256 independent periodic drops of uneven size (64..512) stepped by one
+    launch per step, after the autotuner picked the tile shape; against the same
+    lattices stepped one launch per lattice."""
+    from paper_2005_04642_amd import lbm, workloads as Wk
+    lats = Wk.config_batch(nsim=nsim, seed=1)
+    sites = sum(nx * ny for nx, ny, _, _ in lats)
+    b = lbm.Batch(lats, storage="f32", device="cuda:0")
+    b.step(3)
+    t0 = time.time()
+    chosen = b.autotune(5)
+    tune_s = time.time() - t0
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    b.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_b = e0.elapsed_time(e1) / steps
+    finite = all(all(v == v for v in b.masses(k)) for k in range(nsim))
+    info = b.plan_info()
+    b.close()
+    sims = [lbm.Simulation(nx, ny, prm, rn, storage="f32", device="cuda:0") for nx, ny, prm, rn in lats]
+    for s_ in sims:
+        s_.step(1)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        for s_ in sims:
+            s_.step(1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1) / 5
+    for s_ in sims:
+        s_.close()
+    return {"workload": "%d periodic drops, side ~U{64,128,256,512}, Lambda ~U{1,10,100}, sigma 10^U[-3,-1], "
+                        "elliptic, FP32, %d sites" % (nsim, sites),
+            "ms_per_step": round(ms_b, 4), "MLUPS": round(sites / ms_b / 1e3, 1),
+            "ms_per_step_one_launch_per_lattice": round(ms_s, 4),
+            "MLUPS_one_launch_per_lattice": round(sites / ms_s / 1e3, 1),
+            "autotune": {"chosen_ntx": chosen[0], "chosen_chunk_cap": chosen[1], "seconds": round(tune_s, 3),
+                         "work_items": info["items"], "bins": info["bins"]},
+            "finite": finite}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,6 +236,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy-roof", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one plain 1 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -267,6 +315,8 @@ def main():
         out["adjoint"] = dict({"workload": "same lattice and state, one adjoint step vs one forward step, FP32"},
                               **adjoint_measure(n, params, rn, torch))
         out["adjoint_rollout"] = adjoint_rollout(torch)
+    if not args.no_batch:
+        out["batch"] = batch_measure(torch)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

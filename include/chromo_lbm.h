@@ -190,6 +190,64 @@ int lbm_rhoN_adjoint(lbm_handle* h, const void* pops, const void* dL_drhoN, void
  * colour index rhoN0, given adj_pops0 = dL/d(initial populations). */
 int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, void* dL_drhoN0, hipStream_t stream);
 
+/* ---- batches: many independent periodic lattices, one launch per step ------
+ * All lattices of a batch share the storage format and the stencil radii; each
+ * has its own size and physical parameters (lbm_params), and none has walls or
+ * a force field.  Their population buffers are packed one after the other (each
+ * at a 256-byte aligned offset, lbm_batch_offsets) in two caller-owned buffers
+ * of lbm_batch_pops_bytes() bytes.  Every lbm_batch_step is one launch of a
+ * persistent-style kernel: each workgroup owns a bin of (lattice, tile) work
+ * items, planned on the host so that the bins' costs (march iterations) are
+ * balanced (longest processing time first).  The tile shape (workgroup width
+ * and chunk height) comes from a table of candidates; lbm_batch_autotune times
+ * them on the batch itself and keeps the fastest.  Each lattice evolves exactly
+ * as it would alone under lbm_step. */
+typedef struct lbm_batch lbm_batch;
+
+/* Bytes of each packed population buffer of the batch p[0..nsim-1]; 0 on
+ * invalid input. */
+size_t lbm_batch_pops_bytes(const lbm_params* p, int nsim);
+
+/* Byte offset of every lattice's buffer inside a packed buffer (offsets[nsim]). */
+int lbm_batch_offsets(const lbm_params* p, int nsim, size_t* offsets);
+
+/* Bytes of device workspace of a batch (work-list tables, mass partials). */
+size_t lbm_batch_workspace_bytes(const lbm_params* p, int nsim);
+
+/* Create a batch and write every lattice's rest state (as lbm_init) into
+ * pops_a.  rhoN0[k]: device [ny_k][nx_k] colour index of lattice k (arithmetic
+ * type).  pops_a, pops_b: device, 256-byte aligned, lbm_batch_pops_bytes()
+ * each.  Copies the initial work list to the workspace and waits for that
+ * copy. */
+int lbm_batch_init(const lbm_params* p, int nsim, const void* const* rhoN0, void* pops_a, void* pops_b,
+                   void* workspace, size_t ws_bytes, hipStream_t stream, lbm_batch** out);
+
+/* Advance every lattice by nsteps steps (one launch per step). */
+int lbm_batch_step(lbm_batch* b, int32_t nsteps, hipStream_t stream);
+
+/* Time every candidate tile shape for steps_per_trial steps on the batch's
+ * current state, keep the fastest, and restore the state (the step count is
+ * unchanged).  scratch: device memory of lbm_batch_pops_bytes() bytes.
+ * chosen (NULL or int32[2]) receives the workgroup width and chunk-height cap.
+ * Synchronises the stream. */
+int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_t steps_per_trial,
+                       hipStream_t stream, int32_t* chosen);
+
+/* info[5]: workgroup width, chunk-height cap, number of bins, number of work
+ * items, largest bin cost in march iterations. */
+int lbm_batch_plan_info(const lbm_batch* b, int32_t* info);
+
+/* Fields (as lbm_fields) and per-colour masses (as lbm_masses_host) of lattice k. */
+int lbm_batch_fields(lbm_batch* b, int32_t k, void* rho, void* ux, void* uy, void* rhoN, hipStream_t stream);
+int lbm_batch_masses_host(lbm_batch* b, int32_t k, double out[2], hipStream_t stream);
+
+/* 0 if pops_a holds the live states, 1 if pops_b does; steps taken. */
+int lbm_batch_current_pops(const lbm_batch* b);
+int64_t lbm_batch_step_count(const lbm_batch* b);
+
+/* Free the host object (device buffers stay with the caller). */
+void lbm_batch_destroy(lbm_batch* b);
+
 /* 0 if pops_a holds the live state, 1 if pops_b does. */
 int lbm_current_pops(const lbm_handle* h);
 

@@ -23,6 +23,10 @@ HEADERS = [os.path.join(CSRC, f) for f in ("chromo_kernels.hpp", "chromo_host.hp
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
+    # multiply-add fusion only within one source expression: a site's arithmetic
+    # is then the same in every unrolled copy of the march, so results do not
+    # depend on how a lattice is cut into tiles
+    "-ffp-contract=on",
     # no packed-FP32 VALU instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

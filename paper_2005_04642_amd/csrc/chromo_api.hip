@@ -6,8 +6,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <queue>
 #include <string>
+#include <vector>
 
 #include "chromo_lbm.h"
 #include "chromo_adjoint.hpp"
@@ -315,5 +318,387 @@ int64_t lbm_step_count(const lbm_handle* h) { return h ? h->steps : -1; }
 void lbm_destroy(lbm_handle* h) { delete h; }
 
 const char* lbm_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches of independent periodic lattices stepped by one launch
+// ===========================================================================
+namespace {
+
+constexpr int BATCH_MAX_BINS = 1024;
+const int BATCH_TYCAPS[] = {32, 64, 128, 256, 1 << 30};
+
+size_t round256(size_t n) { return (n + 255) / 256 * 256; }
+
+// Byte offset of every lattice's population buffer inside the packed buffers.
+size_t batch_offsets(const lbm_params* p, int nsim, std::vector<size_t>* off) {
+  size_t total = 0;
+  if (off) off->resize(nsim);
+  for (int k = 0; k < nsim; ++k) {
+    if (off) (*off)[k] = total;
+    total += round256(lbm_pops_bytes(&p[k]));
+  }
+  return total;
+}
+
+int batch_validate(const lbm_params* p, int nsim) {
+  if (!p || nsim < 1) return fail(LBM_EINVAL, "empty batch");
+  for (int k = 0; k < nsim; ++k) {
+    const int st = validate(&p[k]);
+    if (st != LBM_OK) return fail(st, "lattice %d: %s", k, g_last_error.c_str());
+    if (p[k].walls_y) return fail(LBM_ENOTIMPL, "lattice %d: batches hold periodic lattices only", k);
+    if (p[k].flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_EINVAL, "lattice %d: no stream-only mode in batches", k);
+    if (p[k].storage != p[0].storage) return fail(LBM_EINVAL, "lattice %d: storage differs from lattice 0", k);
+    for (int r = 0; r < 4; ++r)
+      if (p[k].stencil[r] != p[0].stencil[r]) return fail(LBM_EINVAL, "lattice %d: stencil radii differ", k);
+  }
+  return LBM_OK;
+}
+
+// Tile plan of one lattice for workgroup width ntx and chunk height cap.
+chromo::Geom batch_geom(const lbm_params& p, int ntx, int tycap) {
+  chromo::Geom g;
+  g.nx = p.nx;
+  g.ny = p.ny;
+  g.walls = 0;
+  g.F = p.ny;
+  g.plane = p.nx * p.ny;
+  const int txmax = ntx - 2 * halo(p);
+  g.nstrips = (p.nx + txmax - 1) / txmax;
+  g.TX = (p.nx + g.nstrips - 1) / g.nstrips;
+  int nch = (g.F + tycap - 1) / tycap;
+  if (nch < 1) nch = 1;
+  g.TY = (g.F + nch - 1) / nch;
+  g.nchunks = (g.F + g.TY - 1) / g.TY;
+  return g;
+}
+
+size_t batch_tiles(const lbm_params* p, int nsim, int ntx, int tycap) {
+  size_t n = 0;
+  for (int k = 0; k < nsim; ++k) {
+    const chromo::Geom g = batch_geom(p[k], ntx, tycap);
+    n += (size_t)g.nstrips * g.nchunks;
+  }
+  return n;
+}
+
+size_t batch_items_cap(const lbm_params* p, int nsim) {
+  size_t cap = 0;
+  const chromo::Ops* ops = ops_of(p[0].storage);
+  for (int i = 0; i < 3 && ops->batch_ntx[i]; ++i)
+    for (int tc : BATCH_TYCAPS) cap = std::max(cap, batch_tiles(p, nsim, ops->batch_ntx[i], tc));
+  return cap;
+}
+
+struct BatchPlan {
+  int ntx = 0, tycap = 0, nbins = 0;
+  std::vector<unsigned char> sims;
+  std::vector<int> bin_start, items;
+  double max_cost = 0.0;  // largest bin, in march iterations
+};
+
+// Longest-processing-time-first assignment of the tiles of every lattice to
+// nbins bins (one workgroup each), costs counted in march iterations.
+BatchPlan batch_plan(const lbm_params* p, int nsim, const std::vector<size_t>& off, int nbins, int ntx, int tycap,
+                     const chromo::Ops& ops, int nr, int it0) {
+  BatchPlan b;
+  b.ntx = ntx;
+  b.tycap = tycap;
+  b.nbins = nbins;
+  b.sims.resize((size_t)nsim * ops.sim_desc_bytes);
+  struct Tile {
+    int sim, tile;
+    int cost;
+  };
+  std::vector<Tile> tiles;
+  for (int k = 0; k < nsim; ++k) {
+    const chromo::Geom g = batch_geom(p[k], ntx, tycap);
+    ops.sim_desc(p[k], g, (unsigned long long)off[k], &b.sims[(size_t)k * ops.sim_desc_bytes]);
+    for (int t = 0; t < g.nstrips * g.nchunks; ++t) {
+      const int chunk = t / g.nstrips;
+      const int rows = std::min(g.TY, g.F - chunk * g.TY);
+      tiles.push_back({k, t, it0 + (rows + nr - 1) / nr});
+    }
+  }
+  std::stable_sort(tiles.begin(), tiles.end(), [](const Tile& a, const Tile& c) { return a.cost > c.cost; });
+  typedef std::pair<long long, int> Load;  // (cost, bin)
+  std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+  for (int i = 0; i < nbins; ++i) heap.push(Load(0, i));
+  std::vector<std::vector<int>> bins(nbins);
+  for (size_t i = 0; i < tiles.size(); ++i) {
+    Load l = heap.top();
+    heap.pop();
+    bins[l.second].push_back((int)i);
+    l.first += tiles[i].cost;
+    b.max_cost = std::max(b.max_cost, (double)l.first);
+    heap.push(l);
+  }
+  b.bin_start.assign(nbins + 1, 0);
+  for (int i = 0; i < nbins; ++i) {
+    b.bin_start[i + 1] = b.bin_start[i] + (int)bins[i].size();
+    for (int j : bins[i]) {
+      b.items.push_back(tiles[j].sim);
+      b.items.push_back(tiles[j].tile);
+    }
+  }
+  return b;
+}
+
+}  // namespace
+
+struct lbm_batch {
+  int nsim;
+  std::vector<lbm_params> p;
+  std::vector<size_t> off;
+  char* pops[2];
+  int live;
+  int64_t steps;
+  int ncu;
+  const chromo::Ops* ops;
+  void* d_sims;
+  int* d_bin_start;
+  int* d_items;
+  double* d_mass;
+  size_t items_cap;
+  BatchPlan plan;
+  std::vector<lbm_handle> view;  // one single-lattice handle per lattice (fields, masses)
+};
+
+namespace {
+
+int batch_upload(lbm_batch* b, BatchPlan&& pl, hipStream_t s) {
+  if (pl.items.size() / 2 > b->items_cap || pl.nbins > BATCH_MAX_BINS)
+    return fail(LBM_EINVAL, "batch plan exceeds the workspace tables");
+  b->plan = std::move(pl);
+  HIP_TRY(hipMemcpyAsync(b->d_sims, b->plan.sims.data(), b->plan.sims.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(b->d_bin_start, b->plan.bin_start.data(), b->plan.bin_start.size() * sizeof(int),
+                         hipMemcpyHostToDevice, s));
+  if (!b->plan.items.empty())
+    HIP_TRY(hipMemcpyAsync(b->d_items, b->plan.items.data(), b->plan.items.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+  // the host vectors must outlive the copies
+  HIP_TRY(hipStreamSynchronize(s));
+  return LBM_OK;
+}
+
+int batch_step_impl(lbm_batch* b, int nsteps, hipStream_t s) {
+  for (int k = 0; k < nsteps; ++k) {
+    hipError_t e = b->ops->batch(b->plan.ntx, b->p[0].stencil, b->pops[b->live], b->pops[1 - b->live], b->d_sims,
+                                 b->d_bin_start, b->d_items, b->plan.nbins, s);
+    if (e != hipSuccess) return fail(LBM_EHIP, "batch step launch: %s", hipGetErrorString(e));
+    b->live = 1 - b->live;
+    b->steps += 1;
+  }
+  return LBM_OK;
+}
+
+lbm_handle* batch_view(lbm_batch* b, int k) {
+  lbm_handle* h = &b->view[k];
+  h->live = b->live;
+  h->steps = b->steps;
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm_batch_pops_bytes(const lbm_params* p, int nsim) {
+  if (batch_validate(p, nsim) != LBM_OK) return 0;
+  return batch_offsets(p, nsim, nullptr);
+}
+
+int lbm_batch_offsets(const lbm_params* p, int nsim, size_t* offsets) {
+  g_last_error.clear();
+  int st = batch_validate(p, nsim);
+  if (st != LBM_OK) return st;
+  if (!offsets) return fail(LBM_EINVAL, "offsets is NULL");
+  std::vector<size_t> off;
+  batch_offsets(p, nsim, &off);
+  for (int k = 0; k < nsim; ++k) offsets[k] = off[k];
+  return LBM_OK;
+}
+
+size_t lbm_batch_workspace_bytes(const lbm_params* p, int nsim) {
+  if (batch_validate(p, nsim) != LBM_OK) return 0;
+  const chromo::Ops* ops = ops_of(p[0].storage);
+  return round256((size_t)nsim * ops->sim_desc_bytes) + round256((BATCH_MAX_BINS + 1) * sizeof(int)) +
+         round256(batch_items_cap(p, nsim) * 2 * sizeof(int)) + (size_t)(MASS_BLOCKS + 1) * 2 * sizeof(double);
+}
+
+int lbm_batch_init(const lbm_params* p, int nsim, const void* const* rhoN0, void* pops_a, void* pops_b,
+                   void* workspace, size_t ws_bytes, hipStream_t stream, lbm_batch** out) {
+  g_last_error.clear();
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int st = batch_validate(p, nsim);
+  if (st != LBM_OK) return st;
+  if (!rhoN0 || !pops_a || !pops_b || !workspace)
+    return fail(LBM_EINVAL, "rhoN0, pops_a, pops_b and workspace must be non-NULL");
+  for (int k = 0; k < nsim; ++k)
+    if (!rhoN0[k]) return fail(LBM_EINVAL, "rhoN0[%d] is NULL", k);
+  const size_t total = batch_offsets(p, nsim, nullptr);
+  const char* a = static_cast<const char*>(pops_a);
+  const char* bb = static_cast<const char*>(pops_b);
+  if (a < bb + total && bb < a + total) return fail(LBM_EINVAL, "pops_a and pops_b overlap");
+  if (reinterpret_cast<uintptr_t>(pops_a) % 256 || reinterpret_cast<uintptr_t>(pops_b) % 256)
+    return fail(LBM_EINVAL, "packed population buffers must be 256-byte aligned");
+  if (ws_bytes < lbm_batch_workspace_bytes(p, nsim))
+    return fail(LBM_EINVAL, "workspace too small: %zu < %zu", ws_bytes, lbm_batch_workspace_bytes(p, nsim));
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (ncu < 1) ncu = 1;
+  if (ncu > BATCH_MAX_BINS) ncu = BATCH_MAX_BINS;
+
+  lbm_batch* b = new (std::nothrow) lbm_batch;
+  if (!b) return fail(LBM_EINVAL, "out of host memory");
+  b->nsim = nsim;
+  b->p.assign(p, p + nsim);
+  batch_offsets(p, nsim, &b->off);
+  b->pops[0] = static_cast<char*>(pops_a);
+  b->pops[1] = static_cast<char*>(pops_b);
+  b->live = 0;
+  b->steps = 0;
+  b->ncu = ncu;
+  b->ops = ops_of(p[0].storage);
+  char* w = static_cast<char*>(workspace);
+  b->d_sims = w;
+  w += round256((size_t)nsim * b->ops->sim_desc_bytes);
+  b->d_bin_start = reinterpret_cast<int*>(w);
+  w += round256((BATCH_MAX_BINS + 1) * sizeof(int));
+  b->items_cap = batch_items_cap(p, nsim);
+  b->d_items = reinterpret_cast<int*>(w);
+  w += round256(b->items_cap * 2 * sizeof(int));
+  b->d_mass = reinterpret_cast<double*>(w);
+  b->view.resize(nsim);
+  for (int k = 0; k < nsim; ++k) {
+    lbm_handle& h = b->view[k];
+    h.p = p[k];
+    h.pops[0] = b->pops[0] + b->off[k];
+    h.pops[1] = b->pops[1] + b->off[k];
+    h.live = 0;
+    h.ws = b->d_mass;
+    h.ws_bytes = (size_t)(MASS_BLOCKS + 1) * 2 * sizeof(double);
+    h.force = nullptr;
+    h.steps = 0;
+    h.g = plan(p[k], ncu, chromo::ntx_for(p[k].storage));
+    h.g_adj = plan(p[k], ncu, chromo::ntx_for(p[k].storage, true));
+    h.ops = b->ops;
+    hipError_t e = b->ops->init(p[k], h.g, rhoN0[k], h.pops[0], stream);
+    if (e != hipSuccess) {
+      delete b;
+      return fail(LBM_EHIP, "init launch: %s", hipGetErrorString(e));
+    }
+  }
+  const int nr = b->ops->math_bytes == 8 ? chromo::NR_F64 : chromo::NR_F32;
+  const int it0 = 3 * ((nr * ((3 + nr - 1) / nr) + 3 + nr - 1) / nr);
+  int ntx0 = b->ops->batch_ntx[0];
+  for (int i = 1; i < 3 && b->ops->batch_ntx[i]; ++i) ntx0 = std::max(ntx0, b->ops->batch_ntx[i]);
+  st = batch_upload(b, batch_plan(p, nsim, b->off, ncu, ntx0, 128, *b->ops, nr, it0), stream);
+  if (st != LBM_OK) {
+    delete b;
+    return st;
+  }
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int32_t nsteps, hipStream_t stream) {
+  g_last_error.clear();
+  if (!b) return fail(LBM_EINVAL, "batch is NULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  return batch_step_impl(b, nsteps, stream);
+}
+
+int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_t steps_per_trial,
+                       hipStream_t stream, int32_t* chosen) {
+  g_last_error.clear();
+  if (!b || !scratch) return fail(LBM_EINVAL, "batch and scratch must be non-NULL");
+  const size_t total = b->off.back() + round256(lbm_pops_bytes(&b->p.back()));
+  if (scratch_bytes < total) return fail(LBM_EINVAL, "scratch too small: %zu < %zu", scratch_bytes, total);
+  if (steps_per_trial < 1) return fail(LBM_EINVAL, "steps_per_trial < 1");
+  const int live0 = b->live;
+  const int64_t steps0 = b->steps;
+  HIP_TRY(hipMemcpyAsync(scratch, b->pops[live0], total, hipMemcpyDeviceToDevice, stream));
+  const int nr = b->ops->math_bytes == 8 ? chromo::NR_F64 : chromo::NR_F32;
+  const int it0 = 3 * ((nr * ((3 + nr - 1) / nr) + 3 + nr - 1) / nr);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  float best = -1.0f;
+  int best_ntx = b->plan.ntx, best_tycap = b->plan.tycap;
+  int st = LBM_OK;
+  for (int i = 0; i < 3 && b->ops->batch_ntx[i] && st == LBM_OK; ++i) {
+    for (int tc : BATCH_TYCAPS) {
+      st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, b->ops->batch_ntx[i], tc, *b->ops, nr,
+                                      it0),
+                        stream);
+      if (st != LBM_OK) break;
+      hipMemcpyAsync(b->pops[live0], scratch, total, hipMemcpyDeviceToDevice, stream);
+      b->live = live0;
+      if ((st = batch_step_impl(b, 1, stream)) != LBM_OK) break;  // warm-up
+      hipEventRecord(e0, stream);
+      if ((st = batch_step_impl(b, steps_per_trial, stream)) != LBM_OK) break;
+      hipEventRecord(e1, stream);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        st = fail(LBM_EHIP, "autotune: event synchronisation failed");
+        break;
+      }
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, e0, e1);
+      if (best < 0.0f || ms < best) {
+        best = ms;
+        best_ntx = b->ops->batch_ntx[i];
+        best_tycap = tc;
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  // restore the state and install the winner
+  HIP_TRY(hipMemcpyAsync(b->pops[live0], scratch, total, hipMemcpyDeviceToDevice, stream));
+  b->live = live0;
+  b->steps = steps0;
+  if (st != LBM_OK) return st;
+  st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, best_ntx, best_tycap, *b->ops, nr, it0),
+                    stream);
+  if (st != LBM_OK) return st;
+  if (chosen) {
+    chosen[0] = best_ntx;
+    chosen[1] = best_tycap;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_plan_info(const lbm_batch* b, int32_t* info) {
+  if (!b || !info) return fail(LBM_EINVAL, "batch and info must be non-NULL");
+  info[0] = b->plan.ntx;
+  info[1] = b->plan.tycap;
+  info[2] = b->plan.nbins;
+  info[3] = (int32_t)(b->plan.items.size() / 2);
+  info[4] = (int32_t)b->plan.max_cost;
+  return LBM_OK;
+}
+
+int lbm_batch_fields(lbm_batch* b, int32_t k, void* rho, void* ux, void* uy, void* rhoN, hipStream_t stream) {
+  g_last_error.clear();
+  if (!b || k < 0 || k >= b->nsim) return fail(LBM_EINVAL, "bad batch or lattice index");
+  return lbm_fields(batch_view(b, k), rho, ux, uy, rhoN, nullptr, stream);
+}
+
+int lbm_batch_masses_host(lbm_batch* b, int32_t k, double out[2], hipStream_t stream) {
+  g_last_error.clear();
+  if (!b || k < 0 || k >= b->nsim) return fail(LBM_EINVAL, "bad batch or lattice index");
+  return lbm_masses_host(batch_view(b, k), out, stream);
+}
+
+int lbm_batch_current_pops(const lbm_batch* b) { return b ? b->live : -1; }
+
+int64_t lbm_batch_step_count(const lbm_batch* b) { return b ? b->steps : -1; }
+
+void lbm_batch_destroy(lbm_batch* b) { delete b; }
 
 }  // extern "C"

@@ -47,6 +47,13 @@ struct Ops {
                              hipStream_t s);
   hipError_t (*init_adjoint)(const lbm_params& p, const Geom& g, const void* rhoN0, const void* lam0, void* out,
                              hipStream_t s);
+  // batched periodic step: ntx in batch_ntx (0-terminated); tables in device memory
+  hipError_t (*batch)(int ntx, const int* radii, const void* src, void* dst, const void* sims, const int* bin_start,
+                      const int* items, int nbins, hipStream_t s);
+  // one SimDesc<math> of lattice p with tile plan g and byte offset off, written to out
+  void (*sim_desc)(const lbm_params& p, const Geom& g, unsigned long long off, void* out);
+  int sim_desc_bytes;
+  int batch_ntx[3];
   int words;        // words per site
   int word_bytes;   // bytes per word
   int math_bytes;   // bytes of the arithmetic type (fields, rho^N, force)

@@ -699,22 +699,14 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   }
 }
 
+// One tile (strip x chunk of rows) of one lattice: the whole march.
 template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE>
-__global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typename ST::math> a) {
+__device__ __forceinline__ void march_tile(const StepArgs<typename ST::math>& a, int tile,
+                                           Smem<typename ST::math, NTX, Pipe<NR>::RING>& sm) {
   using T = typename ST::math;
   using PP = Pipe<NR>;
   constexpr int H = RG + RK + RU;
-  static_assert(NTX > 2 * H, "strip must be wider than its halo");
-  static_assert(NTX % 64 == 0, "a wavefront must cover a single lattice row");
-  __shared__ Smem<T, NTX, PP::RING> sm;
   const Geom& g = a.g;
-  // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
-  // XCD gets a contiguous run of tiles (neighbouring strips of the same rows),
-  // whose shared halo columns and boundary cache lines then meet in one L2.
-  const int ntiles = g.nstrips * g.nchunks;
-  const int per_xcd = (ntiles + 7) / 8;
-  const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (tile >= ntiles) return;
   const __amdgpu_buffer_rsrc_t src = make_rsrc<ST>(a.src, g.plane);
   const __amdgpu_buffer_rsrc_t dst = make_rsrc<ST>(MODE != MODE_STEP ? a.src : a.dst, g.plane);
   Thread t;
@@ -752,6 +744,67 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typen
       march_iter<2, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it + 2, a, src, dst, sm, st, t, tM, tU);
     if (it + 3 < t.nit)
       march_iter<3, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it + 3, a, src, dst, sm, st, t, tM, tU);
+  }
+}
+
+template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE>
+__global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typename ST::math> a) {
+  using T = typename ST::math;
+  using PP = Pipe<NR>;
+  static_assert(NTX > 2 * (RG + RK + RU), "strip must be wider than its halo");
+  static_assert(NTX % 64 == 0, "a wavefront must cover a single lattice row");
+  __shared__ Smem<T, NTX, PP::RING> sm;
+  const Geom& g = a.g;
+  // Workgroups are dealt to the 8 XCDs round-robin; renumber them so that each
+  // XCD gets a contiguous run of tiles (neighbouring strips of the same rows),
+  // whose shared halo columns and boundary cache lines then meet in one L2.
+  const int ntiles = g.nstrips * g.nchunks;
+  const int per_xcd = (ntiles + 7) / 8;
+  const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (tile >= ntiles) return;
+  march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(a, tile, sm);
+}
+
+// ---------------------------------------------------------------------------
+// Batched step: many independent periodic lattices in one launch.  Each
+// workgroup owns a bin of work items (lattice, tile), planned on the host so
+// that the bins' costs are balanced, and runs them one after the other.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SimDesc {
+  Geom g;                 // per-lattice geometry and tile plan
+  Coef<T> c;              // per-lattice constants
+  unsigned long long off; // byte offset of the lattice's populations in both packed buffers
+};
+
+template <typename T>
+struct BatchArgs {
+  const char* src;              // packed population buffers
+  char* dst;
+  const SimDesc<T>* sims;
+  const int* bin_start;         // [nbins + 1] offsets into items
+  const int* items;             // pairs (lattice, tile)
+};
+
+template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU>
+__global__ void __launch_bounds__(NTX * NR, 1) chromo_batch_kernel(BatchArgs<typename ST::math> b) {
+  using T = typename ST::math;
+  using PP = Pipe<NR>;
+  static_assert(NTX > 2 * (RG + RK + RU), "strip must be wider than its halo");
+  __shared__ Smem<T, NTX, PP::RING> sm;
+  const int k0 = b.bin_start[blockIdx.x], k1 = b.bin_start[blockIdx.x + 1];
+  for (int k = k0; k < k1; ++k) {
+    const int sim = b.items[2 * k], tile = b.items[2 * k + 1];
+    StepArgs<T> a;
+    a.src = b.src + b.sims[sim].off;
+    a.dst = b.dst + b.sims[sim].off;
+    a.force = nullptr;
+    a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = a.out_save = a.out_adj = nullptr;
+    a.lam_next = nullptr;
+    a.g = b.sims[sim].g;
+    a.c = b.sims[sim].c;
+    march_tile<ST, NTX, NR, RG, RK, RP, RU, false, MODE_STEP>(a, tile, sm);
+    __syncthreads();  // the next tile reuses the LDS rings
   }
 }
 

@@ -3,6 +3,8 @@
 // the formats compile as separate translation units.
 #pragma once
 
+#include <cstring>
+
 #include "chromo_adjoint.hpp"
 #include "chromo_host.hpp"
 
@@ -239,6 +241,72 @@ hipError_t init_adjoint(const lbm_params& p, const Geom& g0, const void* rhoN0, 
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// batched periodic step (chromo_batch_kernel)
+// ---------------------------------------------------------------------------
+template <typename S, int NTX, int RG, int RK, int RP, int RU>
+hipError_t batch_launch(const BatchArgs<typename S::math>& b, int nbins, hipStream_t s) {
+  hipLaunchKernelGGL((chromo_batch_kernel<S, NTX, Shape<S>::nr, RG, RK, RP, RU>), dim3(nbins),
+                     dim3(NTX * Shape<S>::nr), 0, s, b);
+  return hipGetLastError();
+}
+
+template <typename S, int NTX>
+hipError_t batch_radii(const BatchArgs<typename S::math>& b, const int* r, int nbins, hipStream_t s) {
+  const int code = (r[0] == 3) * 8 + (r[1] == 3) * 4 + (r[2] == 3) * 2 + (r[3] == 3);
+#define CHROMO_CASE(C, A, B, P, U) \
+  case C:                          \
+    return batch_launch<S, NTX, A, B, P, U>(b, nbins, s);
+  switch (code) {
+    CHROMO_CASE(0, 1, 1, 1, 1)
+    CHROMO_CASE(1, 1, 1, 1, 3)
+    CHROMO_CASE(2, 1, 1, 3, 1)
+    CHROMO_CASE(3, 1, 1, 3, 3)
+    CHROMO_CASE(4, 1, 3, 1, 1)
+    CHROMO_CASE(5, 1, 3, 1, 3)
+    CHROMO_CASE(6, 1, 3, 3, 1)
+    CHROMO_CASE(7, 1, 3, 3, 3)
+    CHROMO_CASE(8, 3, 1, 1, 1)
+    CHROMO_CASE(9, 3, 1, 1, 3)
+    CHROMO_CASE(10, 3, 1, 3, 1)
+    CHROMO_CASE(11, 3, 1, 3, 3)
+    CHROMO_CASE(12, 3, 3, 1, 1)
+    CHROMO_CASE(13, 3, 3, 1, 3)
+    CHROMO_CASE(14, 3, 3, 3, 1)
+    CHROMO_CASE(15, 3, 3, 3, 3)
+  }
+#undef CHROMO_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename S>
+hipError_t batch(int ntx, const int* radii, const void* src, void* dst, const void* sims, const int* bin_start,
+                 const int* items, int nbins, hipStream_t s) {
+  using T = typename S::math;
+  BatchArgs<T> b;
+  b.src = static_cast<const char*>(src);
+  b.dst = static_cast<char*>(dst);
+  b.sims = static_cast<const SimDesc<T>*>(sims);
+  b.bin_start = bin_start;
+  b.items = items;
+  if constexpr (Shape<S>::f64) {
+    if (ntx == NTX_F64) return batch_radii<S, NTX_F64>(b, radii, nbins, s);
+  } else {
+    if (ntx == 128) return batch_radii<S, 128>(b, radii, nbins, s);
+    if (ntx == 192) return batch_radii<S, 192>(b, radii, nbins, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename S>
+void sim_desc(const lbm_params& p, const Geom& g, unsigned long long off, void* out) {
+  SimDesc<typename S::math> d;
+  d.g = geom_for<S>(g);
+  d.c = make_coef<S>(p);
+  d.off = off;
+  memcpy(out, &d, sizeof(d));
+}
+
 template <typename S>
 Ops make_ops() {
   Ops o;
@@ -255,6 +323,18 @@ Ops make_ops() {
     o.adjoint = adjoint<S>;
     o.rhoN_adjoint = rhoN_adjoint<S>;
     o.init_adjoint = init_adjoint<S>;
+  }
+  o.batch_ntx[0] = o.batch_ntx[1] = o.batch_ntx[2] = 0;
+  o.batch = batch<S>;
+  o.sim_desc = sim_desc<S>;
+  o.sim_desc_bytes = (int)sizeof(SimDesc<typename S::math>);
+  if constexpr (Shape<S>::f64) {
+    o.batch_ntx[0] = NTX_F64;
+    o.batch_ntx[1] = 0;
+  } else {
+    o.batch_ntx[0] = 128;
+    o.batch_ntx[1] = 192;
+    o.batch_ntx[2] = 0;
   }
   o.words = S::NW;
   o.word_bytes = (int)sizeof(typename S::W);

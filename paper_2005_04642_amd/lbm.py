@@ -26,7 +26,9 @@ LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR = 1, 2, 4
 EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_workspace_bytes", "lbm_init",
             "lbm_step", "lbm_fields", "lbm_masses_host", "lbm_adjoint_workspace_bytes", "lbm_adjoint_step",
             "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_current_pops", "lbm_step_count", "lbm_destroy",
-            "lbm_last_error")
+            "lbm_last_error", "lbm_batch_pops_bytes", "lbm_batch_offsets", "lbm_batch_workspace_bytes",
+            "lbm_batch_init", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_plan_info", "lbm_batch_fields",
+            "lbm_batch_masses_host", "lbm_batch_current_pops", "lbm_batch_step_count", "lbm_batch_destroy")
 
 
 class LbmError(RuntimeError):
@@ -94,6 +96,31 @@ def load_library(path=None):
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.argtypes = []
     lib.lbm_last_error.restype = ctypes.c_char_p
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    lib.lbm_batch_pops_bytes.argtypes = [P, ctypes.c_int]
+    lib.lbm_batch_pops_bytes.restype = sz
+    lib.lbm_batch_offsets.argtypes = [P, ctypes.c_int, ctypes.POINTER(sz)]
+    lib.lbm_batch_offsets.restype = ctypes.c_int
+    lib.lbm_batch_workspace_bytes.argtypes = [P, ctypes.c_int]
+    lib.lbm_batch_workspace_bytes.restype = sz
+    lib.lbm_batch_init.argtypes = [P, ctypes.c_int, ctypes.POINTER(vp), vp, vp, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.lbm_batch_init.restype = ctypes.c_int
+    lib.lbm_batch_step.argtypes = [vp, i32, vp]
+    lib.lbm_batch_step.restype = ctypes.c_int
+    lib.lbm_batch_autotune.argtypes = [vp, vp, sz, i32, vp, i32p]
+    lib.lbm_batch_autotune.restype = ctypes.c_int
+    lib.lbm_batch_plan_info.argtypes = [vp, i32p]
+    lib.lbm_batch_plan_info.restype = ctypes.c_int
+    lib.lbm_batch_fields.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    lib.lbm_batch_fields.restype = ctypes.c_int
+    lib.lbm_batch_masses_host.argtypes = [vp, i32, dp, vp]
+    lib.lbm_batch_masses_host.restype = ctypes.c_int
+    lib.lbm_batch_current_pops.argtypes = [vp]
+    lib.lbm_batch_current_pops.restype = ctypes.c_int
+    lib.lbm_batch_step_count.argtypes = [vp]
+    lib.lbm_batch_step_count.restype = ctypes.c_int64
+    lib.lbm_batch_destroy.argtypes = [vp]
+    lib.lbm_batch_destroy.restype = None
     if path is None:
         _lib = lib
     return lib
@@ -318,6 +345,119 @@ class Simulation:
     def close(self):
         if getattr(self, "h", None) is not None:
             lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------------------
+# batches of independent periodic lattices
+# ---------------------------------------------------------------------------
+
+def lbm_batch_pops_bytes(plist):
+    arr = (lbm_params * len(plist))(*plist)
+    return load_library().lbm_batch_pops_bytes(arr, len(plist))
+
+
+def lbm_batch_offsets(plist):
+    lib = load_library()
+    arr = (lbm_params * len(plist))(*plist)
+    out = (ctypes.c_size_t * len(plist))()
+    _check(lib, lib.lbm_batch_offsets(arr, len(plist), out))
+    return list(out)
+
+
+def lbm_batch_workspace_bytes(plist):
+    arr = (lbm_params * len(plist))(*plist)
+    return load_library().lbm_batch_workspace_bytes(arr, len(plist))
+
+
+class Batch:
+    """Independent periodic lattices stepped together by one launch per step.
+
+    lattices: list of (nx, ny, params, rhoN0); every lattice shares the
+    storage format and the stencil radii.  ``state(k)`` is a view of lattice
+    k's live population buffer ([2, 9, ny, nx], F32/F64 storage).
+    """
+
+    def __init__(self, lattices, storage="f32", device="cuda:0"):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the chromodynamic LBM step runs only on the HIP device")
+        self.torch = torch
+        self.device = torch.device(device)
+        self.storage = storage
+        self.dtype = torch.float64 if storage == "f64" else torch.float32
+        self.shapes = [(nx, ny) for nx, ny, _, _ in lattices]
+        self.plist = [make_params(nx, ny, storage, **dict(prm)) for nx, ny, prm, _ in lattices]
+        lib = load_library()
+        n = len(self.plist)
+        arr = (lbm_params * n)(*self.plist)
+        nbytes = lib.lbm_batch_pops_bytes(arr, n)
+        if nbytes == 0:
+            raise LbmError(LBM_EINVAL, lib.lbm_last_error().decode())
+        self.offsets = lbm_batch_offsets(self.plist)
+        self.pops = [torch.empty(nbytes, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        wsb = lib.lbm_batch_workspace_bytes(arr, n)
+        self.ws = torch.zeros(wsb, dtype=torch.uint8, device=self.device)
+        self.rhoN0 = [torch.as_tensor(np.asarray(r) if not torch.is_tensor(r) else r).to(
+            device=self.device, dtype=self.dtype).contiguous() for _, _, _, r in lattices]
+        ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.rhoN0])
+        h = ctypes.c_void_p()
+        _check(lib, lib.lbm_batch_init(arr, n, ptrs, self.pops[0].data_ptr(), self.pops[1].data_ptr(),
+                                       self.ws.data_ptr(), wsb, self.stream(), ctypes.byref(h)))
+        self.h = h
+        self.lib = lib
+
+    def stream(self):
+        return self.torch.cuda.current_stream(self.device).cuda_stream
+
+    def step(self, n=1):
+        _check(self.lib, self.lib.lbm_batch_step(self.h, int(n), self.stream()))
+        return self
+
+    def autotune(self, steps_per_trial=5):
+        scratch = self.torch.empty_like(self.pops[0])
+        chosen = (ctypes.c_int32 * 2)()
+        _check(self.lib, self.lib.lbm_batch_autotune(self.h, scratch.data_ptr(), scratch.numel(),
+                                                     int(steps_per_trial), self.stream(), chosen))
+        return chosen[0], chosen[1]
+
+    def plan_info(self):
+        info = (ctypes.c_int32 * 5)()
+        _check(self.lib, self.lib.lbm_batch_plan_info(self.h, info))
+        return dict(ntx=info[0], tycap=info[1], bins=info[2], items=info[3], max_cost=info[4])
+
+    def state(self, k):
+        nx, ny = self.shapes[k]
+        live = self.lib.lbm_batch_current_pops(self.h)
+        n = 18 * nx * ny * (8 if self.storage == "f64" else 4)
+        return self.pops[live][self.offsets[k]:self.offsets[k] + n].view(self.dtype).view(2, 9, ny, nx)
+
+    def fields(self, k):
+        t = self.torch
+        nx, ny = self.shapes[k]
+        out = {key: t.empty((ny, nx), dtype=self.dtype, device=self.device) for key in ("rho", "ux", "uy", "rhoN")}
+        _check(self.lib, self.lib.lbm_batch_fields(self.h, int(k), out["rho"].data_ptr(), out["ux"].data_ptr(),
+                                                   out["uy"].data_ptr(), out["rhoN"].data_ptr(), self.stream()))
+        return out
+
+    def masses(self, k):
+        out = (ctypes.c_double * 2)()
+        _check(self.lib, self.lib.lbm_batch_masses_host(self.h, int(k), out, self.stream()))
+        return out[0], out[1]
+
+    @property
+    def steps(self):
+        return self.lib.lbm_batch_step_count(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            self.lib.lbm_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -107,13 +107,18 @@ def emulsion(nx=4096, ny=4096, ndrops=50, rmin=20.0, rmax=80.0, gap=6.0, seed=0)
     return out
 
 
-def ellipse_drop(n, aspect, center=None):
-    """Axis-aligned ellipse with semi-axes (n/4) sqrt(AR) and (n/4)/sqrt(AR)."""
+def ellipse_drop(n, aspect, center=None, width=None):
+    """Axis-aligned ellipse with semi-axes (n/4) sqrt(AR) and (n/4)/sqrt(AR):
+    rho^N = +1 inside, -1 outside, or, with ``width``, the smooth profile
+    tanh(d / width) of the approximate signed distance d to the ellipse."""
     cx, cy = center if center is not None else ((n - 1) / 2.0, (n - 1) / 2.0)
     a = n / 4.0 * math.sqrt(aspect)
     b = n / 4.0 / math.sqrt(aspect)
     y, x = np.mgrid[0:n, 0:n].astype(np.float64)
-    return np.where(((x - cx) / a) ** 2 + ((y - cy) / b) ** 2 < 1.0, 1.0, -1.0)
+    q = np.sqrt(((x - cx) / a) ** 2 + ((y - cy) / b) ** 2)
+    if width is None:
+        return np.where(q < 1.0, 1.0, -1.0)
+    return np.tanh((1.0 - q) * math.sqrt(a * b) / width)
 
 
 def gaussian_bumps(nx, ny, nbumps=8, width=24.0, amplitude=1e-6, seed=2):
@@ -170,3 +175,26 @@ def config_emulsion(nx=4096, ny=4096, seed=0):
 def emulsion_crop(n=512, ndrops=3, seed=0):
     """Smaller emulsion for parity runs: ``ndrops`` drops with the same radius law."""
     return emulsion(n, n, ndrops, 20.0, 80.0 if n >= 400 else n / 8.0, 6.0, seed)
+
+
+def config_batch(nsim=256, seed=1, width=2.0):
+    """Batch of independent periodic drops: side ~ U{64, 128, 256, 512},
+    Lambda ~ U{1, 10, 100}, sigma = 10^U[-3, -1], an axis-aligned centred
+    ellipse of aspect ratio ~ U[1, 1.5] with semi-axes (L/4) sqrt(AR) and
+    (L/4)/sqrt(AR), given as tanh(d / width) of the distance to the ellipse
+    (a sharp +-1 ellipse if width is None); beta = 0.67, nu = 1/6, ghost rates
+    1.4 / 1.2.  At Lambda = 100 the scheme is unstable for sigma above about
+    0.06 (these rates and viscosity), so sigma is redrawn there until it is at
+    most 0.05.  Returns a list of (nx, ny, params, rhoN0)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(nsim):
+        L = int(rng.choice([64, 128, 256, 512]))
+        Lam = float(rng.choice([1.0, 10.0, 100.0]))
+        sigma = float(10.0 ** rng.uniform(-3.0, -1.0))
+        while Lam >= 100.0 and sigma > 0.05:
+            sigma = float(10.0 ** rng.uniform(-3.0, -1.0))
+        ar = float(rng.uniform(1.0, 1.5))
+        prm = base_params(Lambda=Lam, sigma=sigma)
+        out.append((L, L, prm, ellipse_drop(L, ar, width=width)))
+    return out

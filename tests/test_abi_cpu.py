@@ -110,3 +110,20 @@ def test_adjoint_availability_and_argument_errors():
     assert lib.lbm_adjoint_step(None, None, None, None, None, 0, None, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_rhoN_adjoint(None, None, None, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_init_adjoint(None, None, None, None, None) == lbm.LBM_EINVAL
+
+
+def test_batch_validation_and_layout():
+    prm = Wk.base_params(Lambda=10.0)
+    ps = [lbm.make_params(n, m, "f32", **prm) for n, m in ((64, 64), (5, 7), (300, 20))]
+    total = lbm.lbm_batch_pops_bytes(ps)
+    offs = lbm.lbm_batch_offsets(ps)
+    assert offs[0] == 0 and all(o % 256 == 0 for o in offs)
+    assert offs[1] >= 72 * 64 * 64 and offs[2] - offs[1] >= 72 * 5 * 7
+    assert total >= offs[2] + 72 * 300 * 20
+    assert lbm.lbm_batch_workspace_bytes(ps) > 0
+    walls = [lbm.make_params(64, 64, "f32", **dict(prm, walls=True))]
+    assert lbm.lbm_batch_pops_bytes(walls) == 0
+    mixed = [ps[0], lbm.make_params(64, 64, "f64", **prm)]
+    assert lbm.lbm_batch_pops_bytes(mixed) == 0
+    radii = [ps[0], lbm.make_params(64, 64, "f32", **dict(prm, stencil=(1, 1, 1, 1)))]
+    assert lbm.lbm_batch_pops_bytes(radii) == 0

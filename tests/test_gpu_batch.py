@@ -1,0 +1,87 @@
+"""Batched launch (lbm_batch_*): every lattice of a batch evolves exactly as it
+does alone under lbm_step, before and after the autotuner picks a tile shape,
+and the autotuner leaves the state unchanged."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2005_04642_amd import lbm, workloads as Wk
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def lattices():
+    rng = np.random.default_rng(0)
+    out = []
+    for (nx, ny, Lam, sigma) in [(5, 7, 10.0, 0.005), (64, 64, 1.0, 0.001), (100, 60, 100.0, 0.01),
+                                 (130, 40, 10.0, 0.01), (200, 200, 10.0, 0.005), (37, 300, 2.0, 0.02)]:
+        prm = Wk.base_params(Lambda=Lam, sigma=sigma)
+        y, x = np.mgrid[0:ny, 0:nx]
+        d = np.hypot((x - (nx - 1) / 2.0) / 1.15, (y - (ny - 1) / 2.0) * 1.15)
+        rn = 0.3 * np.tanh(rng.standard_normal((ny, nx))) if nx < 10 else np.tanh((min(nx, ny) / 4.0 - d) / 2.0)
+        out.append((nx, ny, prm, rn))
+    return out
+
+
+def singles(lats, storage, steps):
+    res = []
+    for nx, ny, prm, rn in lats:
+        s = lbm.Simulation(nx, ny, prm, rn, storage=storage, device=DEV)
+        s.step(steps)
+        torch.cuda.synchronize()
+        res.append((s.live_words().cpu().numpy().copy(), s.masses()))
+        s.close()
+    return res
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+def test_batch_matches_single_lattices(storage):
+    lats = lattices()
+    b = lbm.Batch(lats, storage=storage, device=DEV)
+    info = b.plan_info()
+    assert info["items"] >= len(lats)
+    b.step(12)
+    ref = singles(lats, storage, 12)
+    live = lambda k: b.pops[b.lib.lbm_batch_current_pops(b.h)]
+    for k, (nx, ny, _, _) in enumerate(lats):
+        words = lbm.WORDS_PER_SITE[storage] * nx * ny
+        esz = 8 if storage == "f64" else 4
+        got = live(k)[b.offsets[k]:b.offsets[k] + words * esz].cpu().numpy()
+        want = ref[k][0].reshape(-1).view(np.uint8)
+        assert np.array_equal(got, want), k
+        m = b.masses(k)
+        assert m == ref[k][1], k
+    b.close()
+
+
+def test_autotune_keeps_state_and_results():
+    lats = lattices()
+    b = lbm.Batch(lats, storage="f32", device=DEV)
+    b.step(3)
+    torch.cuda.synchronize()
+    before = b.pops[b.lib.lbm_batch_current_pops(b.h)].clone()
+    chosen = b.autotune(steps_per_trial=2)
+    assert chosen[0] in (128, 192)
+    torch.cuda.synchronize()
+    after = b.pops[b.lib.lbm_batch_current_pops(b.h)]
+    assert torch.equal(before, after) and b.steps == 3
+    b.step(9)
+    ref = singles(lats, "f32", 12)
+    for k in range(len(lats)):
+        got = b.state(k).cpu().numpy()
+        assert np.array_equal(got, ref[k][0].reshape(got.shape)), k
+    f = b.fields(2)
+    assert torch.isfinite(f["rho"]).all()
+    b.close()
+
+
+def test_batch_of_the_benchmark_workload_runs():
+    lats = Wk.config_batch(nsim=32, seed=1)
+    b = lbm.Batch(lats, storage="f32", device=DEV)
+    b.step(20)
+    for k in range(len(lats)):
+        m = b.masses(k)
+        assert np.isfinite(m).all()
+    b.close()
