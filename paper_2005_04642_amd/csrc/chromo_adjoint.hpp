@@ -38,8 +38,10 @@ enum { B_RR, B_RB, B_JX, B_JY, B_K, B_GX, B_GY, B_N };
 enum { C_GX, C_GY, C_N };
 enum { D_RR, D_RB, D_N };
 constexpr int WS_PLANES = SV_N + A_N + B_N + C_N + D_N;
-// FP64 partial sums of dL/dsigma: one per 256-site block of a row
+// FP64 partial sums of dL/dsigma: one per 256-site block of a row, then up to
+// RED2 second-stage sums
 __host__ __device__ inline int red_blocks(int nx, int ny) { return ((nx + 255) / 256) * ny; }
+constexpr int RED2 = 256;
 
 // App. B first-derivative stencil of radius R applied to a periodic global
 // field at (x, y): (d/dx, d/dy), the same sums as the forward ring stencils.
@@ -352,6 +354,17 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, 
   }
   const double tot = block_sum(acc);
   if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = tot;
+}
+
+// in[0..n) -> out[blockIdx.x]: each block sums a contiguous slice (fixed order)
+static __global__ void __launch_bounds__(256) partial_sum_kernel(const double* __restrict__ in, int n,
+                                                                 double* __restrict__ out) {
+  const int per = (n + gridDim.x - 1) / gridDim.x;
+  const int lo = blockIdx.x * per, hi = min(n, lo + per);
+  double v = 0.0;
+  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) v += in[i];
+  const double tot = block_sum(v);
+  if (threadIdx.x == 0) out[blockIdx.x] = tot;
 }
 
 static __global__ void __launch_bounds__(256) sum_into_kernel(const double* __restrict__ part, int n, double* out) {

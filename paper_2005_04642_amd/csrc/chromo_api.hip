@@ -261,7 +261,7 @@ size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
   const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
   size_t bytes = (size_t)chromo::adj::WS_PLANES * (size_t)p->nx * (size_t)p->ny * elem;
   bytes = (bytes + 255) / 256 * 256;
-  return bytes + (size_t)chromo::adj::red_blocks(p->nx, p->ny) * sizeof(double);
+  return bytes + (size_t)(chromo::adj::red_blocks(p->nx, p->ny) + chromo::adj::RED2) * sizeof(double);
 }
 
 static int adjoint_supported(const lbm_handle* h) {

@@ -356,65 +356,75 @@ __device__ __forceinline__ T stencil_b(int n) {
   return n == 1 ? T(4.5) : (n == 2 ? T(-0.9) : T(0.1));
 }
 
-// (d/dx, d/dy) of a ring field at (ring row `row`, column tx).
-template <int R, int RING, int NTX, typename T>
-__device__ __forceinline__ void ring_grad(const T (*s)[NTX], int row, int tx, T& gx, T& gy) {
+// (d/dx, d/dy) of a ring field at (ring row `row`, column tx); s points at the
+// field's first row, successive ring rows are STRIDE elements apart.  Row
+// pointers start R columns left of tx so that every column offset is
+// non-negative (LDS instruction offsets are unsigned).
+template <int R, int RING, int STRIDE, typename T>
+__device__ __forceinline__ void ring_grad(const T* s, int row, int tx, T& gx, T& gy) {
   const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
   gx = T(0);
   gy = T(0);
-  const T* md = &s[ring_row<RING>(row)][tx];
+  const T* md = s + ring_row<RING>(row) * STRIDE + (tx - R);
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
     const T b = stencil_b<R, T>(n);
-    const T* up = &s[ring_row<RING>(row + n)][tx];
-    const T* dn = &s[ring_row<RING>(row - n)][tx];
-    const T d1 = up[n] - dn[-n];
-    const T d3 = up[-n] - dn[n];
-    const T d8 = md[n] - md[-n];
-    const T d2 = up[0] - dn[0];
+    const T* up = s + ring_row<RING>(row + n) * STRIDE + (tx - R);
+    const T* dn = s + ring_row<RING>(row - n) * STRIDE + (tx - R);
+    const T d1 = up[R + n] - dn[R - n];
+    const T d3 = up[R - n] - dn[R + n];
+    const T d8 = md[R + n] - md[R - n];
+    const T d2 = up[R] - dn[R];
     gx += b * (wd * (d1 - d3) + wa * d8);
     gy += b * (wd * (d1 + d3) + wa * d2);
   }
 }
 
 // d vx/dx + d vy/dy of a ring vector field.
-template <int R, int RING, int NTX, typename T>
-__device__ __forceinline__ T ring_div(const T (*sx)[NTX], const T (*sy)[NTX], int row, int tx) {
+template <int R, int RING, int STRIDE, typename T>
+__device__ __forceinline__ T ring_div(const T* sx, const T* sy, int row, int tx) {
   const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
   T acc = T(0);
-  const T* mdx = &sx[ring_row<RING>(row)][tx];
+  const T* mdx = sx + ring_row<RING>(row) * STRIDE + (tx - R);
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
     const T b = stencil_b<R, T>(n);
-    const T* upx = &sx[ring_row<RING>(row + n)][tx];
-    const T* dnx = &sx[ring_row<RING>(row - n)][tx];
-    const T* upy = &sy[ring_row<RING>(row + n)][tx];
-    const T* dny = &sy[ring_row<RING>(row - n)][tx];
-    const T d1 = upx[n] - dnx[-n];
-    const T d3 = upx[-n] - dnx[n];
-    const T d8 = mdx[n] - mdx[-n];
-    const T e1 = upy[n] - dny[-n];
-    const T e3 = upy[-n] - dny[n];
-    const T e2 = upy[0] - dny[0];
+    const T* upx = sx + ring_row<RING>(row + n) * STRIDE + (tx - R);
+    const T* dnx = sx + ring_row<RING>(row - n) * STRIDE + (tx - R);
+    const T* upy = sy + ring_row<RING>(row + n) * STRIDE + (tx - R);
+    const T* dny = sy + ring_row<RING>(row - n) * STRIDE + (tx - R);
+    const T d1 = upx[R + n] - dnx[R - n];
+    const T d3 = upx[R - n] - dnx[R + n];
+    const T d8 = mdx[R + n] - mdx[R - n];
+    const T e1 = upy[R + n] - dny[R - n];
+    const T e3 = upy[R - n] - dny[R + n];
+    const T e2 = upy[R] - dny[R];
     acc += b * (wd * ((d1 - d3) + (e1 + e3)) + wa * (d8 + e2));
   }
   return acc;
 }
 
+// LDS rings, laid out [ring row][field][column] so that every field of one
+// row is within a small immediate offset of one address.
+enum {
+  // stencil operands
+  F_RHON, F_MX, F_MY, F_UX, F_UY, F_PHI,
+  // values handed from one band to a later one at the same site
+  F_RR, F_RB,    // colour densities, band M -> bands U, O
+  F_GNX, F_GNY,  // grad rho^N, band N -> band U
+  F_GX, F_GY,    // force G, band U -> band O
+  F_IRHO,        // 1/rho, band U -> band O
+  NFIELD
+};
+
 template <typename T, int NTX, int RING>
 struct Smem {
-  // stencil operands
-  T rhoN[RING][NTX];
-  T mx[RING][NTX];
-  T my[RING][NTX];
-  T ux[RING][NTX];
-  T uy[RING][NTX];
-  T phi[RING][NTX];
-  // values handed from one band to a later one at the same site
-  T rR[RING][NTX], rB[RING][NTX];    // colour densities, band M -> bands U, O
-  T gnx[RING][NTX], gny[RING][NTX];  // grad rho^N, band N -> band U
-  T Gx[RING][NTX], Gy[RING][NTX];    // force G, band U -> band O
-  T irho[RING][NTX];                 // 1/rho, band U -> band O
+  static constexpr int STRIDE = NFIELD * NTX;  // elements per ring row
+  static constexpr int PAD = 16 / sizeof(T) > 3 ? 16 / sizeof(T) : 3;  // keeps tx - 3 inside the array
+  T pad[PAD];
+  T d[RING * STRIDE];
+  __device__ __forceinline__ T& at(int field, int row, int tx) { return d[row * STRIDE + field * NTX + tx]; }
+  __device__ __forceinline__ const T* field(int f) const { return d + f * NTX; }
 };
 
 // Register state of one thread: the nine total populations of the rows it
@@ -590,6 +600,7 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
                                            RowTrack<WALLS>& tU) {
   using PP = Pipe<NR>;
   constexpr int RING = PP::RING;
+  using SM = Smem<T, NTX, RING>;
   const Geom& g = a.g;
   const Coef<T>& c = a.c;
   // ty passes through an opaque scalar move each iteration, so the ring-row
@@ -615,9 +626,9 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
 #pragma unroll
     for (int i = 0; i < 9; ++i) rf[i] = pr[i] + pb[i];
     const int rm = ring_row<RING>(rowM);
-    sm.rR[rm][tx] = rR;
-    sm.rB[rm][tx] = rB;
-    sm.rhoN[rm][tx] = colour_index(rR * c.inv_rho0R, rB * c.inv_rho0B);
+    sm.at(F_RR, rm, tx) = rR;
+    sm.at(F_RB, rm, tx) = rB;
+    sm.at(F_RHON, rm, tx) = colour_index(rR * c.inv_rho0R, rB * c.inv_rho0B);
     // prefetch the next band-M row (after the last iteration: a row never used)
     gather_words<ST, WALLS>(src, g, tM.phys(g), t.cols, st.pw);
     tM.advance(g);
@@ -627,13 +638,13 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   // ---- band N: grad rho^N and director m -------------------------------------
   if (it >= PP::ITN && tx >= RG && tx < NTX - RG) {
     T gx, gy;
-    ring_grad<RG, RING, NTX>(sm.rhoN, rowN, tx, gx, gy);
+    ring_grad<RG, RING, SM::STRIDE>(sm.field(F_RHON), rowN, tx, gx, gy);
     const T is = rsqrt_pos(gx * gx + gy * gy + c.eps2);
     const int rn = ring_row<RING>(rowN);
-    sm.mx[rn][tx] = gx * is;
-    sm.my[rn][tx] = gy * is;
-    sm.gnx[rn][tx] = gx;
-    sm.gny[rn][tx] = gy;
+    sm.at(F_MX, rn, tx) = gx * is;
+    sm.at(F_MY, rn, tx) = gy * is;
+    sm.at(F_GNX, rn, tx) = gx;
+    sm.at(F_GNY, rn, tx) = gy;
   }
   __syncthreads();
 
@@ -641,9 +652,9 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   if (it >= PP::ITU) {
     const T* rf = st.rf[sU];
     const int ru = ring_row<RING>(rowU);
-    const T rR = sm.rR[ru][tx], rB = sm.rB[ru][tx];
+    const T rR = sm.at(F_RR, ru, tx), rB = sm.at(F_RB, ru, tx);
     const T rho = rR + rB;
-    sm.phi[ru][tx] = c.c06R * rR + c.phiB * rB - rho * T(1.0 / 3.0);
+    sm.at(F_PHI, ru, tx) = c.c06R * rR + c.phiB * rB - rho * T(1.0 / 3.0);
     if (tx >= RG + RK && tx < NTX - RG - RK) {
       const int p = tU.phys(g);
       const bool refl = tU.refl(g);
@@ -651,13 +662,13 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
       if (c.fixed_K) {
         K = c.K_fixed;
       } else {
-        K = -ring_div<RK, RING, NTX>(sm.mx, sm.my, rowU, tx);  // K = div n, n = -m
+        K = -ring_div<RK, RING, SM::STRIDE>(sm.field(F_MX), sm.field(F_MY), rowU, tx);  // K = div n, n = -m
       }
       if (MODE == MODE_ADJ) {
         const int v = base + PP::LU;  // virtual row of band U
         if (t.own && v >= t.ya && v < t.yb) a.out_save[SV_K * g.plane + p * g.nx + t.xg] = K;
       }
-      const T gnx = sm.gnx[ru][tx], gny = sm.gny[ru][tx];
+      const T gnx = sm.at(F_GNX, ru, tx), gny = sm.at(F_GNY, ru, tx);
       T Gx = c.half_sigma * K * gnx + c.gx;
       T Gy = c.half_sigma * K * gny + (refl ? -c.gy : c.gy);
       if (a.force) {
@@ -669,11 +680,11 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
       momenta(rf, jx, jy);
       if (refl) jy = -jy;   // mirror image: the y-momentum changes sign
       const T ir = recip(rho);
-      sm.ux[ru][tx] = (jx + T(0.5) * Gx) * ir;
-      sm.uy[ru][tx] = (jy + T(0.5) * Gy) * ir;
-      sm.Gx[ru][tx] = Gx;
-      sm.Gy[ru][tx] = Gy;
-      sm.irho[ru][tx] = ir;
+      sm.at(F_UX, ru, tx) = (jx + T(0.5) * Gx) * ir;
+      sm.at(F_UY, ru, tx) = (jy + T(0.5) * Gy) * ir;
+      sm.at(F_GX, ru, tx) = Gx;
+      sm.at(F_GY, ru, tx) = Gy;
+      sm.at(F_IRHO, ru, tx) = ir;
     }
   }
   tU.advance(g);
@@ -682,20 +693,20 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   // ---- band O: correction, collision, recolour, store ----------------------
   if (it >= PP::IT0 && t.own && base < t.yb) {
     T dPx, dPy;
-    ring_grad<RP, RING, NTX>(sm.phi, rowO, tx, dPx, dPy);
+    ring_grad<RP, RING, SM::STRIDE>(sm.field(F_PHI), rowO, tx, dPx, dPy);
     __builtin_amdgcn_sched_barrier(0);  // bound register pressure: finish one stencil before the next
-    const T theta = ring_div<RU, RING, NTX>(sm.ux, sm.uy, rowO, tx);
+    const T theta = ring_div<RU, RING, SM::STRIDE>(sm.field(F_UX), sm.field(F_UY), rowO, tx);
     __builtin_amdgcn_sched_barrier(0);
     const int ro = ring_row<RING>(rowO);
     const int p = WALLS ? base + 1 : base;
     if (MODE == MODE_ADJ) {
       T* sv = a.out_save + p * g.nx + t.xg;
-      sv[SV_GNX * g.plane] = sm.gnx[ro][tx];
-      sv[SV_GNY * g.plane] = sm.gny[ro][tx];
+      sv[SV_GNX * g.plane] = sm.at(F_GNX, ro, tx);
+      sv[SV_GNY * g.plane] = sm.at(F_GNY, ro, tx);
     }
-    collide_store<ST, T, MODE>(a, dst, st.rf[sO], sm.rR[ro][tx], sm.rB[ro][tx], sm.ux[ro][tx], sm.uy[ro][tx],
-                                 sm.Gx[ro][tx], sm.Gy[ro][tx], sm.irho[ro][tx], dPx, dPy, theta,
-                                 sm.rhoN[ro][tx], sm.mx[ro][tx], sm.my[ro][tx], p, t);
+    collide_store<ST, T, MODE>(a, dst, st.rf[sO], sm.at(F_RR, ro, tx), sm.at(F_RB, ro, tx), sm.at(F_UX, ro, tx), sm.at(F_UY, ro, tx),
+                                 sm.at(F_GX, ro, tx), sm.at(F_GY, ro, tx), sm.at(F_IRHO, ro, tx), dPx, dPy, theta,
+                                 sm.at(F_RHON, ro, tx), sm.at(F_MX, ro, tx), sm.at(F_MY, ro, tx), p, t);
   }
 }
 

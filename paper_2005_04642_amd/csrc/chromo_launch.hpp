@@ -183,7 +183,8 @@ hipError_t mass(const lbm_params& p, const Geom& g, const void* pops, double* pa
 // ---------------------------------------------------------------------------
 // adjoint: save pass of the step kernel, then the five passes of
 // chromo_adjoint.hpp.  ws holds adj::WS_PLANES planes of the arithmetic type
-// followed, at the next multiple of 256 bytes, by adj::red_blocks() doubles.
+// followed, at the next multiple of 256 bytes, by adj::red_blocks() + adj::RED2
+// doubles.
 // ---------------------------------------------------------------------------
 template <typename S>
 hipError_t adjoint(const lbm_params& p, const Geom& g0, const void* pops, const void* force, const void* lam_next,
@@ -207,8 +208,13 @@ hipError_t adjoint(const lbm_params& p, const Geom& g0, const void* pops, const 
   const adj::Radii r = {p.stencil[0], p.stencil[1], p.stencil[2], p.stencil[3]};
   hipLaunchKernelGGL(adj::force_kernel<T>, grid, dim3(256), 0, s, g, a.c, (T)p.sigma, r, (const T*)sv,
                      (const T*)A, B, static_cast<T*>(dforce), part);
-  if (dsigma) hipLaunchKernelGGL(adj::sum_into_kernel, dim3(1), dim3(256), 0, s, (const double*)part,
-                                 adj::red_blocks(g.nx, g.ny), dsigma);
+  if (dsigma) {
+    const int n = adj::red_blocks(g.nx, g.ny);
+    const int n2 = n < adj::RED2 ? n : adj::RED2;
+    double* part2 = part + n;
+    hipLaunchKernelGGL(adj::partial_sum_kernel, dim3(n2), dim3(256), 0, s, (const double*)part, n, part2);
+    hipLaunchKernelGGL(adj::sum_into_kernel, dim3(1), dim3(256), 0, s, (const double*)part2, n2, dsigma);
+  }
   hipLaunchKernelGGL(adj::director_kernel<T>, grid, dim3(256), 0, s, g, a.c, r, (const T*)sv, (const T*)A,
                      (const T*)B, C);
   hipLaunchKernelGGL(adj::colour_kernel<T>, grid, dim3(256), 0, s, g, a.c, r, (const T*)sv, (const T*)A,
