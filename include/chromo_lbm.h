@@ -20,7 +20,9 @@
  * population buffers is live).  Nothing here allocates device memory.
  *
  * Populations: two buffers of lbm_pops_bytes() bytes each, holding NW words
- * per site in NW planes [NW][ny][nx] (x fastest).  The live buffer holds, for
+ * per site, laid out [ny][NW][nx] (x fastest): each lattice row is NW
+ * consecutive runs of nx words, word q of site (x, y) at index
+ * (y NW + q) nx + x.  The live buffer holds, for
  * every site r and link i, the post-recolour populations of the previous step
  * at their source site (a "pull" layout): the pre-collision population of the
  * current step is C_i(r) = buf_i(r - c_i), or buf_opp(i)(r) when r - c_i is a
@@ -158,7 +160,7 @@ int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream);
 /* ---- adjoint (reverse-mode derivative of lbm_step) ------------------------
  * Provided for LBM_STORAGE_F64 and LBM_STORAGE_F32 on periodic lattices
  * (walls_y = 0); other cases return LBM_ENOTIMPL.  Adjoint buffers have the
- * layout of an F64/F32 population buffer ([colour 2][link 9][ny][nx], the
+ * layout of an F64/F32 population buffer ([ny][colour 2][link 9][nx], the
  * arithmetic type), aligned with the pull layout: adj[C][i](s) is dL/d of the
  * stored word buf[C][i](s).  The step that is differentiated is the one
  * lbm_step performs with the handle's parameters and force field. */

@@ -44,9 +44,8 @@ class _Rollout(torch.autograd.Function):
     def backward(ctx, grad_rhoN):
         sim = ctx.sim
         T = sim.dtype
-        shape = ctx.final.shape
-        lam = torch.empty(shape, dtype=T, device=sim.device)
-        lam_prev = torch.empty_like(lam)
+        lam = sim.pops_like()
+        lam_prev = sim.pops_like()
         sim.rhoN_adjoint(ctx.final, grad_rhoN.to(T), lam)
         dsigma = torch.zeros(1, dtype=torch.float64, device=sim.device)
         dforce = torch.zeros((2, sim.ny, sim.nx), dtype=T, device=sim.device)

@@ -426,7 +426,7 @@ __global__ void __launch_bounds__(256) push_kernel(Geom g, const T* __restrict__
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
-  const int P = g.plane, site = y * g.nx + x;
+  const int P = g.plane;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int cx = link_cx(i), cy = link_cy(i);
@@ -435,8 +435,8 @@ __global__ void __launch_bounds__(256) push_kernel(Geom g, const T* __restrict__
     ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
     const int r = ys * g.nx + xs;
     const T common = A[(A_F + i) * P + r] + T(cx) * B[B_JX * P + r] + T(cy) * B[B_JY * P + r];
-    out[i * P + site] = common + D[D_RR * P + r];
-    out[(9 + i) * P + site] = common + D[D_RB * P + r];
+    out[((size_t)y * 18 + i) * g.nx + x] = common + D[D_RR * P + r];
+    out[((size_t)y * 18 + 9 + i) * g.nx + x] = common + D[D_RB * P + r];
   }
 }
 
@@ -452,7 +452,6 @@ __global__ void __launch_bounds__(256) rhoN_adjoint_kernel(const void* popsv, Ge
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
-  const int P = g.plane;
   const int E = (int)sizeof(typename S::W);
   // every site needs rho_R, rho_B of its 9 neighbours r = s + c_i
 #pragma unroll
@@ -477,8 +476,8 @@ __global__ void __launch_bounds__(256) rhoN_adjoint_kernel(const void* popsv, Ge
     const T a = rR * c.inv_rho0R, b = rB * c.inv_rho0B;
     const T is = T(1) / (a + b);
     const T wgt = T(2) * lrN[ys * g.nx + xs] * is * is;
-    out[i * P + y * g.nx + x] = wgt * b * c.inv_rho0R;
-    out[(9 + i) * P + y * g.nx + x] = -wgt * a * c.inv_rho0B;
+    out[((size_t)y * 18 + i) * g.nx + x] = wgt * b * c.inv_rho0R;
+    out[((size_t)y * 18 + 9 + i) * g.nx + x] = -wgt * a * c.inv_rho0B;
   }
 }
 
@@ -493,7 +492,7 @@ __global__ void __launch_bounds__(256) init_adjoint_kernel(const T* __restrict__
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
-  const int P = g.plane, site = y * g.nx + x;
+  const int site = y * g.nx + x;
   const T rn = rhoN0[site];
   const T rR = rho0R * (T(1) + rn) * T(0.5), rB = rho0B * (T(1) - rn) * T(0.5);
   const T dR = rho0R * T(0.5), dB = -rho0B * T(0.5);
@@ -507,7 +506,6 @@ __global__ void __launch_bounds__(256) init_adjoint_kernel(const T* __restrict__
     int xs = x - link_cx(i), ys = y - link_cy(i);
     xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
     ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
-    const int s = ys * g.nx + xs;
     T phi, dphi;
     if (i == 0) {
       phi = a0 * irho;
@@ -517,7 +515,8 @@ __global__ void __launch_bounds__(256) init_adjoint_kernel(const T* __restrict__
       phi = wt * mv * irho;
       dphi = wt * (dmv - mv * irho * drho) * irho;
     }
-    acc += lam0[i * P + s] * (dR * phi + rR * dphi) + lam0[(9 + i) * P + s] * (dB * phi + rB * dphi);
+    const T* l = lam0 + (size_t)ys * 18 * g.nx + xs;  // [y][C i][x], as the populations
+    acc += l[i * g.nx] * (dR * phi + rR * dphi) + l[(9 + i) * g.nx] * (dB * phi + rB * dphi);
   }
   out[site] += acc;
 }

@@ -93,8 +93,8 @@ int validate(const lbm_params* p) {
 }
 
 // Strips of at most NTX-2H columns; chunks of rows such that all tiles run in
-// a single wave of workgroups (one workgroup fills a CU: its 8 wavefronts use
-// the whole register file), i.e. nstrips * nchunks <= number of CUs, with
+// a single wave of workgroups (one workgroup fills a CU: its LDS rings take
+// nearly all of the CU's LDS), i.e. nstrips * nchunks <= number of CUs, with
 // chunks no shorter than 24 rows.
 chromo::Geom plan(const lbm_params& p, int ncu, int ntx) {
   chromo::Geom g;

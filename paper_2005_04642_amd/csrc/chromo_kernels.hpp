@@ -72,7 +72,7 @@ struct Geom {
   int TX, nstrips, TY, nchunks;
   int plane;               // nx * ny
   // set per storage format and workgroup shape at launch:
-  unsigned pb, rb;         // bytes of one plane and of one row of a plane
+  unsigned pb, rb;         // byte strides of the storage words: word q of row y at q pb + y rb
   int period;              // period of the virtual row index: ny, or 2 F with walls
   int nr_mod;              // rows per march iteration, modulo period
 };
@@ -489,11 +489,12 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
   if (MODE == MODE_ADJ) {
     const int P = a.g.plane;
     const int site = p * a.g.nx + t.xg;
+    const T* ln = a.lam_next + (size_t)p * 18 * a.g.nx + t.xg;  // [y][C i][x], as the populations
     T lR[9], lB[9], out[adj::A_N];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      lR[i] = a.lam_next[i * P + site];
-      lB[i] = a.lam_next[(9 + i) * P + site];
+      lR[i] = ln[i * a.g.nx];
+      lB[i] = ln[(9 + i) * a.g.nx];
     }
     adj::local_backward(c, f, rR, rB, ux, uy, Gx, Gy, dPx, dPy, theta, rhoN, mx, my, lR, lB, out);
 #pragma unroll
@@ -836,9 +837,9 @@ __global__ void __launch_bounds__(256) stream_only_kernel(const void* src, void*
   cols.p = (x == g.nx - 1 ? 0 : x + 1) * E;
   W v[S::NW];
   gather_words_any<S>(make_rsrc<S>(src, g.plane), g, p, cols, v);
-  W* d = static_cast<W*>(dst) + p * g.nx + x;
+  W* d = static_cast<W*>(dst) + (size_t)p * S::NW * g.nx + x;
 #pragma unroll
-  for (int q = 0; q < S::NW; ++q) d[q * g.plane] = v[q];
+  for (int q = 0; q < S::NW; ++q) d[q * g.nx] = v[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -898,7 +899,7 @@ __global__ void __launch_bounds__(256) init_kernel(const typename S::math* __res
     encode<S>(R, B, c, w);
   }
 #pragma unroll
-  for (int q = 0; q < S::NW; ++q) dst[q * g.plane + y * g.nx + x] = w[q];
+  for (int q = 0; q < S::NW; ++q) dst[((size_t)y * S::NW + q) * g.nx + x] = w[q];
 }
 
 // ---------------------------------------------------------------------------
@@ -920,10 +921,11 @@ __global__ void __launch_bounds__(256) mass_partial_kernel(const void* popsv, Ge
   double sr = 0.0, sb = 0.0;
   for (long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x; s < nsite;
        s += (long long)gridDim.x * blockDim.x) {
-    const int off = (int)(row0 * g.nx + s);
+    const int y = row0 + (int)(s / g.nx), x = (int)(s % g.nx);
+    const typename S::W* r = pops + (size_t)y * S::NW * g.nx + x;
     typename S::W w[S::NW];
 #pragma unroll
-    for (int q = 0; q < S::NW; ++q) w[q] = pops[q * g.plane + off];
+    for (int q = 0; q < S::NW; ++q) w[q] = r[q * g.nx];
     T R[9], B[9];
     decode<S>(w, c, R, B);
 #pragma unroll

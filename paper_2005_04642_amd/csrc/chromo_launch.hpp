@@ -61,13 +61,14 @@ Coef<typename S::math> make_coef(const lbm_params& p) {
 }
 
 
-// Per-format geometry: byte strides of the storage words and the row period
-// of the march.
+// Per-format geometry: byte strides of the storage words ([y][word][x]: the
+// NW words of one lattice row are NW consecutive runs of nx words) and the row
+// period of the march.
 template <typename S>
 Geom geom_for(const Geom& g0) {
   Geom g = g0;
-  g.pb = (unsigned)g.plane * (unsigned)sizeof(typename S::W);
-  g.rb = (unsigned)g.nx * (unsigned)sizeof(typename S::W);
+  g.pb = (unsigned)g.nx * (unsigned)sizeof(typename S::W);
+  g.rb = (unsigned)S::NW * g.pb;
   g.period = g.walls ? 2 * g.F : g.ny;
   g.nr_mod = Shape<S>::nr % g.period;
   return g;

@@ -312,31 +312,66 @@ class Simulation:
             self._adj_ws = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
         return self._adj_ws
 
+    def pops_like(self):
+        """New [2, 9, ny, nx] tensor of the arithmetic type whose memory has the
+        library's layout ([ny][colour][link][nx]): population states and
+        adjoint buffers in this form pass to the library without a copy."""
+        t = self.torch.empty((self.ny, 2, 9, self.nx), dtype=self.dtype, device=self.device)
+        return t.permute(1, 2, 0, 3)
+
+    def _is_lib_layout(self, t):
+        n = self.nx
+        return (tuple(t.shape) == (2, 9, self.ny, n) and t.dtype == self.dtype and t.device == self.device
+                and tuple(t.stride()) == (9 * n, n, 18 * n, 1))
+
+    def _in(self, t):
+        """t ([2, 9, ny, nx]) in the library's memory layout (copied if needed)."""
+        if self._is_lib_layout(t):
+            return t
+        out = self.pops_like()
+        out.copy_(t)
+        return out
+
+    def _call_out(self, t, fn):
+        """Run fn(pointer) that writes a [2, 9, ny, nx] buffer into t."""
+        if self._is_lib_layout(t):
+            fn(t.data_ptr())
+        else:
+            tmp = self.pops_like()
+            fn(tmp.data_ptr())
+            t.copy_(tmp)
+
     def adjoint_step(self, pops_t, adj_next, adj_out, dsigma=None, dforce=None):
         """adj_out = dL/dpops_t given adj_next = dL/dpops_{t+1}; adds dL/dsigma
         into dsigma (float64 device tensor of one element) and dL/dG_ext into
-        dforce ([2, ny, nx]) when given."""
+        dforce ([2, ny, nx]) when given.  States and adjoints are [2, 9, ny, nx]
+        tensors (zero-copy when laid out as pops_like())."""
         ws = self.adjoint_workspace()
-        lbm_adjoint_step(self.h, pops_t.data_ptr(), adj_next.data_ptr(), adj_out.data_ptr(), ws.data_ptr(),
-                         ws.numel(), None if dsigma is None else dsigma.data_ptr(),
-                         None if dforce is None else dforce.data_ptr(), self.stream())
+        S, L = self._in(pops_t), self._in(adj_next)
+        self._call_out(adj_out, lambda ptr: lbm_adjoint_step(
+            self.h, S.data_ptr(), L.data_ptr(), ptr, ws.data_ptr(), ws.numel(),
+            None if dsigma is None else dsigma.data_ptr(), None if dforce is None else dforce.data_ptr(),
+            self.stream()))
 
     def rhoN_adjoint(self, pops, dL_drhoN, adj_out):
-        lbm_rhoN_adjoint(self.h, pops.data_ptr(), dL_drhoN.contiguous().data_ptr(), adj_out.data_ptr(),
-                         self.stream())
+        S, g = self._in(pops), dL_drhoN.contiguous()
+        self._call_out(adj_out, lambda ptr: lbm_rhoN_adjoint(self.h, S.data_ptr(), g.data_ptr(), ptr,
+                                                             self.stream()))
 
     def init_adjoint(self, adj0, dL_drhoN0):
-        lbm_init_adjoint(self.h, self.rhoN0.data_ptr(), adj0.data_ptr(), dL_drhoN0.data_ptr(), self.stream())
+        L = self._in(adj0)
+        lbm_init_adjoint(self.h, self.rhoN0.data_ptr(), L.data_ptr(), dL_drhoN0.data_ptr(), self.stream())
 
     def live_words(self):
-        """View [NW, ny, nx] of the live buffer (storage words, pull layout)."""
-        return self.pops[lbm_current_pops(self.h)].view(-1, self.ny, self.nx)
+        """View [NW, ny, nx] of the live buffer (storage words, pull layout;
+        the memory itself is [ny][NW][nx])."""
+        return self.pops[lbm_current_pops(self.h)].view(self.ny, -1, self.nx).permute(1, 0, 2)
 
     def live_pops(self):
         """View [2, 9, ny, nx] of the live buffer (F64/F32 storage only)."""
         if self.storage not in ("f32", "f64"):
             raise ValueError("live_pops() needs F32/F64 storage; use live_words() for %s" % self.storage)
-        return self.pops[lbm_current_pops(self.h)].view(2, 9, self.ny, self.nx)
+        return self.pops[lbm_current_pops(self.h)].view(self.ny, 2, 9, self.nx).permute(1, 2, 0, 3)
 
     @property
     def steps(self):
@@ -436,7 +471,8 @@ class Batch:
         nx, ny = self.shapes[k]
         live = self.lib.lbm_batch_current_pops(self.h)
         n = 18 * nx * ny * (8 if self.storage == "f64" else 4)
-        return self.pops[live][self.offsets[k]:self.offsets[k] + n].view(self.dtype).view(2, 9, ny, nx)
+        return self.pops[live][self.offsets[k]:self.offsets[k] + n].view(self.dtype).view(ny, 2, 9, nx).permute(
+            1, 2, 0, 3)
 
     def fields(self, k):
         t = self.torch
