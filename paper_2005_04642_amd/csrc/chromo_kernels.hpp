@@ -221,18 +221,21 @@ __device__ __forceinline__ void store_word(W v, __amdgpu_buffer_rsrc_t r, int vo
   }
 }
 
-// words -> populations (R_0..R_8, B_0..B_8)
+// words -> populations (R_0..R_8, B_0..B_8) and, when F is given, the totals
+// f_i = R_i + B_i (the 16-bit formats carry f_i itself for the moving links)
 template <typename S, typename T>
-__device__ __forceinline__ void decode(const typename S::W* w, const Coef<T>& c, T* R, T* B) {
+__device__ __forceinline__ void decode(const typename S::W* w, const Coef<T>& c, T* R, T* B, T* F = nullptr) {
   if constexpr (!is_ofs16<S>::value) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       R[i] = w[i];
       B[i] = w[9 + i];
+      if (F) F[i] = R[i] + B[i];
     }
   } else {
     R[0] = __builtin_bit_cast(float, w[0]);
     B[0] = __builtin_bit_cast(float, w[1]);
+    if (F) F[0] = R[0] + B[0];
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       const int k = link_class(i);
@@ -243,6 +246,7 @@ __device__ __forceinline__ void decode(const typename S::W* w, const Coef<T>& c,
       const bool blue = (v & 0x40000000u) != 0u;
       R[i] = blue ? o : s;
       B[i] = blue ? s : o;
+      if (F) F[i] = f;
     }
   }
 }
@@ -355,6 +359,16 @@ __device__ __forceinline__ T stencil_b(int n) {
   if (R == 1) return T(3);
   return n == 1 ? T(4.5) : (n == 2 ? T(-0.9) : T(0.1));
 }
+// b_N w_i for the diagonal (w = 1/36) and axis (w = 1/9) links, each product
+// formed in double and rounded once to T
+template <int R, typename T>
+__device__ __forceinline__ T stencil_bd(int n) {
+  return T(stencil_b<R, double>(n) * (1.0 / 36.0));
+}
+template <int R, typename T>
+__device__ __forceinline__ T stencil_ba(int n) {
+  return T(stencil_b<R, double>(n) * (1.0 / 9.0));
+}
 
 // (d/dx, d/dy) of a ring field at (ring row `row`, column tx); s points at the
 // field's first row, successive ring rows are STRIDE elements apart.  Row
@@ -362,33 +376,33 @@ __device__ __forceinline__ T stencil_b(int n) {
 // non-negative (LDS instruction offsets are unsigned).
 template <int R, int RING, int STRIDE, typename T>
 __device__ __forceinline__ void ring_grad(const T* s, int row, int tx, T& gx, T& gy) {
-  const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
   gx = T(0);
   gy = T(0);
   const T* md = s + ring_row<RING>(row) * STRIDE + (tx - R);
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
-    const T b = stencil_b<R, T>(n);
+    const T bd = stencil_bd<R, T>(n), ba = stencil_ba<R, T>(n);
     const T* up = s + ring_row<RING>(row + n) * STRIDE + (tx - R);
     const T* dn = s + ring_row<RING>(row - n) * STRIDE + (tx - R);
     const T d1 = up[R + n] - dn[R - n];
     const T d3 = up[R - n] - dn[R + n];
     const T d8 = md[R + n] - md[R - n];
     const T d2 = up[R] - dn[R];
-    gx += b * (wd * (d1 - d3) + wa * d8);
-    gy += b * (wd * (d1 + d3) + wa * d2);
+    gx += ba * d8;
+    gx += bd * (d1 - d3);
+    gy += ba * d2;
+    gy += bd * (d1 + d3);
   }
 }
 
 // d vx/dx + d vy/dy of a ring vector field.
 template <int R, int RING, int STRIDE, typename T>
 __device__ __forceinline__ T ring_div(const T* sx, const T* sy, int row, int tx) {
-  const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
   T acc = T(0);
   const T* mdx = sx + ring_row<RING>(row) * STRIDE + (tx - R);
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
-    const T b = stencil_b<R, T>(n);
+    const T bd = stencil_bd<R, T>(n), ba = stencil_ba<R, T>(n);
     const T* upx = sx + ring_row<RING>(row + n) * STRIDE + (tx - R);
     const T* dnx = sx + ring_row<RING>(row - n) * STRIDE + (tx - R);
     const T* upy = sy + ring_row<RING>(row + n) * STRIDE + (tx - R);
@@ -399,7 +413,8 @@ __device__ __forceinline__ T ring_div(const T* sx, const T* sy, int row, int tx)
     const T e1 = upy[R + n] - dny[R - n];
     const T e3 = upy[R - n] - dny[R + n];
     const T e2 = upy[R] - dny[R];
-    acc += b * (wd * ((d1 - d3) + (e1 + e3)) + wa * (d8 + e2));
+    acc += ba * (d8 + e2);
+    acc += bd * ((d1 - d3) + (e1 + e3));
   }
   return acc;
 }
@@ -621,11 +636,9 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   {
     T* rf = st.rf[sM];
     T pr[9], pb[9];
-    decode<ST>(st.pw, c, pr, pb);
+    decode<ST>(st.pw, c, pr, pb, rf);
     T rR = ((pr[0] + pr[2]) + (pr[4] + pr[6])) + ((pr[1] + pr[3]) + (pr[5] + pr[7])) + pr[8];
     T rB = ((pb[0] + pb[2]) + (pb[4] + pb[6])) + ((pb[1] + pb[3]) + (pb[5] + pb[7])) + pb[8];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) rf[i] = pr[i] + pb[i];
     const int rm = ring_row<RING>(rowM);
     sm.at(F_RR, rm, tx) = rR;
     sm.at(F_RB, rm, tx) = rB;
