@@ -100,11 +100,11 @@ def copy_roof(n, params, rn, torch, storage, steps=200):
             "GB_s": round(BYTES_PER_LU[storage] * n * n / (ms * 1e-3) / 1e9, 1)}
 
 
-def adjoint_measure(n, params, rn, torch, steps=20):
+def adjoint_measure(n, params, rn, torch, steps=20, force=None):
     """Adjoint step (lbm_adjoint_step, FP32 storage, FP64 dL/dsigma) against the
     forward step on the same lattice and state."""
     from paper_2005_04642_amd import lbm
-    sim = lbm.Simulation(n, n, params, rn, storage="f32", device="cuda:0")
+    sim = lbm.Simulation(n, n, params, rn, storage="f32", device="cuda:0", force=force)
     sim.step(20)
     S = sim.live_pops().clone()
     lam = torch.full_like(S, 1e-3)
@@ -132,13 +132,12 @@ def adjoint_measure(n, params, rn, torch, steps=20):
             "ratio": round(ms_fwd / ms_adj, 4)}
 
 
-def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
-    """Gradient of an interface-shape loss over a checkpointed rollout: 512^2
-    periodic, circle of radius 128 to a seeded ellipse target of equal area,
-    8 Gaussian force bumps (amplitude 1e-6); FP32 storage, FP64 dL/dsigma.
-    Returns forward and backward (recompute + adjoint) times."""
+def drop_to_ellipse(n=512):
+    """The adjoint workload: n^2 periodic, circle of radius n/4 to a seeded
+    ellipse target of equal area, 8 Gaussian force bumps (amplitude 1e-6).
+    Returns (rhoN0, target, force [2, n, n], params)."""
     import numpy as np
-    from paper_2005_04642_amd import adjoint, workloads as Wk
+    from paper_2005_04642_amd import workloads as Wk
     rng = np.random.default_rng(2)
     yy, xx = np.mgrid[0:n, 0:n]
     c = (n - 1) / 2.0
@@ -155,7 +154,15 @@ def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
         bump = 1e-6 * np.exp(-((xx - bx) ** 2 + (yy - by) ** 2) / (2 * 24.0 ** 2))
         force[0] += bump * np.cos(th)
         force[1] += bump * np.sin(th)
-    params = Wk.base_params(Lambda=10.0, sigma=0.01)
+    return rn0, target, force, Wk.base_params(Lambda=10.0, sigma=0.01)
+
+
+def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
+    """Gradient of an interface-shape loss over a checkpointed rollout of the
+    drop_to_ellipse workload; FP32 storage, FP64 dL/dsigma.  Returns forward
+    and backward (recompute + adjoint) times."""
+    from paper_2005_04642_amd import adjoint
+    rn0, target, force, params = drop_to_ellipse(n)
     dev = "cuda:0"
     rn_t = torch.tensor(rn0, dtype=torch.float32, device=dev, requires_grad=True)
     f_t = torch.tensor(force, dtype=torch.float32, device=dev, requires_grad=True)
@@ -314,6 +321,11 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = dict({"workload": "same lattice and state, one adjoint step vs one forward step, FP32"},
                               **adjoint_measure(n, params, rn, torch))
+        rn_d, _, f_d, p_d = drop_to_ellipse(512)
+        out["adjoint_512"] = dict({"workload": "512^2 drop of the rollout below (with its force field), one adjoint "
+                                               "step vs one forward step, FP32"},
+                                  **adjoint_measure(512, p_d, rn_d, torch, steps=200,
+                                                    force=torch.tensor(f_d, dtype=torch.float32, device="cuda:0")))
         out["adjoint_rollout"] = adjoint_rollout(torch)
     if not args.no_batch:
         out["batch"] = batch_measure(torch)

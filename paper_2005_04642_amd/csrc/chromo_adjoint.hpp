@@ -38,8 +38,8 @@ enum { B_RR, B_RB, B_JX, B_JY, B_K, B_GX, B_GY, B_N };
 enum { C_GX, C_GY, C_N };
 enum { D_RR, D_RB, D_N };
 constexpr int WS_PLANES = SV_N + A_N + B_N + C_N + D_N;
-// FP64 partial sums of dL/dsigma: one per 256-site block of a row, then up to
-// RED2 second-stage sums
+// FP64 partial sums of dL/dsigma, one per 256-site block of a row; the
+// workspace keeps RED2 more doubles of slack
 __host__ __device__ inline int red_blocks(int nx, int ny) { return ((nx + 255) / 256) * ny; }
 constexpr int RED2 = 256;
 
@@ -356,33 +356,38 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, 
   if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = tot;
 }
 
-// in[0..n) -> out[blockIdx.x]: each block sums a contiguous slice (fixed order)
-static __global__ void __launch_bounds__(256) partial_sum_kernel(const double* __restrict__ in, int n,
-                                                                 double* __restrict__ out) {
-  const int per = (n + gridDim.x - 1) / gridDim.x;
-  const int lo = blockIdx.x * per, hi = min(n, lo + per);
-  double v = 0.0;
-  for (int i = lo + threadIdx.x; i < hi; i += blockDim.x) v += in[i];
-  const double tot = block_sum(v);
-  if (threadIdx.x == 0) out[blockIdx.x] = tot;
-}
-
-static __global__ void __launch_bounds__(256) sum_into_kernel(const double* __restrict__ part, int n, double* out) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
-  const double tot = block_sum(v);
-  if (threadIdx.x == 0) *out += tot;
-}
-
 // ---------------------------------------------------------------------------
 // pass 3: K = -div m transposed; m = g / sqrt(|g|^2 + eps^2)
 // ---------------------------------------------------------------------------
+// One extra row of workgroups, dispatched first (blockIdx.y == 0; lattice row y
+// is blockIdx.y - 1): its first workgroup adds the sum of pass 2's
+// per-workgroup dL/dsigma partials to *dsigma while the other workgroups run
+// the pass.  Each thread sums a fixed strided subset in 8 interleaved
+// accumulators, combined in a fixed order (deterministic).
 template <typename T>
 __global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii r, const T* __restrict__ sv,
                                                        const T* __restrict__ A, const T* __restrict__ B,
-                                                       T* __restrict__ C) {
+                                                       T* __restrict__ C, const double* __restrict__ part,
+                                                       int npart, double* dsigma) {
+  if (blockIdx.y == 0) {
+    if (blockIdx.x == 0 && dsigma) {
+      constexpr int U = 8, BS = 256;
+      double v[U] = {};
+      int i = threadIdx.x;
+      for (; i + (U - 1) * BS < npart; i += U * BS) {
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] += part[i + k * BS];
+      }
+#pragma unroll
+      for (int k = 0; k < U - 1; ++k)
+        if (i + k * BS < npart) v[k] += part[i + k * BS];
+      const double tot = block_sum(((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])));
+      if (threadIdx.x == 0) *dsigma += tot;
+    }
+    return;
+  }
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y;
+  const int y = blockIdx.y - 1;
   if (x >= g.nx) return;
   const int P = g.plane, site = y * g.nx + x;
   T kx, ky;

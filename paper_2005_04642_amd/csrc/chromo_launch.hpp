@@ -209,15 +209,9 @@ hipError_t adjoint(const lbm_params& p, const Geom& g0, const void* pops, const 
   const adj::Radii r = {p.stencil[0], p.stencil[1], p.stencil[2], p.stencil[3]};
   hipLaunchKernelGGL(adj::force_kernel<T>, grid, dim3(256), 0, s, g, a.c, (T)p.sigma, r, (const T*)sv,
                      (const T*)A, B, static_cast<T*>(dforce), part);
-  if (dsigma) {
-    const int n = adj::red_blocks(g.nx, g.ny);
-    const int n2 = n < adj::RED2 ? n : adj::RED2;
-    double* part2 = part + n;
-    hipLaunchKernelGGL(adj::partial_sum_kernel, dim3(n2), dim3(256), 0, s, (const double*)part, n, part2);
-    hipLaunchKernelGGL(adj::sum_into_kernel, dim3(1), dim3(256), 0, s, (const double*)part2, n2, dsigma);
-  }
-  hipLaunchKernelGGL(adj::director_kernel<T>, grid, dim3(256), 0, s, g, a.c, r, (const T*)sv, (const T*)A,
-                     (const T*)B, C);
+  // pass 3, plus the sum of pass 2's dL/dsigma partials in one extra row of workgroups
+  hipLaunchKernelGGL(adj::director_kernel<T>, dim3(grid.x, g.ny + 1), dim3(256), 0, s, g, a.c, r, (const T*)sv,
+                     (const T*)A, (const T*)B, C, (const double*)part, adj::red_blocks(g.nx, g.ny), dsigma);
   hipLaunchKernelGGL(adj::colour_kernel<T>, grid, dim3(256), 0, s, g, a.c, r, (const T*)sv, (const T*)A,
                      (const T*)B, (const T*)C, D);
   hipLaunchKernelGGL(adj::push_kernel<T>, grid, dim3(256), 0, s, g, (const T*)A, (const T*)B, (const T*)D,
