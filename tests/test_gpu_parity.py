@@ -246,6 +246,41 @@ def test_layered_channel_parity(storage, tol):
 
 
 # ---------------------------------------------------------------------------
+# 512^2 crop of the emulsion (3 drops), 1000 steps, against the oracle's fields
+# stored by tests/golden/make_emulsion_crop.py (FP64 and FP32 oracle)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_emulsion_crop_1000_steps(storage):
+    import os
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "emulsion_crop512_1000.npz"))
+    n, steps = int(g["n"]), int(g["steps"])
+    rn = Wk.emulsion_crop(n, 3, 0)
+    sim = sim_for(n, n, Wk.config_emulsion(nx=n, ny=n)["params"], rn, storage)
+    m0 = sim.masses()
+    sim.step(steps)
+    f = {k: host(v).astype(np.float64) for k, v in sim.fields().items()}
+    m1 = sim.masses()
+    sim.close()
+    ys, xs = g["ys"], g["xs"]
+
+    def errs(rho, ux, uy):
+        e_rho = float(np.max(np.abs(rho - g["rho64"]) / g["rho64"]))
+        e_u = float(np.max(np.hypot(ux - g["ux64"], uy - g["uy64"])) / g["umax64"])
+        return e_rho, e_u
+
+    e_rho, e_u = errs(f["rho"][ys, xs], f["ux"][ys, xs], f["uy"][ys, xs])
+    floor = errs(g["rho32"].astype(np.float64), g["ux32"].astype(np.float64), g["uy32"].astype(np.float64))
+    print("emulsion crop %s: e_rho %.3e e_u %.3e (fp32 oracle: %.3e %.3e)" % (storage, e_rho, e_u, *floor))
+    dm = max(abs(m1[0] - m0[0]) / m0[0], abs(m1[1] - m0[1]) / m0[1])
+    if storage == "f64":
+        assert e_rho < 1e-11 and e_u < 1e-11 and dm < 1e-13
+    else:
+        assert e_rho < FP32_TOL_RHO and e_u < FP32_TOL_U and dm < 1e-6
+        assert e_rho <= floor[0] and e_u <= floor[1]
+
+
+# ---------------------------------------------------------------------------
 # full-size emulsion: sampled sites of the benchmarked launch
 # ---------------------------------------------------------------------------
 
