@@ -371,23 +371,23 @@ __device__ __forceinline__ T stencil_ba(int n) {
 }
 
 // (d/dx, d/dy) of a ring field at (ring row `row`, column tx); s points at the
-// field's first row, successive ring rows are STRIDE elements apart.  Row
-// pointers start R columns left of tx so that every column offset is
-// non-negative (LDS instruction offsets are unsigned).
-template <int R, int RING, int STRIDE, typename T>
+// field's first element, successive ring rows are STRIDE elements apart and
+// successive columns CS.  Row pointers start R columns left of tx so that
+// every column offset is non-negative (LDS instruction offsets are unsigned).
+template <int R, int RING, int STRIDE, int CS, typename T>
 __device__ __forceinline__ void ring_grad(const T* s, int row, int tx, T& gx, T& gy) {
   gx = T(0);
   gy = T(0);
-  const T* md = s + ring_row<RING>(row) * STRIDE + (tx - R);
+  const T* md = s + ring_row<RING>(row) * STRIDE + (tx - R) * CS;
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
     const T bd = stencil_bd<R, T>(n), ba = stencil_ba<R, T>(n);
-    const T* up = s + ring_row<RING>(row + n) * STRIDE + (tx - R);
-    const T* dn = s + ring_row<RING>(row - n) * STRIDE + (tx - R);
-    const T d1 = up[R + n] - dn[R - n];
-    const T d3 = up[R - n] - dn[R + n];
-    const T d8 = md[R + n] - md[R - n];
-    const T d2 = up[R] - dn[R];
+    const T* up = s + ring_row<RING>(row + n) * STRIDE + (tx - R) * CS;
+    const T* dn = s + ring_row<RING>(row - n) * STRIDE + (tx - R) * CS;
+    const T d1 = up[(R + n) * CS] - dn[(R - n) * CS];
+    const T d3 = up[(R - n) * CS] - dn[(R + n) * CS];
+    const T d8 = md[(R + n) * CS] - md[(R - n) * CS];
+    const T d2 = up[R * CS] - dn[R * CS];
     gx += ba * d8;
     gx += bd * (d1 - d3);
     gy += ba * d2;
@@ -396,31 +396,33 @@ __device__ __forceinline__ void ring_grad(const T* s, int row, int tx, T& gx, T&
 }
 
 // d vx/dx + d vy/dy of a ring vector field.
-template <int R, int RING, int STRIDE, typename T>
+template <int R, int RING, int STRIDE, int CS, typename T>
 __device__ __forceinline__ T ring_div(const T* sx, const T* sy, int row, int tx) {
   T acc = T(0);
-  const T* mdx = sx + ring_row<RING>(row) * STRIDE + (tx - R);
+  const T* mdx = sx + ring_row<RING>(row) * STRIDE + (tx - R) * CS;
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
     const T bd = stencil_bd<R, T>(n), ba = stencil_ba<R, T>(n);
-    const T* upx = sx + ring_row<RING>(row + n) * STRIDE + (tx - R);
-    const T* dnx = sx + ring_row<RING>(row - n) * STRIDE + (tx - R);
-    const T* upy = sy + ring_row<RING>(row + n) * STRIDE + (tx - R);
-    const T* dny = sy + ring_row<RING>(row - n) * STRIDE + (tx - R);
-    const T d1 = upx[R + n] - dnx[R - n];
-    const T d3 = upx[R - n] - dnx[R + n];
-    const T d8 = mdx[R + n] - mdx[R - n];
-    const T e1 = upy[R + n] - dny[R - n];
-    const T e3 = upy[R - n] - dny[R + n];
-    const T e2 = upy[R] - dny[R];
+    const T* upx = sx + ring_row<RING>(row + n) * STRIDE + (tx - R) * CS;
+    const T* dnx = sx + ring_row<RING>(row - n) * STRIDE + (tx - R) * CS;
+    const T* upy = sy + ring_row<RING>(row + n) * STRIDE + (tx - R) * CS;
+    const T* dny = sy + ring_row<RING>(row - n) * STRIDE + (tx - R) * CS;
+    const T d1 = upx[(R + n) * CS] - dnx[(R - n) * CS];
+    const T d3 = upx[(R - n) * CS] - dnx[(R + n) * CS];
+    const T d8 = mdx[(R + n) * CS] - mdx[(R - n) * CS];
+    const T e1 = upy[(R + n) * CS] - dny[(R - n) * CS];
+    const T e3 = upy[(R - n) * CS] - dny[(R + n) * CS];
+    const T e2 = upy[R * CS] - dny[R * CS];
     acc += ba * (d8 + e2);
     acc += bd * ((d1 - d3) + (e1 + e3));
   }
   return acc;
 }
 
-// LDS rings, laid out [ring row][field][column] so that every field of one
-// row is within a small immediate offset of one address.
+// LDS rings, laid out [ring row][column][field]: the fields of one site and
+// its stencil neighbours in the same row are within the immediate offset range
+// of paired LDS reads from one address (fewer address computations; the
+// 13-element column stride is odd, so lanes of a wave hit distinct banks).
 enum {
   // stencil operands
   F_RHON, F_MX, F_MY, F_UX, F_UY, F_PHI,
@@ -435,11 +437,12 @@ enum {
 template <typename T, int NTX, int RING>
 struct Smem {
   static constexpr int STRIDE = NFIELD * NTX;  // elements per ring row
-  static constexpr int PAD = 16 / sizeof(T) > 3 ? 16 / sizeof(T) : 3;  // keeps tx - 3 inside the array
+  static constexpr int CS = NFIELD;            // elements between neighbouring columns
+  static constexpr int PAD = 3 * NFIELD;       // keeps (tx - 3) CS inside the array
   T pad[PAD];
   T d[RING * STRIDE];
-  __device__ __forceinline__ T& at(int field, int row, int tx) { return d[row * STRIDE + field * NTX + tx]; }
-  __device__ __forceinline__ const T* field(int f) const { return d + f * NTX; }
+  __device__ __forceinline__ T& at(int field, int row, int tx) { return d[row * STRIDE + tx * CS + field]; }
+  __device__ __forceinline__ const T* field(int f) const { return d + f; }
 };
 
 // Register state of one thread: the nine total populations of the rows it
@@ -652,7 +655,7 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   // ---- band N: grad rho^N and director m -------------------------------------
   if (it >= PP::ITN && tx >= RG && tx < NTX - RG) {
     T gx, gy;
-    ring_grad<RG, RING, SM::STRIDE>(sm.field(F_RHON), rowN, tx, gx, gy);
+    ring_grad<RG, RING, SM::STRIDE, SM::CS>(sm.field(F_RHON), rowN, tx, gx, gy);
     const T is = rsqrt_pos(gx * gx + gy * gy + c.eps2);
     const int rn = ring_row<RING>(rowN);
     sm.at(F_MX, rn, tx) = gx * is;
@@ -676,7 +679,7 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
       if (c.fixed_K) {
         K = c.K_fixed;
       } else {
-        K = -ring_div<RK, RING, SM::STRIDE>(sm.field(F_MX), sm.field(F_MY), rowU, tx);  // K = div n, n = -m
+        K = -ring_div<RK, RING, SM::STRIDE, SM::CS>(sm.field(F_MX), sm.field(F_MY), rowU, tx);  // K = div n, n = -m
       }
       if (MODE == MODE_ADJ) {
         const int v = base + PP::LU;  // virtual row of band U
@@ -707,9 +710,9 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   // ---- band O: correction, collision, recolour, store ----------------------
   if (it >= PP::IT0 && t.own && base < t.yb) {
     T dPx, dPy;
-    ring_grad<RP, RING, SM::STRIDE>(sm.field(F_PHI), rowO, tx, dPx, dPy);
+    ring_grad<RP, RING, SM::STRIDE, SM::CS>(sm.field(F_PHI), rowO, tx, dPx, dPy);
     __builtin_amdgcn_sched_barrier(0);  // bound register pressure: finish one stencil before the next
-    const T theta = ring_div<RU, RING, SM::STRIDE>(sm.field(F_UX), sm.field(F_UY), rowO, tx);
+    const T theta = ring_div<RU, RING, SM::STRIDE, SM::CS>(sm.field(F_UX), sm.field(F_UY), rowO, tx);
     __builtin_amdgcn_sched_barrier(0);
     const int ro = ring_row<RING>(rowO);
     const int p = WALLS ? base + 1 : base;
