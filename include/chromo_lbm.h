@@ -253,6 +253,16 @@ void lbm_batch_destroy(lbm_batch* b);
 /* 0 if pops_a holds the live state, 1 if pops_b does. */
 int lbm_current_pops(const lbm_handle* h);
 
+/* Re-point the handle at two other caller-owned population buffers (host-side
+ * only, nothing is copied or enqueued): `live` must hold a state in the
+ * handle's storage format and layout (it becomes the live buffer, in the slot
+ * lbm_current_pops reports), `next` receives the next lbm_step (each step still
+ * alternates between the two).  Lets a caller run a trajectory straight into
+ * its own array of states, as the checkpointed adjoint's recompute does.  Both
+ * must be lbm_pops_bytes() long and distinct; LBM_EINVAL for NULL or equal
+ * pointers.  Work already enqueued keeps the buffers it was given. */
+int lbm_set_pops(lbm_handle* h, void* live, void* next);
+
 /* Steps taken since lbm_init. */
 int64_t lbm_step_count(const lbm_handle* h);
 

@@ -53,12 +53,14 @@ class _Rollout(torch.autograd.Function):
         for k in reversed(range(len(starts))):
             t0 = starts[k]
             t1 = starts[k + 1] if k + 1 < len(starts) else ctx.nsteps
-            # states t0 .. t1-1 of this segment, recomputed from its checkpoint
+            # states t0 .. t1-1 of this segment, recomputed from its checkpoint,
+            # each step written straight into a buffer of its own
             states = [ctx.ckpts[t0]]
-            sim.live_pops().copy_(ctx.ckpts[t0])
             for _ in range(t0 + 1, t1):
+                nxt = sim.pops_like()
+                sim.set_pops(states[-1], nxt)
                 sim.step(1)
-                states.append(sim.live_pops().clone())
+                states.append(nxt)
             for t in reversed(range(t0, t1)):
                 sim.adjoint_step(states[t - t0], lam, lam_prev, dsigma, dforce)
                 lam, lam_prev = lam_prev, lam

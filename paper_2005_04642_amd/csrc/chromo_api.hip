@@ -317,6 +317,16 @@ int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, vo
 
 int lbm_current_pops(const lbm_handle* h) { return h ? h->live : -1; }
 
+int lbm_set_pops(lbm_handle* h, void* live, void* next) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!live || !next) return fail(LBM_EINVAL, "population buffer is NULL");
+  if (live == next) return fail(LBM_EINVAL, "the two population buffers must differ");
+  h->pops[h->live] = live;
+  h->pops[1 - h->live] = next;
+  return LBM_OK;
+}
+
 int64_t lbm_step_count(const lbm_handle* h) { return h ? h->steps : -1; }
 
 void lbm_destroy(lbm_handle* h) { delete h; }

@@ -25,7 +25,8 @@ LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR = 1, 2, 4
 # every symbol the header declares
 EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_workspace_bytes", "lbm_init",
             "lbm_step", "lbm_fields", "lbm_masses_host", "lbm_adjoint_workspace_bytes", "lbm_adjoint_step",
-            "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_current_pops", "lbm_step_count", "lbm_destroy",
+            "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_current_pops", "lbm_set_pops", "lbm_step_count",
+            "lbm_destroy",
             "lbm_last_error", "lbm_batch_pops_bytes", "lbm_batch_offsets", "lbm_batch_workspace_bytes",
             "lbm_batch_init", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_plan_info", "lbm_batch_fields",
             "lbm_batch_masses_host", "lbm_batch_current_pops", "lbm_batch_step_count", "lbm_batch_destroy")
@@ -90,6 +91,8 @@ def load_library(path=None):
     lib.lbm_init_adjoint.restype = ctypes.c_int
     lib.lbm_current_pops.argtypes = [vp]
     lib.lbm_current_pops.restype = ctypes.c_int
+    lib.lbm_set_pops.argtypes = [vp, vp, vp]
+    lib.lbm_set_pops.restype = ctypes.c_int
     lib.lbm_step_count.argtypes = [vp]
     lib.lbm_step_count.restype = ctypes.c_int64
     lib.lbm_destroy.argtypes = [vp]
@@ -224,6 +227,11 @@ def lbm_init_adjoint(h, rhoN0_ptr, adj0_ptr, dL_drhoN0_ptr, stream):
 
 def lbm_current_pops(h):
     return load_library().lbm_current_pops(h)
+
+
+def lbm_set_pops(h, live_ptr, next_ptr):
+    lib = load_library()
+    return _check(lib, lib.lbm_set_pops(h, live_ptr, next_ptr))
 
 
 def lbm_step_count(h):
@@ -361,6 +369,19 @@ class Simulation:
     def init_adjoint(self, adj0, dL_drhoN0):
         L = self._in(adj0)
         lbm_init_adjoint(self.h, self.rhoN0.data_ptr(), L.data_ptr(), dL_drhoN0.data_ptr(), self.stream())
+
+    def set_pops(self, live, nxt):
+        """Step from now on between the caller's buffers ``live`` (holding the
+        current state) and ``nxt`` (receives the next step), both
+        [2, 9, ny, nx] tensors laid out as pops_like() (F64/F32 storage)."""
+        for t in (live, nxt):
+            if not self._is_lib_layout(t):
+                raise ValueError("set_pops needs [2, 9, ny, nx] buffers laid out as pops_like()")
+        lbm_set_pops(self.h, live.data_ptr(), nxt.data_ptr())
+        k = lbm_current_pops(self.h)
+        # flat word views of the same memory, so live_pops() and friends follow
+        self.pops[k] = live.permute(2, 0, 1, 3).reshape(-1)
+        self.pops[1 - k] = nxt.permute(2, 0, 1, 3).reshape(-1)
 
     def live_words(self):
         """View [NW, ny, nx] of the live buffer (storage words, pull layout;

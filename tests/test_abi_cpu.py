@@ -110,6 +110,7 @@ def test_adjoint_availability_and_argument_errors():
     assert lib.lbm_adjoint_step(None, None, None, None, None, 0, None, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_rhoN_adjoint(None, None, None, None, None) == lbm.LBM_EINVAL
     assert lib.lbm_init_adjoint(None, None, None, None, None) == lbm.LBM_EINVAL
+    assert lib.lbm_set_pops(None, None, None) == lbm.LBM_EINVAL
 
 
 def test_batch_validation_and_layout():

@@ -320,6 +320,35 @@ def test_full_size_emulsion_sampled_sites():
     sim.close()
 
 
+def test_set_pops_runs_into_caller_buffers():
+    """lbm_set_pops: stepping between the caller's own buffers gives the same
+    states, bit for bit, as stepping between the handle's two buffers."""
+    n = 64
+    cfg = Wk.config_static_drop()
+    a = sim_for(n, n, cfg["params"], cfg["rhoN0"], "f32")
+    b = sim_for(n, n, cfg["params"], cfg["rhoN0"], "f32")
+    a.step(5)
+    b.step(5)
+    states = [b.live_pops().clone()]
+    for _ in range(4):
+        nxt = b.pops_like()
+        b.set_pops(states[-1], nxt)
+        b.step(1)
+        states.append(nxt)
+        a.step(1)
+        assert torch.equal(host_t(a.live_pops()), host_t(nxt))
+    assert torch.equal(host_t(b.live_pops()), host_t(states[-1]))
+    with pytest.raises(ValueError):
+        b.set_pops(states[-1], torch.empty((2, 9, n, n), device=DEV))  # not the library's layout
+    a.close()
+    b.close()
+
+
+def host_t(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu()
+
+
 # ---------------------------------------------------------------------------
 # invariants and failure reporting
 # ---------------------------------------------------------------------------
