@@ -454,6 +454,7 @@ struct March {
   using T = typename S::math;
   T rf[4][9];
   typename S::W pw[S::NW];
+  T fx[2], fy[2];  // body force of the band-U rows, loaded one iteration ahead
 };
 
 struct Thread {
@@ -653,6 +654,15 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   __syncthreads();
 
   // ---- band N: grad rho^N and director m -------------------------------------
+  if (a.force) {
+    // the next iteration's band-U row: its force is waited for with this
+    // iteration's stores, before band M, instead of right where it is used
+    RowTrack<WALLS> nu = tU;
+    nu.advance(g);
+    const int site = nu.phys(g) * g.nx + t.xg;
+    st.fx[(S + 1) & 1] = a.force[site];
+    st.fy[(S + 1) & 1] = a.force[g.plane + site];
+  }
   if (it >= PP::ITN && tx >= RG && tx < NTX - RG) {
     T gx, gy;
     ring_grad<RG, RING, SM::STRIDE, SM::CS>(sm.field(F_RHON), rowN, tx, gx, gy);
@@ -689,9 +699,8 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
       T Gx = c.half_sigma * K * gnx + c.gx;
       T Gy = c.half_sigma * K * gny + (refl ? -c.gy : c.gy);
       if (a.force) {
-        const int site = p * g.nx + t.xg;
-        Gx += a.force[site];
-        Gy += refl ? -a.force[g.plane + site] : a.force[g.plane + site];
+        Gx += st.fx[S & 1];
+        Gy += refl ? -st.fy[S & 1] : st.fy[S & 1];
       }
       T jx, jy;
       momenta(rf, jx, jy);
@@ -764,6 +773,11 @@ __device__ __forceinline__ void march_tile(const StepArgs<typename ST::math>& a,
   gather_words<ST, WALLS>(src, g, tM.phys(g), t.cols, st.pw);
   tM.advance(g);
   tU.init(v0 + PP::LU, g);
+  if (a.force) {
+    const int site = tU.phys(g) * g.nx + t.xg;
+    st.fx[0] = a.force[site];
+    st.fy[0] = a.force[g.plane + site];
+  }
   for (int it = 0; it < t.nit; it += 4) {
     march_iter<0, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it, a, src, dst, sm, st, t, tM, tU);
     if (it + 1 < t.nit)
