@@ -651,18 +651,23 @@ int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_
                                       it0),
                         stream);
       if (st != LBM_OK) break;
-      hipMemcpyAsync(b->pops[live0], scratch, total, hipMemcpyDeviceToDevice, stream);
-      b->live = live0;
-      if ((st = batch_step_impl(b, 1, stream)) != LBM_OK) break;  // warm-up
-      hipEventRecord(e0, stream);
-      if ((st = batch_step_impl(b, steps_per_trial, stream)) != LBM_OK) break;
-      hipEventRecord(e1, stream);
-      if (hipEventSynchronize(e1) != hipSuccess) {
-        st = fail(LBM_EHIP, "autotune: event synchronisation failed");
+      if (hipMemcpyAsync(b->pops[live0], scratch, total, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
+        st = fail(LBM_EHIP, "autotune: restoring the state failed");
         break;
       }
+      b->live = live0;
+      if ((st = batch_step_impl(b, 1, stream)) != LBM_OK) break;  // warm-up
+      if (hipEventRecord(e0, stream) != hipSuccess) {
+        st = fail(LBM_EHIP, "autotune: event record failed");
+        break;
+      }
+      if ((st = batch_step_impl(b, steps_per_trial, stream)) != LBM_OK) break;
       float ms = 0.0f;
-      hipEventElapsedTime(&ms, e0, e1);
+      if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        st = fail(LBM_EHIP, "autotune: timing a candidate failed");
+        break;
+      }
       if (best < 0.0f || ms < best) {
         best = ms;
         best_ntx = b->ops->batch_ntx[i];
@@ -670,8 +675,8 @@ int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_
       }
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   // restore the state and install the winner
   HIP_TRY(hipMemcpyAsync(b->pops[live0], scratch, total, hipMemcpyDeviceToDevice, stream));
   b->live = live0;
