@@ -38,9 +38,16 @@ def traffic_file(storage):
 
 
 def kernel_hash():
+    """Hash of the kernel sources' code: comments and blank space are dropped,
+    so a counter run stays matched to the code it measured across comment
+    edits."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        h.update(open(f, "rb").read())
+        src = open(f).read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

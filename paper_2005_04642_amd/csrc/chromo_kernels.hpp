@@ -123,7 +123,8 @@ __host__ __device__ constexpr int link_class(int i) { return i == 0 ? 0 : ((i & 
 
 // ---------------------------------------------------------------------------
 // Population storage formats.  A format keeps the 18 populations of a site as
-// NW words, word q in plane q of the buffer ([plane][ny][nx], x fastest).
+// NW words; a buffer is laid out [ny][NW][nx] (x fastest), word q of site
+// (x, y) at (y NW + q) nx + x.
 //   F64, F32 : NW = 18, word q = population (colour q / 9, link q % 9).
 //   F16O, BF16O (16-bit offset formats, FP32 arithmetic): NW = 10 words of
 //     4 bytes.  Words 0 and 1 are R_0 and B_0 as float.  Word 1 + i, i = 1..8,
@@ -142,7 +143,7 @@ __host__ __device__ constexpr int link_class(int i) { return i == 0 ? 0 : ((i & 
 //                   exceed 8 fref_i in magnitude.
 //     The minority colour thus keeps FP16's relative precision down to its
 //     smallest tails, and f_i keeps it relative to its departure from rest.
-// Memory access goes through buffer resources: plane and row offsets are
+// Memory access goes through buffer resources: word and row offsets are
 // wave-uniform (SGPR soffset), only the column offset lives in a VGPR.
 // ---------------------------------------------------------------------------
 struct F64 {
@@ -290,7 +291,7 @@ struct Cols {
 // Pull-streaming gather of the words of site (x, p): the word of link i comes
 // from the source site r - c_i, or, when r - c_i is a solid row, from the
 // reversed link's word at r itself (half-way bounce-back).  p is wave-uniform,
-// so every plane / row offset is scalar.  WALLS: rows 0 and ny - 1 are solid
+// so every word / row offset is scalar.  WALLS: rows 0 and ny - 1 are solid
 // (else y is periodic).
 template <typename S, bool WALLS>
 __device__ __forceinline__ void gather_words(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
