@@ -139,6 +139,40 @@ def adjoint_measure(n, params, rn, torch, steps=20, force=None):
             "ratio": round(ms_fwd / ms_adj, 4)}
 
 
+def storage16_measure(n, params, rn, torch, steps=200, warmup=20):
+    """The 16-bit offset formats on the benchmark lattice: time per step, and the
+    largest difference of rho (relative) and u (relative to max |u|) from the
+    FP32 path after the same warmup + steps from the same initial state."""
+    from paper_2005_04642_amd import lbm
+
+    def run(storage, timed):
+        sim = lbm.Simulation(n, n, params, rn, storage=storage, device="cuda:0")
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        f = sim.fields()
+        sim.close()
+        return e0.elapsed_time(e1) / steps, f
+
+    _, ref = run("f32", False)
+    umax = float(torch.sqrt(ref["ux"] ** 2 + ref["uy"] ** 2).max())
+    out = {"workload": "the benchmark lattice, %d + %d steps; differences from the FP32 path" % (warmup, steps)}
+    for storage in ("f16", "bf16"):
+        ms, f = run(storage, True)
+        e_rho = float((torch.abs(f["rho"] - ref["rho"]) / ref["rho"]).max())
+        e_u = float(torch.sqrt((f["ux"] - ref["ux"]) ** 2 + (f["uy"] - ref["uy"]) ** 2).max()) / umax
+        gbs = BYTES_PER_LU[storage] * n * n / (ms * 1e-3) / 1e9
+        out[storage] = {"ms_per_step": round(ms, 5), "MLUPS": round(n * n / ms / 1e3, 1),
+                        "GB_s": round(gbs, 1), "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4),
+                        "max_rel_drho_vs_f32": float("%.3g" % e_rho), "max_du_over_umax_vs_f32": float("%.3g" % e_u)}
+    return out
+
+
 def drop_to_ellipse(n=512):
     """The adjoint workload: n^2 periodic, circle of radius n/4 to a seeded
     ellipse target of equal area, 8 Gaussian force bumps (amplitude 1e-6).
@@ -251,6 +285,7 @@ def main():
     ap.add_argument("--no-copy-roof", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-storage16", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one plain 1 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -325,6 +360,8 @@ def main():
     if not args.no_copy_roof:
         out["copy_roof"] = copy_roof(n, params, rn, torch, args.storage)
         out["roofline"]["frac_of_copy"] = round(achieved / out["copy_roof"]["GB_s"], 4)
+    if not args.no_storage16 and args.storage == "f32":
+        out["storage16"] = storage16_measure(n, params, rn, torch)
     if not args.no_adjoint:
         out["adjoint"] = dict({"workload": "same lattice and state, one adjoint step vs one forward step, FP32"},
                               **adjoint_measure(n, params, rn, torch))
