@@ -156,12 +156,20 @@ def config_static_drop():
     return dict(nx=64, ny=64, steps=1000, params=p, rhoN0=static_drop(64, 64, 16.0))
 
 
-def config_layered_channel():
+def config_layered_channel(width=2.0):
     """256x128 channel, walls at rows 0 and 127, Lambda = 100, dynamic
-    viscosity ratio 10 (nu_B = 10 nu_R), body force density 1e-6 along x."""
+    viscosity ratio 10 (nu_B = 10 nu_R), body force density 1e-6 along x.
+    Red below, blue above, joined by a tanh colour profile of the given width
+    centred on the channel's mid-plane (width 0: the sharp +-1 step, which
+    diverges within 500 steps at this density ratio)."""
     p = base_params(Lambda=100.0, sigma=0.01)
     p.update(nu_R=1.0 / 6.0, nu_B=10.0 / 6.0, gx=1e-6, walls=True)
-    return dict(nx=256, ny=128, steps=20000, params=p, rhoN0=layered_channel(256, 128))
+    if width > 0:
+        yy = (np.arange(128) - 0.5)[:, None] * np.ones((1, 256))
+        rn = np.tanh((128 / 2.0 - yy) / width)
+    else:
+        rn = layered_channel(256, 128)
+    return dict(nx=256, ny=128, steps=20000, params=p, rhoN0=rn)
 
 
 def config_emulsion(nx=4096, ny=4096, seed=0):
