@@ -28,6 +28,27 @@ def pull_gather(S, walls):
     return out
 
 
+def push_scatter(P, ny):
+    """Inverse of pull_gather for walled lattices: the pull-layout buffer
+    [2, 9, ny, nx] whose gather gives the fluid-row populations P [2, 9, ny-2, nx]
+    (S_i(s) = P_i(s + c_i), or P_opp(i)(s) when s + c_i is a solid row)."""
+    P = np.asarray(P)
+    nx = P.shape[-1]
+    Pf = np.zeros(P.shape[:2] + (ny, nx))
+    Pf[:, :, 1:ny - 1] = P
+    S = np.empty_like(Pf)
+    for i in range(Q):
+        cx, cy = C[i]
+        S[:, i] = np.roll(np.roll(Pf[:, i], -cx, axis=-1), -cy, axis=-2)
+    for i in range(Q):
+        cy = C[i][1]
+        if cy == -1:
+            S[:, i, 1] = Pf[:, OPP[i], 1]
+        elif cy == 1:
+            S[:, i, ny - 2] = Pf[:, OPP[i], ny - 2]
+    return S
+
+
 def oracle_params(nx, ny, params):
     return O.Params(nx=nx, ny=ny, **params)
 

@@ -1,8 +1,14 @@
 """Physics of the GPU path itself (not only its agreement with the oracle):
-Laplace's law for a static drop (Sec. IV, curved interfaces: the pressure
-step across a drop follows sigma / R), in FP32 on the static-drop workload's
-lattice, for two tensions and two radii."""
+* Laplace's law for a static drop (Sec. IV, curved interfaces: the pressure
+  step across a drop follows sigma / R), in FP32 on the static-drop
+  workload's lattice, for two tensions and two radii;
+* the flat-interface transient of Sec. IV / App. C on the paper's lattice
+  (interface at 500 of H = 1000, eta = 0.166, beta = 0.5, the four density
+  ratios and times of Table 3), epsilon(t) against the Sturm-Liouville
+  solution below the paper's 1 % bound."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -11,6 +17,8 @@ import torch
 from oracle import analytic as A
 from oracle import chromo as O
 from paper_2005_04642_amd import lbm, workloads as Wk
+
+from gpu_helpers import pull_gather, push_scatter
 
 pytestmark = pytest.mark.gpu
 
@@ -42,3 +50,40 @@ def test_laplace_law(sigma, R):
     ratio = dp / A.laplace_pressure(sigma, Reff)
     print("Laplace sigma %g R %g: dp / (sigma / R_eff) = %.4f" % (sigma, R, ratio))
     assert abs(ratio - 1.0) < 0.05
+
+
+TABLE3 = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))[
+    "transient_error_table3"]
+
+
+@pytest.mark.parametrize("Lam", TABLE3["Lambda"])
+def test_flat_interface_transient_table3(Lam):
+    """Dense (red) half moving at +u0, light half at -u0 (tanh colour profile,
+    u = u0 rho^N), equal shear viscosity; FP64.  The paper's u0 and densities
+    are unprinted: u0 = 1e-3, rho0_R = 1 (epsilon is relative, and the flow is
+    linear in u0 here).  Measured epsilon (%) at T = 1000 .. 50000: Lambda 10:
+    0.011 .. 0.005; Lambda 50: 0.032 .. 0.065 (Table 3: 0.30 .. 0.05 and
+    0.98 .. 0.12)."""
+    H, eta, beta, u0 = 1000, 1.0 / 6.0, 0.5, 1e-3
+    nx, ny = 4, H + 2
+    d = Wk.base_params(Lambda=Lam, beta=beta)
+    d.update(walls=True, nu_R=eta, nu_B=eta * Lam)
+    yy = (np.arange(ny) - 0.5)[:, None] * np.ones((1, nx))
+    rn = np.tanh(0.9 * beta * (H / 2 - yy))
+    o = O.Oracle(O.Params(nx=nx, ny=ny, **d)).init_moving(rn, u0 * rn, np.zeros_like(rn))
+    P = np.stack([o.R.numpy(), o.B.numpy()])
+    S = push_scatter(P, ny)
+    assert np.array_equal(pull_gather(S, True), P)
+    sim = lbm.Simulation(nx, ny, d, rn, storage="f64", device=DEV)
+    sim.live_pops().copy_(torch.from_numpy(S))
+    y = np.arange(H) + 0.5
+    done = 0
+    for T in TABLE3["T"]:
+        sim.step(T - done)
+        done = T
+        u = sim.fields()["ux"].double().cpu().numpy()[1:-1, 0]
+        ua = A.flat_transient(y, T, H, 1.0, 1.0 / Lam, eta, eta, u0, n_modes=600)
+        eps = A.transient_error(u, ua)
+        print("flat transient Lambda %g T %d: epsilon %.4f %%" % (Lam, T, 100 * eps))
+        assert 100 * eps < TABLE3["bound_percent"]
+    sim.close()
