@@ -15,6 +15,7 @@ import pytest
 import torch
 
 from oracle import chromo as O
+from oracle.lattice import C
 from paper_2005_04642_amd import lbm, workloads as Wk
 
 from gpu_helpers import (fluid, oracle_params, oracle_post_collision, perturbed_buffer, pull_gather,
@@ -425,6 +426,50 @@ def test_full_size_emulsion_50_steps(storage, tol):
     e_u = float(np.max(np.hypot(g["ux"] - r["ux"], g["uy"] - r["uy"])) / np.max(np.hypot(r["ux"], r["uy"])))
     print("emulsion 4096^2 %s, 50 steps, window at (%d, %d): e_rho %.3e e_u %.3e" % (storage, yc, xc, e_rho, e_u))
     assert e_rho < tol[0] and e_u < tol[1]
+
+
+def test_largest_lattice_class():
+    """7680^2 FP32: each population buffer is 4.25 GB, just under the 4 GiB a
+    buffer may have, so word and row byte offsets run past 2^31.  Streaming
+    is bit-exact and one full step matches the oracle at sampled sites in the
+    first and last rows and columns (the largest offsets)."""
+    n = 7680
+    params = Wk.base_params(Lambda=10.0, sigma=0.005)
+    rn = Wk.emulsion(n, n, 12, 20.0, 80.0, 6.0, 3)
+    rng = np.random.default_rng(5)
+    picks = [(0, 0), (n - 1, n - 1), (n - 1, 0), (0, n - 1), (n - 2, n // 2)]
+    picks += [tuple(rng.integers(0, n, 2)) for _ in range(3)]
+    # streaming only
+    sim = sim_for(n, n, params, rn, "f32", flags=lbm.LBM_FLAG_STREAM_ONLY)
+    sim.step(2)
+    before = sim.live_pops().clone()
+    sim.step(1)
+    after = sim.live_pops()
+    for (y, x) in picks:
+        for i in range(9):
+            cx, cy = C[i]
+            src = before[:, i, (y - cy) % n, (x - cx) % n]
+            assert torch.equal(after[:, i, y, x], src), (y, x, i)
+    sim.close()
+    del before
+    # one step against the oracle
+    sim = sim_for(n, n, params, rn, "f32")
+    sim.step(3)
+    before = sim.live_pops().clone()
+    sim.step(1)
+    after = sim.live_pops()
+    half = 12
+    worst = 0.0
+    for (y, x) in picks:
+        S = window(before, int(x), int(y), half)
+        ref = oracle_post_collision(S, 2 * half + 1, 2 * half + 1, params)[:, :, half, half]
+        got = after[:, :, y, x].double().cpu().numpy()
+        worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    print("7680^2 f32: one step at sampled sites, max rel err %.3e" % worst)
+    assert worst < 2e-5
+    m = sim.masses()
+    assert np.isfinite(m[0]) and np.isfinite(m[1])
+    sim.close()
 
 
 # ---------------------------------------------------------------------------
