@@ -206,3 +206,26 @@ def test_ofs16_masses_and_nan(fmt):
         sim.masses()
     assert ei.value.code == lbm.LBM_ENONFINITE
     sim.close()
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+def test_ofs16_largest_lattice_class_streaming(fmt):
+    """10240^2 in a 16-bit offset format: 4.19 GB per buffer (under 4 GiB, byte
+    offsets past 2^31); the packed words stream bit-exactly at sites in the
+    first and last rows and columns."""
+    from oracle.lattice import C
+    n = 10240
+    params = Wk.base_params(Lambda=10.0)
+    sim = sim_for(n, n, params, Wk.emulsion(n, n, 12, 20.0, 80.0, 6.0, 4), fmt, flags=lbm.LBM_FLAG_STREAM_ONLY)
+    sim.step(2)
+    before = sim.live_words().clone()
+    sim.step(1)
+    after = sim.live_words()
+    rng = np.random.default_rng(9)
+    picks = [(0, 0), (n - 1, n - 1), (n - 1, 0), (0, n - 1)] + [tuple(rng.integers(0, n, 2)) for _ in range(3)]
+    for (y, x) in picks:
+        for q in range(10):
+            i = 0 if q < 2 else q - 1        # word q carries link i (words 0, 1: the rest link)
+            cx, cy = C[i]
+            assert torch.equal(after[q, y, x], before[q, (y - cy) % n, (x - cx) % n]), (y, x, q)
+    sim.close()
