@@ -158,8 +158,10 @@ int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN,
 int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream);
 
 /* ---- adjoint (reverse-mode derivative of lbm_step) ------------------------
- * Provided for LBM_STORAGE_F64 and LBM_STORAGE_F32 on periodic lattices
- * (walls_y = 0); other cases return LBM_ENOTIMPL.  Adjoint buffers have the
+ * Provided for LBM_STORAGE_F64 and LBM_STORAGE_F32, periodic or walled
+ * (walls_y = 1: the transposes of the wall-mirrored stencils and of the
+ * bounce-back); the 16-bit formats return LBM_ENOTIMPL.  The words of solid
+ * rows carry no state: their adjoints are written as 0.  Adjoint buffers have the
  * layout of an F64/F32 population buffer ([ny][colour 2][link 9][nx], the
  * arithmetic type), aligned with the pull layout: adj[C][i](s) is dL/d of the
  * stored word buf[C][i](s).  The step that is differentiated is the one

@@ -86,6 +86,61 @@ __device__ __forceinline__ T div_r(int r, const T* fx, const T* fy, int nx, int 
   return r == 3 ? div_at<3>(fx, fy, nx, ny, x, y) : div_at<1>(fx, fy, nx, ny, x, y);
 }
 
+// Transposes of the App. B stencils on a walled lattice (solid rows 0 and
+// ny - 1).  The forward stencil at fluid row y' reads, for link i and
+// distance n, the fluid row fold(y' + n c_iy) of the mirror-extended strip
+// (negated for a y-component): so fluid row `row` receives from y' =
+// row - n c_iy directly and from y' = 2F - 1 - row - n c_iy through the mirror
+// (both mod 2F, kept when inside the strip).  Returns (D_x^T l, D_y^T l) at
+// the fluid site (x, y) for a field l given on the lattice's rows.
+__device__ __forceinline__ int wrapi(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+template <int R, typename T>
+__device__ __forceinline__ void gradT_walls_at(const T* l, int nx, int ny, int x, int y, bool odd, T& tx, T& ty) {
+  const int F = ny - 2, row = y - 1, F2 = 2 * F;
+  const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
+  const T sg = odd ? T(-1) : T(1);
+  tx = T(0);
+  ty = T(0);
+#pragma unroll
+  for (int n = 1; n <= R; ++n) {
+    const T b = stencil_b<R, T>(n);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int cx = link_cx(i), cy = link_cy(i);
+      const T bw = b * ((i & 1) ? wd : wa);
+      const int xs = wrapi(x - n * cx, nx);
+      const int y1 = wrapi(row - n * cy, F2), y2 = wrapi(F2 - 1 - row - n * cy, F2);
+      T v = T(0);
+      if (y1 < F) v += l[(y1 + 1) * nx + xs];
+      if (y2 < F) v += sg * l[(y2 + 1) * nx + xs];
+      tx += bw * T(cx) * v;
+      ty += bw * T(cy) * v;
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void gradT_walls(int r, const T* l, int nx, int ny, int x, int y, bool odd, T& tx,
+                                            T& ty) {
+  if (r == 3) {
+    gradT_walls_at<3>(l, nx, ny, x, y, odd, tx, ty);
+  } else {
+    gradT_walls_at<1>(l, nx, ny, x, y, odd, tx, ty);
+  }
+}
+
+__device__ __forceinline__ bool solid_row(const Geom& g, int y) { return g.walls && (y == 0 || y == g.ny - 1); }
+
+// the same, with the lattice kind fixed at compile time (periodic: never)
+template <bool W>
+__device__ __forceinline__ bool solid_row_w(const Geom& g, int y) {
+  return W && (y == 0 || y == g.ny - 1);
+}
+
 struct Radii {
   int g, k, p, u;
 };
@@ -306,7 +361,7 @@ static __device__ __forceinline__ double block_sum(double v) {
 // ---------------------------------------------------------------------------
 // pass 2: div u and grad Phi' transposed; u, Phi', G local
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool W>
 __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, Radii r, const T* __restrict__ sv,
                                                     const T* __restrict__ A, T* __restrict__ B,
                                                     T* __restrict__ dforce, double* __restrict__ part) {
@@ -314,12 +369,24 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, 
   const int y = blockIdx.y;
   const int P = g.plane, site = y * g.nx + x;
   double acc = 0.0;
-  if (x < g.nx) {
-    T tx, ty;
-    grad_r(r.u, A + A_TH * P, g.nx, g.ny, x, y, tx, ty);
-    const T lux = A[A_UX * P + site] - tx;  // theta = div u: transpose -grad
-    const T luy = A[A_UY * P + site] - ty;
-    const T lphi = -div_r(r.p, A + A_DPX * P, A + A_DPY * P, g.nx, g.ny, x, y);
+  if (x < g.nx && !solid_row_w<W>(g, y)) {
+    T lux, luy, lphi;
+    if constexpr (W) {
+      T ax, ay, bx, by;
+      gradT_walls(r.u, A + A_TH * P, g.nx, g.ny, x, y, false, ax, ay);  // theta = D_x u_x + D_y u_y (u_y odd)
+      gradT_walls(r.u, A + A_TH * P, g.nx, g.ny, x, y, true, bx, by);
+      lux = A[A_UX * P + site] + ax;
+      luy = A[A_UY * P + site] + by;
+      gradT_walls(r.p, A + A_DPX * P, g.nx, g.ny, x, y, false, ax, ay);  // grad Phi' (even)
+      gradT_walls(r.p, A + A_DPY * P, g.nx, g.ny, x, y, false, bx, by);
+      lphi = ax + by;
+    } else {
+      T tx, ty;
+      grad_r(r.u, A + A_TH * P, g.nx, g.ny, x, y, tx, ty);
+      lux = A[A_UX * P + site] - tx;  // theta = div u: transpose -grad
+      luy = A[A_UY * P + site] - ty;
+      lphi = -div_r(r.p, A + A_DPX * P, A + A_DPY * P, g.nx, g.ny, x, y);
+    }
     const T rR = sv[SV_RR * P + site], rB = sv[SV_RB * P + site];
     const T rho = rR + rB;
     const T ux = sv[SV_UX * P + site], uy = sv[SV_UY * P + site];
@@ -364,7 +431,7 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, 
 // per-workgroup dL/dsigma partials to *dsigma while the other workgroups run
 // the pass.  Each thread sums a fixed strided subset in 8 interleaved
 // accumulators, combined in a fixed order (deterministic).
-template <typename T>
+template <typename T, bool W>
 __global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii r, const T* __restrict__ sv,
                                                        const T* __restrict__ A, const T* __restrict__ B,
                                                        T* __restrict__ C, const double* __restrict__ part,
@@ -388,10 +455,18 @@ __global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii 
   }
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y - 1;
-  if (x >= g.nx) return;
+  if (x >= g.nx || solid_row_w<W>(g, y)) return;
   const int P = g.plane, site = y * g.nx + x;
   T kx, ky;
-  grad_r(r.k, B + B_K * P, g.nx, g.ny, x, y, kx, ky);
+  if constexpr (W) {  // K = -(D_x m_x + D_y m_y), m_y odd: lambda_m = -D^T lambda_K
+    T ax, ay, bx, by;
+    gradT_walls(r.k, B + B_K * P, g.nx, g.ny, x, y, false, ax, ay);
+    gradT_walls(r.k, B + B_K * P, g.nx, g.ny, x, y, true, bx, by);
+    kx = -ax;
+    ky = -by;
+  } else {
+    grad_r(r.k, B + B_K * P, g.nx, g.ny, x, y, kx, ky);
+  }
   const T lmx = A[A_MX * P + site] + kx;  // -(-D)^T = D
   const T lmy = A[A_MY * P + site] + ky;
   const T gx = sv[SV_GNX * P + site], gy = sv[SV_GNY * P + site];
@@ -405,15 +480,24 @@ __global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii 
 // ---------------------------------------------------------------------------
 // pass 4: grad rho^N transposed; colour index
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool W>
 __global__ void __launch_bounds__(256) colour_kernel(Geom g, Coef<T> c, Radii r, const T* __restrict__ sv,
                                                      const T* __restrict__ A, const T* __restrict__ B,
                                                      const T* __restrict__ C, T* __restrict__ D) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= g.nx) return;
+  if (x >= g.nx || solid_row_w<W>(g, y)) return;
   const int P = g.plane, site = y * g.nx + x;
-  const T lrN = A[A_RN * P + site] - div_r(r.g, C + C_GX * P, C + C_GY * P, g.nx, g.ny, x, y);
+  T dv;
+  if constexpr (W) {  // g = grad rho^N (even): lambda_rhoN += D_x^T lambda_gx + D_y^T lambda_gy
+    T ax, ay, bx, by;
+    gradT_walls(r.g, C + C_GX * P, g.nx, g.ny, x, y, false, ax, ay);
+    gradT_walls(r.g, C + C_GY * P, g.nx, g.ny, x, y, false, bx, by);
+    dv = -(ax + by);
+  } else {
+    dv = div_r(r.g, C + C_GX * P, C + C_GY * P, g.nx, g.ny, x, y);
+  }
+  const T lrN = A[A_RN * P + site] - dv;
   const T a = sv[SV_RR * P + site] * c.inv_rho0R, b = sv[SV_RB * P + site] * c.inv_rho0B;
   const T is = T(1) / (a + b);
   const T w = T(2) * lrN * is * is;
@@ -425,21 +509,30 @@ __global__ void __launch_bounds__(256) colour_kernel(Geom g, Coef<T> c, Radii r,
 // pass 5: pre-collision adjoints and the transposed pull gather:
 // lambda_t[C][i](s) = dL/dC_i(s + c_i), dL/dC_i = lambda_f_i + lambda_rho_C + lambda_j . c_i
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool W>
 __global__ void __launch_bounds__(256) push_kernel(Geom g, const T* __restrict__ A, const T* __restrict__ B,
                                                    const T* __restrict__ D, T* __restrict__ out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
   const int P = g.plane;
+  if (solid_row_w<W>(g, y)) {  // no fluid site reads a solid row's words
+#pragma unroll
+    for (int q = 0; q < 18; ++q) out[((size_t)y * 18 + q) * g.nx + x] = T(0);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int cx = link_cx(i), cy = link_cy(i);
     int xs = x + cx, ys = y + cy;
     xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
     ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
-    const int r = ys * g.nx + xs;
-    const T common = A[(A_F + i) * P + r] + T(cx) * B[B_JX * P + r] + T(cy) * B[B_JY * P + r];
+    // the word is pulled by link i of site s + c_i, or, when that site is
+    // solid, bounced back into link opp(i) of s itself
+    const bool bounce = solid_row_w<W>(g, ys);
+    const int k = bounce ? link_opp(i) : i;
+    const int r = bounce ? y * g.nx + x : ys * g.nx + xs;
+    const T common = A[(A_F + k) * P + r] + T(link_cx(k)) * B[B_JX * P + r] + T(link_cy(k)) * B[B_JY * P + r];
     out[((size_t)y * 18 + i) * g.nx + x] = common + D[D_RR * P + r];
     out[((size_t)y * 18 + 9 + i) * g.nx + x] = common + D[D_RB * P + r];
   }
@@ -457,19 +550,29 @@ __global__ void __launch_bounds__(256) rhoN_adjoint_kernel(const void* popsv, Ge
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
+  if (solid_row(g, y)) {
+#pragma unroll
+    for (int q = 0; q < 18; ++q) out[((size_t)y * 18 + q) * g.nx + x] = typename S::math(0);
+    return;
+  }
   const int E = (int)sizeof(typename S::W);
-  // every site needs rho_R, rho_B of its 9 neighbours r = s + c_i
+  // word i of site s is pulled by site r = s + c_i, or, when that site is
+  // solid, bounced back into s itself: every site needs rho_R, rho_B of r
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     int xs = x + link_cx(i), ys = y + link_cy(i);
     xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
     ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
+    if (solid_row(g, ys)) {
+      xs = x;
+      ys = y;
+    }
     Cols cols;
     cols.o = xs * E;
     cols.m = (xs == 0 ? g.nx - 1 : xs - 1) * E;
     cols.p = (xs == g.nx - 1 ? 0 : xs + 1) * E;
     typename S::W w[S::NW];
-    gather_words<S, false>(make_rsrc<S>(popsv, g.plane), g, ys, cols, w);
+    gather_words_any<S>(make_rsrc<S>(popsv, g.plane), g, ys, cols, w);
     T R[9], B[9];
     decode<S>(w, c, R, B);
     T rR = T(0), rB = T(0);
@@ -496,7 +599,7 @@ __global__ void __launch_bounds__(256) init_adjoint_kernel(const T* __restrict__
                                                            T* __restrict__ out) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= g.nx) return;
+  if (x >= g.nx || solid_row(g, y)) return;
   const int site = y * g.nx + x;
   const T rn = rhoN0[site];
   const T rR = rho0R * (T(1) + rn) * T(0.5), rB = rho0B * (T(1) - rn) * T(0.5);
@@ -520,8 +623,17 @@ __global__ void __launch_bounds__(256) init_adjoint_kernel(const T* __restrict__
       phi = wt * mv * irho;
       dphi = wt * (dmv - mv * irho * drho) * irho;
     }
-    const T* l = lam0 + (size_t)ys * 18 * g.nx + xs;  // [y][C i][x], as the populations
-    acc += l[i * g.nx] * (dR * phi + rR * dphi) + l[(9 + i) * g.nx] * (dB * phi + rB * dphi);
+    // word i at s - c_i holds the rest population of link i at s when s - c_i
+    // is fluid; with walls, word i at s itself holds that of link opp(i) (the
+    // same rest fraction) when s + c_i is solid
+    if (!solid_row(g, ys)) {
+      const T* l = lam0 + (size_t)ys * 18 * g.nx + xs;  // [y][C i][x], as the populations
+      acc += l[i * g.nx] * (dR * phi + rR * dphi) + l[(9 + i) * g.nx] * (dB * phi + rB * dphi);
+    }
+    if (solid_row(g, y + link_cy(i))) {
+      const T* l = lam0 + (size_t)y * 18 * g.nx + x;
+      acc += l[i * g.nx] * (dR * phi + rR * dphi) + l[(9 + i) * g.nx] * (dB * phi + rB * dphi);
+    }
   }
   out[site] += acc;
 }

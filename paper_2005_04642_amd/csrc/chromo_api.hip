@@ -261,7 +261,7 @@ int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream) {
 
 size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
-  if (p->walls_y || !ops_of(p->storage)->adjoint) return 0;
+  if (!ops_of(p->storage)->adjoint) return 0;
   const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
   size_t bytes = (size_t)chromo::adj::WS_PLANES * (size_t)p->nx * (size_t)p->ny * elem;
   bytes = (bytes + 255) / 256 * 256;
@@ -270,7 +270,6 @@ size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
 
 static int adjoint_supported(const lbm_handle* h) {
   if (!h->ops->adjoint) return fail(LBM_ENOTIMPL, "the adjoint is provided for F64 and F32 storage only");
-  if (h->p.walls_y) return fail(LBM_ENOTIMPL, "the adjoint is provided for periodic lattices only");
   if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no adjoint of the streaming-only test mode");
   return LBM_OK;
 }

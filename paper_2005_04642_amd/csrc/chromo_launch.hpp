@@ -79,11 +79,7 @@ hipError_t march(const StepArgs<typename S::math>& a, hipStream_t s) {
   constexpr int NTX = Shape<S, MODE>::ntx, NR = Shape<S, MODE>::nr;
   const int ntiles = a.g.nstrips * a.g.nchunks;
   const int nblocks = 8 * ((ntiles + 7) / 8);  // whole rounds over the 8 XCDs (see the kernel)
-  if constexpr (MODE == MODE_ADJ) {  // the adjoint supports periodic lattices only
-    if (a.g.walls) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, false, MODE>), dim3(nblocks),
-                       dim3(NTX * NR), 0, s, a);
-  } else if (a.g.walls) {
+  if (a.g.walls) {
     hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, RG, RK, RP, RU, true, MODE>), dim3(nblocks),
                        dim3(NTX * NR), 0, s, a);
   } else {
@@ -181,6 +177,21 @@ hipError_t mass(const lbm_params& p, const Geom& g, const void* pops, double* pa
   return hipGetLastError();
 }
 
+// passes 2-5 of the adjoint, with the lattice kind (periodic or walled) fixed
+// at compile time
+template <typename T, bool W>
+void adjoint_tail(const StepArgs<T>& a, const Geom& g, const adj::Radii& r, T sigma, const T* sv, const T* A, T* B,
+                  T* C, T* D, double* part, double* dsigma, T* dforce, T* lam_out, hipStream_t s) {
+  const dim3 grid((g.nx + 255) / 256, g.ny);
+  hipLaunchKernelGGL((adj::force_kernel<T, W>), grid, dim3(256), 0, s, g, a.c, sigma, r, sv, A, B, dforce, part);
+  // pass 3, plus the sum of pass 2's dL/dsigma partials in one extra row of workgroups
+  hipLaunchKernelGGL((adj::director_kernel<T, W>), dim3(grid.x, g.ny + 1), dim3(256), 0, s, g, a.c, r, sv, A,
+                     (const T*)B, C, (const double*)part, adj::red_blocks(g.nx, g.ny), dsigma);
+  hipLaunchKernelGGL((adj::colour_kernel<T, W>), grid, dim3(256), 0, s, g, a.c, r, sv, A, (const T*)B,
+                     (const T*)C, D);
+  hipLaunchKernelGGL((adj::push_kernel<T, W>), grid, dim3(256), 0, s, g, A, (const T*)B, (const T*)D, lam_out);
+}
+
 // ---------------------------------------------------------------------------
 // adjoint: save pass of the step kernel, then the five passes of
 // chromo_adjoint.hpp.  ws holds adj::WS_PLANES planes of the arithmetic type
@@ -205,17 +216,14 @@ hipError_t adjoint(const lbm_params& p, const Geom& g0, const void* pops, const 
   a.lam_next = static_cast<const T*>(lam_next);
   hipError_t e = dispatch_radii<S, MODE_ADJ>(a, p.stencil, s);
   if (e != hipSuccess) return e;
-  const dim3 grid((g.nx + 255) / 256, g.ny);
   const adj::Radii r = {p.stencil[0], p.stencil[1], p.stencil[2], p.stencil[3]};
-  hipLaunchKernelGGL(adj::force_kernel<T>, grid, dim3(256), 0, s, g, a.c, (T)p.sigma, r, (const T*)sv,
-                     (const T*)A, B, static_cast<T*>(dforce), part);
-  // pass 3, plus the sum of pass 2's dL/dsigma partials in one extra row of workgroups
-  hipLaunchKernelGGL(adj::director_kernel<T>, dim3(grid.x, g.ny + 1), dim3(256), 0, s, g, a.c, r, (const T*)sv,
-                     (const T*)A, (const T*)B, C, (const double*)part, adj::red_blocks(g.nx, g.ny), dsigma);
-  hipLaunchKernelGGL(adj::colour_kernel<T>, grid, dim3(256), 0, s, g, a.c, r, (const T*)sv, (const T*)A,
-                     (const T*)B, (const T*)C, D);
-  hipLaunchKernelGGL(adj::push_kernel<T>, grid, dim3(256), 0, s, g, (const T*)A, (const T*)B, (const T*)D,
-                     static_cast<T*>(lam_out));
+  if (g.walls) {
+    adjoint_tail<T, true>(a, g, r, (T)p.sigma, sv, A, B, C, D, part, dsigma, static_cast<T*>(dforce),
+                          static_cast<T*>(lam_out), s);
+  } else {
+    adjoint_tail<T, false>(a, g, r, (T)p.sigma, sv, A, B, C, D, part, dsigma, static_cast<T*>(dforce),
+                           static_cast<T*>(lam_out), s);
+  }
   return hipGetLastError();
 }
 

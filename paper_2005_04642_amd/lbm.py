@@ -309,13 +309,13 @@ class Simulation:
     def masses(self):
         return lbm_masses_host(self.h, self.stream())
 
-    # -- adjoint (F64/F32 storage, periodic lattices) ---------------------------
+    # -- adjoint (F64/F32 storage, periodic or walled) --------------------------
     def adjoint_workspace(self):
         """Device workspace of lbm_adjoint_step (allocated on first use)."""
         if getattr(self, "_adj_ws", None) is None:
             n = lbm_adjoint_workspace_bytes(self.params)
             if n == 0:
-                raise LbmError(LBM_ENOTIMPL, "no adjoint for these parameters (needs F64/F32 storage, periodic y)")
+                raise LbmError(LBM_ENOTIMPL, "no adjoint for these parameters (needs F64/F32 storage)")
             self._adj_ws = self.torch.empty(n, dtype=self.torch.uint8, device=self.device)
         return self._adj_ws
 

@@ -95,12 +95,14 @@ def test_init_argument_errors_before_any_gpu_call():
 
 
 def test_adjoint_availability_and_argument_errors():
-    """The adjoint exists for F64/F32 storage on periodic lattices; its
-    workspace size is 0 elsewhere, and NULL arguments fail before any GPU call."""
+    """The adjoint exists for F64/F32 storage, periodic or walled; its
+    workspace size is 0 for the 16-bit formats, and NULL arguments fail before
+    any GPU call."""
     lib = lbm.load_library()
     prm = Wk.base_params(Lambda=10.0)
     for storage, walls, ok in (("f32", False, True), ("f64", False, True), ("f16", False, False),
-                               ("bf16", False, False), ("f32", True, False)):
+                               ("bf16", False, False), ("f32", True, True), ("f64", True, True),
+                               ("f16", True, False)):
         p = lbm.make_params(64, 48, storage, **dict(prm, walls=walls))
         n = lbm.lbm_adjoint_workspace_bytes(p)
         assert (n > 0) == ok, (storage, walls)

@@ -15,7 +15,7 @@ import pytest
 import torch
 
 from oracle import chromo as O
-from oracle.lattice import C
+from oracle.lattice import C, OPP
 from paper_2005_04642_amd import adjoint, lbm, workloads as Wk
 
 pytestmark = pytest.mark.gpu
@@ -27,6 +27,23 @@ def torch_pull(S):
     """Pre-collision populations of a periodic pull-layout buffer S [2, 9, ny, nx]:
     C_i(r) = S_i(r - c_i)."""
     return torch.stack([torch.roll(S[:, i], shifts=(C[i][1], C[i][0]), dims=(-2, -1)) for i in range(9)], dim=1)
+
+
+def torch_pull_walls(S):
+    """Fluid-row pre-collision populations of a walled pull-layout buffer S
+    [2, 9, ny, nx]: C_i(r) = S_i(r - c_i), or S_opp(i)(r) when r - c_i is a
+    solid row (half-way bounce-back); returns [2, 9, ny - 2, nx]."""
+    ny = S.shape[-2]
+    out = []
+    for i in range(9):
+        cx, cy = C[i]
+        v = torch.roll(S[:, i], shifts=(cy, cx), dims=(-2, -1))
+        if cy == 1:
+            v = torch.cat([v[:, :1], S[:, OPP[i], 1:2], v[:, 2:]], dim=1)
+        elif cy == -1:
+            v = torch.cat([v[:, :ny - 2], S[:, OPP[i], ny - 2:ny - 1], v[:, ny - 1:]], dim=1)
+        out.append(v)
+    return torch.stack(out, dim=1)[:, :, 1:ny - 1]
 
 
 def state_and_params(nx, ny, seed, stencil=(3, 3, 3, 3), **extra):
@@ -42,6 +59,10 @@ def state_and_params(nx, ny, seed, stencil=(3, 3, 3, 3), **extra):
     S = S * Wk.random_state_perturbation(S.shape, 0.05, seed + 1)
     lam = rng.standard_normal(S.shape)
     force = 1e-4 * rng.standard_normal((2, ny, nx))
+    if params.get("walls"):      # solid rows hold nothing
+        for a in (S, lam):
+            a[..., 0, :] = 0.0
+            a[..., ny - 1, :] = 0.0
     return params, rn, S, lam, force
 
 
@@ -53,9 +74,11 @@ def oracle_vjp(params, S, lam, force):
     sig = torch.tensor(float(params["sigma"]), dtype=torch.float64, requires_grad=True)
     p.sigma = sig
     F_t = None if force is None else torch.tensor(force, dtype=torch.float64, requires_grad=True)
-    P = torch_pull(S_t)
+    P = torch_pull_walls(S_t) if p.walls else torch_pull(S_t)
     R, B = O.collide_and_recolour(P[0], P[1], p, force=F_t)
     lam_t = torch.tensor(lam, dtype=torch.float64)
+    if p.walls:
+        lam_t = lam_t[..., 1:ny - 1, :]
     L = (R * lam_t[0]).sum() + (B * lam_t[1]).sum()
     L.backward()
     return S_t.grad.numpy(), float(sig.grad), None if F_t is None else F_t.grad.numpy()
@@ -96,6 +119,20 @@ def test_adjoint_one_step_f64_matches_oracle_autograd(stencil, shape):
     assert e[0] < 1e-11 and e[1] < 1e-10 and e[2] < 1e-11
 
 
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (1, 1, 1, 1), (3, 1, 1, 3)])
+@pytest.mark.parametrize("shape", [(12, 10), (33, 40)])
+def test_adjoint_one_step_walls_f64_matches_oracle_autograd(stencil, shape):
+    """Walls at rows 0 and ny - 1: the stencils' mirror images and the
+    bounce-back transposed."""
+    nx, ny = shape
+    params, rn, S, lam, force = state_and_params(nx, ny, seed=3 * nx + ny, stencil=stencil, walls=True)
+    gS, gsig, gF = oracle_vjp(params, S, lam, force)
+    aS, asig, aF = gpu_vjp(params, rn, S, lam, force)
+    e = (rel(aS, gS), abs(asig - gsig) / abs(gsig), rel(aF, gF))
+    print("adjoint walls f64 %s %s: pops %.2e sigma %.2e force %.2e" % (shape, stencil, *e))
+    assert e[0] < 1e-11 and e[1] < 1e-10 and e[2] < 1e-11
+
+
 @pytest.mark.parametrize("extra", [dict(ghost_eq=1), dict(fixed_K=0.05), dict(recolor=False)])
 def test_adjoint_one_step_options_f64(extra):
     nx, ny = 24, 20
@@ -119,17 +156,18 @@ def test_adjoint_one_step_f32_against_f64():
     assert e[0] < 1e-4 and e[1] < 1e-4 and e[2] < 1e-4
 
 
-def test_rhoN_and_init_adjoints_match_autograd():
+@pytest.mark.parametrize("walls", [False, True])
+def test_rhoN_and_init_adjoints_match_autograd(walls):
     nx, ny = 20, 16
-    params, rn, S, lam, force = state_and_params(nx, ny, seed=3)
+    params, rn, S, lam, force = state_and_params(nx, ny, seed=3, walls=walls)
     rng = np.random.default_rng(4)
     w = rng.standard_normal((ny, nx))
     # colour index of the pre-collision state of S
     S_t = torch.tensor(S, requires_grad=True)
-    P = torch_pull(S_t)
+    P = torch_pull_walls(S_t) if walls else torch_pull(S_t)
     p = O.Params(nx=nx, ny=ny, **params)
     rhoN = O.colour_index(P[0].sum(0), P[1].sum(0), p)
-    (rhoN * torch.tensor(w)).sum().backward()
+    (rhoN * torch.tensor(w[1:ny - 1] if walls else w)).sum().backward()
     sim = lbm.Simulation(nx, ny, params, rn, storage="f64", device=DEV)
     out = torch.empty((2, 9, ny, nx), dtype=torch.float64, device=DEV)
     sim.rhoN_adjoint(torch.tensor(S, device=DEV), torch.tensor(w, device=DEV), out)
@@ -142,6 +180,18 @@ def test_rhoN_and_init_adjoints_match_autograd():
     phi = O.rest_fractions(rhoR, rhoB, p)
     pre = torch.stack([rhoR * phi, rhoB * phi])               # pre-collision at each site
     buf = torch.stack([torch.roll(pre[:, i], shifts=(-C[i][1], -C[i][0]), dims=(-2, -1)) for i in range(9)], dim=1)
+    if walls:   # word i at s next to a solid row holds link opp(i) of s; solid rows hold nothing
+        rows = []
+        for y in range(ny):
+            if y in (0, ny - 1):
+                rows.append(torch.zeros_like(buf[:, :, y]))
+                continue
+            links = []
+            for i in range(9):
+                ys = y + C[i][1]
+                links.append(pre[:, OPP[i], y] if ys in (0, ny - 1) else buf[:, i, y])
+            rows.append(torch.stack(links, dim=1))
+        buf = torch.stack(rows, dim=2)
     (buf * torch.tensor(lam)).sum().backward()
     g0 = torch.zeros((ny, nx), dtype=torch.float64, device=DEV)
     sim.init_adjoint(torch.tensor(lam, device=DEV), g0)
