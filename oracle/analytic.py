@@ -4,6 +4,9 @@
                          no-slip walls, Sturm-Liouville eigen-expansion.
 * ``stratified_steady`` App. D: steady force-driven flow with a continuous
                          transverse density profile, Simpson quadrature.
+* ``radial_transient``  App. D (curved interfaces): decay of an azimuthal flow
+                         in a circular container with a dense core,
+                         Bessel-function eigen-expansion.
 * ``laplace_pressure``  Laplace's law for a 2D drop, Delta p = sigma / R
                          (Sec. IV, curved interfaces).
 * ``transient_error``   the error measure epsilon(t) of Sec. IV.
@@ -172,6 +175,108 @@ def stratified_steady(x, H, nu, G, density, nsub=400):
         fx = (H - 2.0 * a) / density(a)
         out.append(G / (2.0 * nu) * _simpson(fx, xs / (2 * nsub)))
     return np.array(out)
+
+
+# ----------------------------------------------------------------------------
+# App. D, curved interfaces: azimuthal transient in a circular container
+# ----------------------------------------------------------------------------
+# rho(r) du/dt = (1/r^2) d/dr (r^3 eta d/dr (u/r)), u(R) = 0, fluid 1 (density
+# rho1) for r < R0, fluid 2 beyond, one shear viscosity eta.  In each region
+# u = e^{-c^2 t} phi(r) with phi'' + phi'/r - phi/r^2 = -(c^2/nu) phi (Bessel's
+# equation of order 1 in k r, k = c/sqrt(nu)): phi = a J1(k1 r) inside (regular
+# at 0) and b Z(r) outside, Z(r) = J1(k2 r) Y1(k2 R) - Y1(k2 r) J1(k2 R)
+# (zero at the wall).  Continuity of u and of the traction eta r d/dr(u/r)
+# (with one eta: of phi and phi') at R0 fixes c.  The modes are orthogonal
+# with weight rho r (the paper writes the same weight as r/nu = r rho/eta).
+
+def _radial_parts(c, R0, R, nu1, nu2):
+    """(J1(k1 R0), k1 J1'(k1 R0), Z(R0), Z'(R0), k1, k2)."""
+    from scipy.special import j1, y1, jvp, yvp
+    k1, k2 = c / math.sqrt(nu1), c / math.sqrt(nu2)
+    jR, yR = j1(k2 * R), y1(k2 * R)
+    Z = j1(k2 * R0) * yR - y1(k2 * R0) * jR
+    dZ = k2 * (jvp(1, k2 * R0) * yR - yvp(1, k2 * R0) * jR)
+    return j1(k1 * R0), k1 * jvp(1, k1 * R0), Z, dZ, k1, k2
+
+
+def _radial_char(c, R0, R, nu1, nu2):
+    """Matching determinant: zero when a J1 and b Z join with equal value and slope."""
+    J, dJ, Z, dZ, _, _ = _radial_parts(c, R0, R, nu1, nu2)
+    return J * dZ - dJ * Z
+
+
+def radial_eigenvalues(R0, R, nu1, nu2, n_modes):
+    """First n_modes positive roots c_n of the matching determinant (the paper
+    uses Newton iteration; here a fine scan brackets each root and Brent's
+    method refines it)."""
+    from scipy.optimize import brentq
+    step = math.pi * math.sqrt(min(nu1, nu2)) / R / 64.0
+    roots = []
+    c = step * 1e-3
+    f_prev = _radial_char(c, R0, R, nu1, nu2)
+    while len(roots) < n_modes:
+        c_next = c + step
+        f_next = _radial_char(c_next, R0, R, nu1, nu2)
+        if f_prev * f_next < 0.0:
+            roots.append(brentq(_radial_char, c, c_next, args=(R0, R, nu1, nu2), xtol=1e-15, rtol=1e-15))
+        c, f_prev = c_next, f_next
+    return np.array(roots)
+
+
+def _lommel(C, dC, k, r):
+    """int_0^r s C(k s)^2 ds for a cylinder function C of order 1 (Lommel's
+    integral): r^2/2 [C'(k r)^2 + (1 - 1/(k r)^2) C(k r)^2], minus its value at
+    the lower end (zero for J1 at 0)."""
+    x = k * r
+    return 0.5 * r * r * (dC(x) ** 2 + (1.0 - 1.0 / (x * x)) * C(x) ** 2)
+
+
+def radial_modes(R0, R, rho1, rho2, eta, n_modes):
+    """Eigen-pairs: c_n and the coefficients (a_n, b_n) of phi_n = a_n J1(k1 r)
+    inside, b_n Z(r) outside, normalised so that int_0^R rho r phi_n^2 dr = 1."""
+    from scipy.special import j1, y1, jvp, yvp
+    nu1, nu2 = eta / rho1, eta / rho2
+    cs = radial_eigenvalues(R0, R, nu1, nu2, n_modes)
+    a, b = [], []
+    for c in cs:
+        J, dJ, Z, dZ, k1, k2 = _radial_parts(c, R0, R, nu1, nu2)
+        # b Z(R0) = a J1(k1 R0): take a = 1, then b from whichever is larger
+        bb = J / Z if abs(Z) > abs(dZ) / k2 else dJ / dZ
+        jR, yR = j1(k2 * R), y1(k2 * R)
+        Cz = lambda x: j1(x) * yR - y1(x) * jR
+        dCz = lambda x: jvp(1, x) * yR - yvp(1, x) * jR
+        inner = _lommel(j1, lambda x: jvp(1, x), k1, R0)
+        outer = _lommel(Cz, dCz, k2, R) - _lommel(Cz, dCz, k2, R0)
+        norm = rho1 * inner + rho2 * bb * bb * outer
+        s = 1.0 / math.sqrt(norm)
+        a.append(s)
+        b.append(s * bb)
+    return cs, np.array(a), np.array(b)
+
+
+def radial_phi(r, c, a, b, R0, R, rho1, rho2, eta):
+    """phi_n(r) of the container transient."""
+    from scipy.special import j1, y1
+    nu1, nu2 = eta / rho1, eta / rho2
+    k1, k2 = c / math.sqrt(nu1), c / math.sqrt(nu2)
+    r = np.asarray(r, dtype=float)
+    Z = j1(k2 * r) * y1(k2 * R) - y1(k2 * r) * j1(k2 * R)
+    return np.where(r < R0, a * j1(k1 * r), b * Z)
+
+
+def radial_transient(r, t, R0, R, rho1, rho2, eta, omega, n_modes=200):
+    """u_phi(r, t) from rigid rotation u_phi = omega r of the core (r < R0),
+    fluid 2 at rest: sigma_n = int rho r u_phi(r, 0) phi_n dr
+    = rho1 a_n omega R0^2 J2(k1 R0) / k1 (int_0^R0 r^2 J1(k r) dr = R0^2 J2(k R0)/k)."""
+    from scipy.special import jv
+    nu1 = eta / rho1
+    cs, a, b = radial_modes(R0, R, rho1, rho2, eta, n_modes)
+    u = np.zeros_like(np.asarray(r, dtype=float))
+    for c, an, bn in zip(cs, a, b):
+        k1 = c / math.sqrt(nu1)
+        sig = rho1 * an * omega * R0 * R0 * jv(2, k1 * R0) / k1
+        u = u + sig * math.exp(-c * c * t) * radial_phi(r, c, an, bn, R0, R, rho1, rho2, eta)
+    return u
 
 
 # ----------------------------------------------------------------------------

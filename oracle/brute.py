@@ -4,8 +4,10 @@ A second, independent transcription of the local pieces of the scheme, in
 plain Python floats and explicit index loops, so that whole-lattice sweeps in
 ``chromo`` (and the HIP path) can be checked against it on 4x4 to 8x8 lattices:
 
-* streaming with periodic wrap and half-way bounce-back (Sec. II kinetic eq.);
-* the App. B gradient stencil, with explicit modular / mirrored indices;
+* streaming with periodic wrap and half-way bounce-back (Sec. II kinetic eq.),
+  at wall rows or at the solid sites of a mask;
+* the App. B gradient stencil, with explicit modular / mirrored indices (a
+  tap on a solid site of a mask reads the centre value);
 * the closed-form post-collision distribution printed in Sec. III / App. A
   (f+_i = w_i {[2 - 3/2 |c_i|^2] rho + 3 j+.c_i + 9/2 c_i.Pi+.c_i
   - 3/2 tr Pi+ + g_i N+/4 + 3/8 g_i J+.c_i}), fed by the modal evolution eqs.;
@@ -18,19 +20,27 @@ import math
 from .lattice import C, W, GHOST, OPP, Q, CHAT, K_PHI, STENCIL_COEFFS
 
 
-def stream_site_by_site(pops, nx, ny, walls):
+def stream_site_by_site(pops, nx, ny, walls, solid=None):
     """Push each post-collision population along its link; a link that would
-    enter a solid row (0 or ny-1 when ``walls``) comes back reversed."""
+    enter a solid row (0 or ny-1 when ``walls``) or a solid site of the mask
+    ``solid`` (nested [ny][nx] truth values) comes back reversed.  Solid sites
+    end up holding 0."""
     out = [[[[None] * nx for _ in range(ny)] for _ in range(Q)] for _ in range(2)]
     rows = range(1, ny - 1) if walls else range(ny)
     for col in range(2):
         for y in rows:
             for x in range(nx):
+                if solid is not None and solid[y][x]:
+                    for i in range(Q):
+                        out[col][i][y][x] = 0.0
+                    continue
                 for i in range(Q):
                     cx, cy = C[i]
                     xd = (x + cx) % nx
                     yd = y + cy
                     if walls and (yd <= 0 or yd >= ny - 1):
+                        out[col][OPP[i]][y][x] = pops[col][i][y][x]
+                    elif solid is not None and solid[yd % ny][xd]:
                         out[col][OPP[i]][y][x] = pops[col][i][y][x]
                     else:
                         out[col][i][yd % ny][xd] = pops[col][i][y][x]
@@ -49,15 +59,19 @@ def mirrored(y, ny, walls):
     return 1 + (2 * F - 1 - t), True
 
 
-def gradient_at(field, x, y, nx, ny, radius, walls, odd_y=False):
-    """(d/dx, d/dy) of a scalar lattice field at one site with the App. B stencil."""
+def gradient_at(field, x, y, nx, ny, radius, walls, odd_y=False, solid=None):
+    """(d/dx, d/dy) of a scalar lattice field at one site with the App. B
+    stencil; a tap on a solid site of ``solid`` reads the centre value."""
     gx = gy = 0.0
     for N, b in enumerate(STENCIL_COEFFS[radius], start=1):
         sx = sy = 0.0
         for i in range(1, Q):
             cx, cy = C[i]
             yy, refl = mirrored(y + N * cy, ny, walls)
-            v = field[yy][(x + N * cx) % nx]
+            xx = (x + N * cx) % nx
+            v = field[yy][xx]
+            if solid is not None and solid[yy][xx]:
+                v = field[y][x]
             if refl and odd_y:
                 v = -v
             sx += W[i] * cx * v
@@ -128,70 +142,68 @@ def local_recolour(fplus, rhoR, rhoB, mx, my, prm):
 def full_step(pops, prm, force=None):
     """One whole step, site by site, on a tiny lattice (pre-collision in, pre-collision out)."""
     nx, ny, walls = prm.nx, prm.ny, prm.walls
+    solid = getattr(prm, 'solid', None)
     rows = list(range(1, ny - 1)) if walls else list(range(ny))
+    sites = [(x, y) for y in rows for x in range(nx) if solid is None or not solid[y][x]]
     rg, rk, rphi, ru = prm.stencil
     nanrow = [float('nan')] * nx
     def blank():
         return [list(nanrow) for _ in range(ny)]
     rhoR, rhoB, rho, jx, jy, rhoN, lam3, Php = (blank() for _ in range(8))
-    for y in rows:
-        for x in range(nx):
-            R = [pops[0][i][y][x] for i in range(Q)]
-            B = [pops[1][i][y][x] for i in range(Q)]
-            rR, rB = sum(R), sum(B)
-            rhoR[y][x], rhoB[y][x] = rR, rB
-            rho[y][x] = rR + rB
-            jx[y][x] = sum((R[i] + B[i]) * C[i][0] for i in range(Q))
-            jy[y][x] = sum((R[i] + B[i]) * C[i][1] for i in range(Q))
-            a, b = rR / prm.rho0_R, rB / prm.rho0_B
-            rn = (a - b) / (a + b)
-            rhoN[y][x] = rn
-            nu = prm.nu_R * (1 + rn) / 2 + prm.nu_B * (1 - rn) / 2
-            lam3[y][x] = 2.0 / (6.0 * nu + 1.0)
-            Php[y][x] = 0.6 * (1 - prm.alpha_R) * (rR + prm.rho0_R / prm.rho0_B * rB) - (rR + rB) / 3.0
+    for x, y in sites:
+        R = [pops[0][i][y][x] for i in range(Q)]
+        B = [pops[1][i][y][x] for i in range(Q)]
+        rR, rB = sum(R), sum(B)
+        rhoR[y][x], rhoB[y][x] = rR, rB
+        rho[y][x] = rR + rB
+        jx[y][x] = sum((R[i] + B[i]) * C[i][0] for i in range(Q))
+        jy[y][x] = sum((R[i] + B[i]) * C[i][1] for i in range(Q))
+        a, b = rR / prm.rho0_R, rB / prm.rho0_B
+        rn = (a - b) / (a + b)
+        rhoN[y][x] = rn
+        nu = prm.nu_R * (1 + rn) / 2 + prm.nu_B * (1 - rn) / 2
+        lam3[y][x] = 2.0 / (6.0 * nu + 1.0)
+        Php[y][x] = 0.6 * (1 - prm.alpha_R) * (rR + prm.rho0_R / prm.rho0_B * rB) - (rR + rB) / 3.0
     gnx, gny, mx, my = blank(), blank(), blank(), blank()
-    for y in rows:
-        for x in range(nx):
-            gx, gy = gradient_at(rhoN, x, y, nx, ny, rg, walls)
-            s = math.sqrt(gx * gx + gy * gy + prm.eps_n ** 2)
-            gnx[y][x], gny[y][x] = gx, gy
-            mx[y][x], my[y][x] = gx / s, gy / s
+    for x, y in sites:
+        gx, gy = gradient_at(rhoN, x, y, nx, ny, rg, walls, solid=solid)
+        s = math.sqrt(gx * gx + gy * gy + prm.eps_n ** 2)
+        gnx[y][x], gny[y][x] = gx, gy
+        mx[y][x], my[y][x] = gx / s, gy / s
     nxf = [[-v for v in row] for row in mx]
     nyf = [[-v for v in row] for row in my]
     Gx, Gy, ux, uy = blank(), blank(), blank(), blank()
-    for y in rows:
-        for x in range(nx):
-            if prm.fixed_K is None:
-                K = gradient_at(nxf, x, y, nx, ny, rk, walls)[0] + \
-                    gradient_at(nyf, x, y, nx, ny, rk, walls, odd_y=True)[1]
-            else:
-                K = prm.fixed_K
-            gx = 0.5 * prm.sigma * K * gnx[y][x] + prm.gx
-            gy = 0.5 * prm.sigma * K * gny[y][x] + prm.gy
-            if force is not None:
-                gx += float(force[0][y][x])
-                gy += float(force[1][y][x])
-            Gx[y][x], Gy[y][x] = gx, gy
-            ux[y][x] = (jx[y][x] + 0.5 * gx) / rho[y][x]
-            uy[y][x] = (jy[y][x] + 0.5 * gy) / rho[y][x]
+    for x, y in sites:
+        if prm.fixed_K is None:
+            K = gradient_at(nxf, x, y, nx, ny, rk, walls, solid=solid)[0] + \
+                gradient_at(nyf, x, y, nx, ny, rk, walls, odd_y=True, solid=solid)[1]
+        else:
+            K = prm.fixed_K
+        gx = 0.5 * prm.sigma * K * gnx[y][x] + prm.gx
+        gy = 0.5 * prm.sigma * K * gny[y][x] + prm.gy
+        if force is not None:
+            gx += float(force[0][y][x])
+            gy += float(force[1][y][x])
+        Gx[y][x], Gy[y][x] = gx, gy
+        ux[y][x] = (jx[y][x] + 0.5 * gx) / rho[y][x]
+        uy[y][x] = (jy[y][x] + 0.5 * gy) / rho[y][x]
     post = [[[[0.0] * nx for _ in range(ny)] for _ in range(Q)] for _ in range(2)]
-    for y in rows:
-        for x in range(nx):
-            dPx, dPy = gradient_at(Php, x, y, nx, ny, rphi, walls)
-            theta = gradient_at(ux, x, y, nx, ny, ru, walls)[0] + \
-                gradient_at(uy, x, y, nx, ny, ru, walls, odd_y=True)[1]
-            l3 = lam3[y][x]
-            k = 1 - l3 / 2
-            u_x, u_y = ux[y][x], uy[y][x]
-            iso = u_x * dPx + u_y * dPy - rho[y][x] * theta / 3
-            Cxx = k * (2 * u_x * (Gx[y][x] - dPx) - iso)
-            Cyy = k * (2 * u_y * (Gy[y][x] - dPy) - iso)
-            Cxy = k * (u_x * (Gy[y][x] - dPy) + u_y * (Gx[y][x] - dPx))
-            R = [pops[0][i][y][x] for i in range(Q)]
-            B = [pops[1][i][y][x] for i in range(Q)]
-            fp = local_collide(R, B, Gx[y][x], Gy[y][x], u_x, u_y, Cxx, Cyy, Cxy, l3, prm)
-            Rpp, Bpp = local_recolour(fp, rhoR[y][x], rhoB[y][x], mx[y][x], my[y][x], prm)
-            for i in range(Q):
-                post[0][i][y][x] = Rpp[i]
-                post[1][i][y][x] = Bpp[i]
-    return stream_site_by_site(post, nx, ny, walls)
+    for x, y in sites:
+        dPx, dPy = gradient_at(Php, x, y, nx, ny, rphi, walls, solid=solid)
+        theta = gradient_at(ux, x, y, nx, ny, ru, walls, solid=solid)[0] + \
+            gradient_at(uy, x, y, nx, ny, ru, walls, odd_y=True, solid=solid)[1]
+        l3 = lam3[y][x]
+        k = 1 - l3 / 2
+        u_x, u_y = ux[y][x], uy[y][x]
+        iso = u_x * dPx + u_y * dPy - rho[y][x] * theta / 3
+        Cxx = k * (2 * u_x * (Gx[y][x] - dPx) - iso)
+        Cyy = k * (2 * u_y * (Gy[y][x] - dPy) - iso)
+        Cxy = k * (u_x * (Gy[y][x] - dPy) + u_y * (Gx[y][x] - dPx))
+        R = [pops[0][i][y][x] for i in range(Q)]
+        B = [pops[1][i][y][x] for i in range(Q)]
+        fp = local_collide(R, B, Gx[y][x], Gy[y][x], u_x, u_y, Cxx, Cyy, Cxy, l3, prm)
+        Rpp, Bpp = local_recolour(fp, rhoR[y][x], rhoB[y][x], mx[y][x], my[y][x], prm)
+        for i in range(Q):
+            post[0][i][y][x] = Rpp[i]
+            post[1][i][y][x] = Bpp[i]
+    return stream_site_by_site(post, nx, ny, walls, solid)

@@ -35,7 +35,15 @@ a parameter or a constant here, and the HIP path takes the same reading):
 * all derivatives use fields of the current time step;
 * walls (rows 0 and ny-1 solid) use half-way bounce-back, and every stencil
   sees a mirror image of the fluid about the wall planes (scalars and
-  x-components even, y-components odd).
+  x-components even, y-components odd);
+* solid sites anywhere (``Params.solid``, a staircase obstacle such as the
+  circular no-slip wall of the curved-interface transient, Sec. IV and
+  App. D) also use half-way bounce-back; a stencil tap that falls on a solid
+  site reads the value of the field at the stencil's own centre (a
+  zero-gradient continuation, so a uniform field has zero derivative next to
+  any obstacle).  The mirror image of the walls has no unique form on a
+  staircase; this continuation is the simplest that keeps the stencils exact
+  on constants.
 """
 from dataclasses import dataclass, field
 import functools
@@ -68,6 +76,7 @@ class Params:
     fixed_K: float = None          # if set, K := fixed_K (Sec. IV, fixed curvature)
     recolor: bool = True
     eps_n: float = 1e-6
+    solid: object = None           # optional [ny][nx] booleans: solid sites anywhere (needs walls=False)
 
     @property
     def Lambda(self):
@@ -81,6 +90,19 @@ def _tensor(vals, dtype):
 # ----------------------------------------------------------------------------
 # lattice geometry
 # ----------------------------------------------------------------------------
+
+def solid_mask(p):
+    """Solid sites as a bool tensor [ny, nx], or None when only the wall rows
+    (or nothing) are solid."""
+    if p.solid is None:
+        return None
+    if p.walls:
+        raise ValueError("solid sites anywhere need walls=False (the mask may hold solid rows)")
+    m = torch.as_tensor(p.solid).to(torch.bool)
+    if tuple(m.shape) != (p.ny, p.nx):
+        raise ValueError("solid mask must have shape (ny, nx)")
+    return m
+
 
 def fluid_rows(p):
     """Row indices of fluid sites (all rows when y is periodic)."""
@@ -127,11 +149,12 @@ def _mirror_map(F, dy):
     return _MIRROR_CACHE[key]
 
 
-def gradient(s, radius, walls, odd_y=False):
+def gradient(s, radius, walls, odd_y=False, solid=None):
     """First-derivative stencil of App. B: d s/d alpha = sum_N b_N sum_i w_i c_ia s(r + N c_i).
 
     radius 1 gives the compact isotropic stencil (b = 3); radius 3 the
-    sixth-order non-compact one (b = 9/2, -9/10, 1/10).
+    sixth-order non-compact one (b = 9/2, -9/10, 1/10).  With a solid mask
+    a tap on a solid site reads s at the centre r.
     """
     gx = torch.zeros_like(s)
     gy = torch.zeros_like(s)
@@ -141,6 +164,8 @@ def gradient(s, radius, walls, odd_y=False):
         for i in range(1, Q):
             cx, cy = C[i]
             v = shift(s, N * cx, N * cy, walls, odd_y)
+            if solid is not None:
+                v = torch.where(shift(solid, N * cx, N * cy, False), s, v)
             sx = sx + W[i] * cx * v
             sy = sy + W[i] * cy * v
         gx = gx + b * sx
@@ -148,10 +173,10 @@ def gradient(s, radius, walls, odd_y=False):
     return gx, gy
 
 
-def divergence(vx, vy, radius, walls):
+def divergence(vx, vy, radius, walls, solid=None):
     """div v = d v_x/dx + d v_y/dy with the App. B stencil (v_y odd under the wall mirror)."""
-    dxx, _ = gradient(vx, radius, walls, odd_y=False)
-    _, dyy = gradient(vy, radius, walls, odd_y=True)
+    dxx, _ = gradient(vx, radius, walls, odd_y=False, solid=solid)
+    _, dyy = gradient(vy, radius, walls, odd_y=True, solid=solid)
     return dxx + dyy
 
 
@@ -282,11 +307,21 @@ def recolour(fplus, rhoR, rhoB, mx, my, p):
     return torch.stack(Rpp), torch.stack(Bpp)
 
 
-def stream(S, walls):
+def stream(S, walls, solid=None):
     """f_i(r + c_i, t + 1) = S_i(r, t); a link that would enter a wall returns
     to its own site reversed (half-way bounce-back, walls at y = 1/2 and F - 1/2
-    on the fluid strip).  S has shape [9, F, nx] (fluid rows only)."""
+    on the fluid strip).  S has shape [9, F, nx] (fluid rows only).  With a
+    solid mask (full lattice, periodic) a link whose target is a solid site
+    returns the same way, and solid sites hold zero."""
     out = torch.empty_like(S)
+    if solid is not None:
+        for i in range(Q):
+            cx, cy = C[i]
+            moved = torch.roll(S[i], shifts=(cy, cx), dims=(-2, -1))            # S_i(r - c_i)
+            from_solid = torch.roll(solid, shifts=(cy, cx), dims=(-2, -1))      # r - c_i solid?
+            out[i] = torch.where(from_solid, S[OPP[i]], moved)
+        out[:, solid] = 0.0
+        return out
     F = S.shape[-2]
     for i in range(Q):
         cx, cy = C[i]
@@ -326,6 +361,7 @@ def _force_field(force, p, F, dtype):
 def interface_fields(R, B, p, force=None):
     """Steps 1-5 of the time step on the fluid strip; returns a dict of fields."""
     walls = p.walls
+    solid = solid_mask(p)
     rg, rk, rphi, ru = p.stencil
     rhoR, rhoB = colour_densities(R, B)
     rho = rhoR + rhoB
@@ -335,12 +371,12 @@ def interface_fields(R, B, p, force=None):
     lam3 = lambda3(rhoN, p)
     Php = phi_prime(rhoR, rhoB, p)
     # colour gradient and director
-    gnx, gny = gradient(rhoN, rg, walls)
+    gnx, gny = gradient(rhoN, rg, walls, solid=solid)
     norm = torch.sqrt(gnx * gnx + gny * gny + p.eps_n * p.eps_n)
     mx, my = gnx / norm, gny / norm
     nx_, ny_ = -mx, -my                      # outward normal of a red drop (Sec. II)
     if p.fixed_K is None:
-        K = divergence(nx_, ny_, rk, walls)
+        K = divergence(nx_, ny_, rk, walls, solid)
     else:
         K = torch.full_like(rho, p.fixed_K)
     Gx = 0.5 * p.sigma * K * gnx + p.gx
@@ -351,8 +387,8 @@ def interface_fields(R, B, p, force=None):
         Gy = Gy + ff[1]
     ux = (jx + 0.5 * Gx) / rho
     uy = (jy + 0.5 * Gy) / rho
-    dPx, dPy = gradient(Php, rphi, walls)
-    theta = divergence(ux, uy, ru, walls)
+    dPx, dPy = gradient(Php, rphi, walls, solid=solid)
+    theta = divergence(ux, uy, ru, walls, solid)
     return dict(rhoR=rhoR, rhoB=rhoB, rho=rho, f=f, jx=jx, jy=jy, rhoN=rhoN, lam3=lam3,
                 Phip=Php, gnx=gnx, gny=gny, mx=mx, my=my, K=K, Gx=Gx, Gy=Gy,
                 ux=ux, uy=uy, dPx=dPx, dPy=dPy, theta=theta)
@@ -372,10 +408,12 @@ class Oracle:
     """Time stepper holding the pre-collision populations of the fluid sites.
 
     ``R`` and ``B`` have shape [9, F, nx] with F = ny (periodic) or ny - 2 (walls).
+    With a solid mask they cover the whole lattice and are zero at solid sites.
     """
 
     def __init__(self, p, dtype=torch.float64, force=None):
         self.p = p
+        self.solid = solid_mask(p)
         self.dtype = dtype
         self.force = None if force is None else torch.as_tensor(force, dtype=dtype)
         self.t = 0
@@ -395,8 +433,14 @@ class Oracle:
         phi = rest_fractions(rhoR, rhoB, p)
         self.R = rhoR * phi
         self.B = rhoB * phi
+        self._clear_solid()
         self.t = 0
         return self
+
+    def _clear_solid(self):
+        if self.solid is not None:
+            self.R[:, self.solid] = 0.0
+            self.B[:, self.solid] = 0.0
 
     def init_moving(self, rhoN0, ux, uy):
         """Initial state with a velocity field: C_i = (rho_C/rho) f^(0)_i(rho, u)
@@ -413,6 +457,7 @@ class Oracle:
         rho = rhoR + rhoB
         self.R = rhoR / rho * f0
         self.B = rhoB / rho * f0
+        self._clear_solid()
         self.t = 0
         return self
 
@@ -428,15 +473,15 @@ class Oracle:
     def step(self, n=1):
         for _ in range(n):
             Rpp, Bpp = self.post_collision()
-            self.R = stream(Rpp, self.p.walls)
-            self.B = stream(Bpp, self.p.walls)
+            self.R = stream(Rpp, self.p.walls, self.solid)
+            self.B = stream(Bpp, self.p.walls, self.solid)
             self.t += 1
         return self
 
     # -- observation ----------------------------------------------------------
     def fields(self):
         """rho, u (force-adjusted, Sec. II), rho^N on the full [ny, nx] lattice;
-        solid rows are NaN."""
+        solid rows and solid sites are NaN."""
         d = interface_fields(self.R, self.B, self.p, self.force)
         return {k: self._full(d[k]) for k in ('rho', 'ux', 'uy', 'rhoN', 'rhoR', 'rhoB')}
 
@@ -444,6 +489,8 @@ class Oracle:
         return float(self.R.sum()), float(self.B.sum())
 
     def _full(self, a):
+        if self.solid is not None:
+            return torch.where(self.solid, torch.full_like(a, float('nan')), a)
         if not self.p.walls:
             return a
         out = torch.full((self.p.ny, self.p.nx), float('nan'), dtype=a.dtype)

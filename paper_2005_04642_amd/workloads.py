@@ -14,6 +14,8 @@ take their structure):
 * ``emulsion``         4096x4096 periodic, 50 non-overlapping drops, radii U[20, 80]
 * ``ellipse_drop``     one axis-aligned elliptic drop per lattice (batched runs)
 * ``gaussian_bumps``   smooth per-site body-force field
+* ``circular_wall``    solid mask of a circular container (staircase wall)
+* ``config_curved_transient``  rotating dense core inside a circular wall
 """
 import math
 
@@ -138,6 +140,23 @@ def gaussian_bumps(nx, ny, nbumps=8, width=24.0, amplitude=1e-6, seed=2):
     return out
 
 
+def circular_wall(nx, ny, radius, center=None):
+    """Solid mask (True = solid) of a circular no-slip container: every site at
+    distance >= radius from the centre (default ((nx-1)/2, (ny-1)/2)) is solid,
+    a staircase approximation of the wall at r = radius."""
+    cx, cy = center if center is not None else ((nx - 1) / 2.0, (ny - 1) / 2.0)
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    return (x - cx) ** 2 + (y - cy) ** 2 >= radius * radius
+
+
+def random_solid_sites(nx, ny, count, seed):
+    """Mask with ``count`` distinct solid sites drawn uniformly (parity tests)."""
+    rng = np.random.default_rng(seed)
+    m = np.zeros(ny * nx, dtype=bool)
+    m[rng.choice(ny * nx, size=count, replace=False)] = True
+    return m.reshape(ny, nx)
+
+
 def random_state_perturbation(shape, scale, seed):
     """Multiplicative noise field (1 + scale U[-1, 1]) used by parity tests to
     drive the step away from equilibrium."""
@@ -178,6 +197,30 @@ def config_emulsion(nx=4096, ny=4096, seed=0):
     p = base_params(Lambda=10.0, sigma=0.005)
     return dict(nx=nx, ny=ny, steps=1000, params=p,
                 rhoN0=emulsion(nx, ny, 50, 20.0, 80.0, 6.0, seed) if nx >= 1024 else None)
+
+
+def config_curved_transient(Lambda, R0=120.0, R=360.0, eta=0.333, beta=0.3, sigma=0.001, u0=1e-3):
+    """Decaying rotation of a dense red core inside a circular no-slip wall
+    (Sec. IV, dynamics of curved interfaces; App. D): red for r < R0, blue
+    out to the wall at r = R, equal shear viscosity eta (nu_C = eta / rho_0C),
+    segregation beta = 0.3 and R0 = 120, R = 360 as in the paper.  The red
+    core starts in rigid rotation with speed u0 at r = R0 (u_phi = u0 r / R0
+    weighted by the red fraction (1 + rho^N)/2 of the tanh profile), the blue
+    fluid at rest.  The paper prints neither sigma nor the speed: sigma = 1e-3,
+    u0 = 1e-3.  Lattice: the smallest square with one solid ring outside r = R.
+    Returns nx, ny, params, rhoN0, ux0, uy0, solid, centre."""
+    n = int(2 * (math.ceil(R) + 2))
+    c = (n - 1) / 2.0
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    r = np.hypot(x - c, y - c)
+    rn = np.tanh(0.9 * beta * (R0 - r))
+    red = 0.5 * (1.0 + rn)
+    omega = u0 / R0
+    ux0 = -omega * (y - c) * red
+    uy0 = omega * (x - c) * red
+    p = base_params(Lambda=Lambda, sigma=sigma, beta=beta)
+    p.update(nu_R=eta / p["rho0_R"], nu_B=eta / p["rho0_B"])
+    return n, n, p, rn, ux0, uy0, circular_wall(n, n, R, (c, c)), (c, c)
 
 
 def emulsion_crop(n=512, ndrops=3, seed=0):

@@ -1,5 +1,5 @@
 """Pins of the semi-analytic reference solutions themselves (App. C, App. D)
-against closed forms and an independent finite-difference solution."""
+against closed forms and independent finite-difference solutions."""
 import math
 
 import numpy as np
@@ -90,3 +90,71 @@ def test_laplace_and_error_measure():
     u = np.array([1.0, 2.0, 4.0])
     assert A.transient_error(u, u) == 0.0
     assert abs(A.transient_error(np.array([1.0, 2.0]), np.array([1.0, 1.0])) - 0.125) < 1e-15
+
+
+# ----------------------------------------------------------------------------
+# App. D, curved interfaces: azimuthal transient in a circular container
+# ----------------------------------------------------------------------------
+
+def fd_radial(R0, R, rho1, rho2, eta, omega, T, n=600):
+    """Crank-Nicolson finite volumes for rho r u_t = eta [(r u_r)_r - u/r],
+    u(0) = u(R) = 0, from u = omega r (r < R0), 0 beyond."""
+    dr = R / n
+    r = (np.arange(n) + 0.5) * dr
+    rf = np.arange(n + 1) * dr
+    rho = np.where(r < R0, rho1, rho2)
+    L = np.zeros((n, n))
+    for i in range(n):
+        m = rho[i] * r[i] * dr
+        wr = eta * rf[i + 1] / dr * (2 if i == n - 1 else 1)   # wall at R: u = 0 half a cell away
+        wl = eta * rf[i] / dr
+        L[i, i] = -(wl + wr + eta * dr / r[i]) / m
+        if i > 0:
+            L[i, i - 1] = wl / m
+        if i < n - 1:
+            L[i, i + 1] = wr / m
+    u = np.where(r < R0, omega * r, 0.0)
+    dt = 0.05
+    I = np.eye(n)
+    step = np.linalg.solve(I - 0.5 * dt * L, I + 0.5 * dt * L)
+    for _ in range(int(round(T / dt))):
+        u = step @ u
+    return r, u
+
+
+def test_radial_equal_densities_give_bessel_zeros():
+    """One fluid: the container's modes are J1(c r / sqrt(nu)) with
+    c R / sqrt(nu) the zeros of J1."""
+    from scipy.special import jn_zeros
+    R0, R, eta = 12.0, 36.0, 0.333
+    cs = A.radial_eigenvalues(R0, R, eta, eta, 8)
+    assert np.max(np.abs(cs * R / math.sqrt(eta) / jn_zeros(1, 8) - 1.0)) < 1e-12
+
+
+def test_radial_modes_orthonormal_and_matched():
+    R0, R, rho1, rho2, eta = 12.0, 36.0, 1.0, 0.2, 0.333
+    cs, a, b = A.radial_modes(R0, R, rho1, rho2, eta, 6)
+    r = np.linspace(0, R, 400001)
+    rho = np.where(r < R0, rho1, rho2)
+    phis = [A.radial_phi(r, c, an, bn, R0, R, rho1, rho2, eta) for c, an, bn in zip(cs, a, b)]
+    for i in range(6):
+        for j in range(6):
+            v = np.trapezoid(rho * r * phis[i] * phis[j], r)
+            assert abs(v - (1.0 if i == j else 0.0)) < 1e-5
+    # value and slope continuous at R0, zero at the wall
+    h = 1e-6
+    for c, an, bn in zip(cs, a, b):
+        f = lambda x: float(A.radial_phi(x, c, an, bn, R0, R, rho1, rho2, eta))
+        assert abs(f(R0 - h) - f(R0 + h)) < 1e-5 * abs(an)
+        s_in = (f(R0 - h) - f(R0 - 2 * h)) / h
+        s_out = (f(R0 + 2 * h) - f(R0 + h)) / h
+        assert abs(s_in - s_out) < 1e-3 * max(abs(s_in), 1e-12)
+        assert abs(f(R)) < 1e-12
+
+
+@pytest.mark.parametrize("rho2", [1.0, 0.2])
+def test_radial_transient_matches_finite_differences(rho2):
+    R0, R, eta, omega, T = 12.0, 36.0, 0.333, 1e-3, 60.0
+    r, ufd = fd_radial(R0, R, 1.0, rho2, eta, omega, T)
+    ua = A.radial_transient(r, T, R0, R, 1.0, rho2, eta, omega, n_modes=150)
+    assert np.max(np.abs(ua - ufd)) < 2e-5 * omega * R0   # measured 2.4e-6
