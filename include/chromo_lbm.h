@@ -13,7 +13,8 @@
  *   - modal relaxation with density-difference sources and explicit
  *     reconstruction f+ = M^{-1} m+ (Sec. III, App. A);
  *   - d'Ortona recolour (Sec. II) and streaming with periodic x, and either
- *     periodic y or half-way bounce-back walls at rows 0 and ny-1.
+ *     periodic y or half-way bounce-back walls at rows 0 and ny-1, or solid
+ *     sites anywhere given by a mask (lbm_set_solid).
  *
  * Memory: every device buffer belongs to the caller.  The library keeps only a
  * small host-side handle (pointers, parameters, step counter, which of the two
@@ -251,6 +252,38 @@ int64_t lbm_batch_step_count(const lbm_batch* b);
 
 /* Free the host object (device buffers stay with the caller). */
 void lbm_batch_destroy(lbm_batch* b);
+
+/* ---- solid sites anywhere (a mask) -----------------------------------------
+ * For obstacles that are not whole rows, such as the staircase circular
+ * no-slip wall of the curved-interface transient (Sec. IV, dynamics of curved
+ * interfaces; App. D).  Provided for LBM_STORAGE_F64 and LBM_STORAGE_F32 on a
+ * handle with walls_y = 0 (put wall rows in the mask instead); both x and y
+ * are periodic around the mask.  A link whose target is solid is bounced back
+ * half-way (as at the walls); an App. B stencil tap that falls on a solid site
+ * reads the field's value at the stencil's centre (a zero-gradient
+ * continuation of every field into the solid; the paper gives no rule for
+ * stencils at a curved wall).  Solid sites hold zero in the population buffers,
+ * carry no mass, and read as NaN from lbm_fields.  The step runs as four
+ * launches over per-site field planes (the fused step kernel is not used). */
+
+/* Bytes of device workspace lbm_set_solid needs: 14 planes of nx*ny values of
+ * the arithmetic type (256-byte multiple); 0 where masks are not provided. */
+size_t lbm_solid_workspace_bytes(const lbm_params* p);
+
+/* Give the handle a mask of solid sites.  solid_dev: device [ny][nx] bytes,
+ * nonzero = solid; workspace: device, 256-byte aligned, at least
+ * lbm_solid_workspace_bytes() bytes.  Both stay owned by the caller and must
+ * stay valid and unchanged for as long as the handle steps.  Re-encodes the
+ * live population buffer in place so that every fluid site keeps the
+ * pre-collision populations it had (the words its links now bounce into take
+ * the values those links pulled before), and zeroes the words of solid sites;
+ * call it on the state to start from (usually right after lbm_init).  From
+ * then on lbm_step and lbm_fields use the mask.  A handle takes one mask:
+ * LBM_EINVAL if it has one already, for NULL pointers, a small workspace,
+ * walls_y = 1 or nx, ny < 4; LBM_ENOTIMPL for the 16-bit formats and the
+ * streaming-only mode.  The adjoint entry points return LBM_ENOTIMPL on such
+ * a handle. */
+int lbm_set_solid(lbm_handle* h, const uint8_t* solid_dev, void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* 0 if pops_a holds the live state, 1 if pops_b does. */
 int lbm_current_pops(const lbm_handle* h);

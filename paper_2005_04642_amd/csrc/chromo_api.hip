@@ -15,6 +15,7 @@
 #include "chromo_lbm.h"
 #include "chromo_adjoint.hpp"
 #include "chromo_host.hpp"
+#include "chromo_solid.hpp"
 
 namespace {
 
@@ -133,6 +134,8 @@ struct lbm_handle {
   chromo::Geom g;      // forward step kernel
   chromo::Geom g_adj;  // adjoint pass 1 (workgroup shape ntx_for(storage, true))
   const chromo::Ops* ops;
+  const unsigned char* solid = nullptr;  // device mask of solid sites (lbm_set_solid), or null
+  void* solid_ws = nullptr;              // its field planes
 };
 
 namespace {
@@ -146,8 +149,9 @@ int step_impl(lbm_handle* h, int nsteps, hipStream_t s) {
   for (int k = 0; k < nsteps; ++k) {
     const void* src = h->pops[h->live];
     void* dst = h->pops[1 - h->live];
-    hipError_t e = (h->p.flags & LBM_FLAG_STREAM_ONLY) ? h->ops->stream_only(h->g, src, dst, s)
-                                                       : h->ops->step(h->p, h->g, src, dst, h->force, s);
+    hipError_t e = h->solid ? h->ops->solid_step(h->p, h->g, src, dst, h->force, h->solid, h->solid_ws, s)
+                   : (h->p.flags & LBM_FLAG_STREAM_ONLY) ? h->ops->stream_only(h->g, src, dst, s)
+                                                         : h->ops->step(h->p, h->g, src, dst, h->force, s);
     if (e != hipSuccess) return fail(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
     h->live = 1 - h->live;
     h->steps += 1;
@@ -239,7 +243,9 @@ int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN, double*
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   int st = LBM_OK;
   if (rho || ux || uy || rhoN) {
-    hipError_t e = h->ops->fields(h->p, h->g, h->pops[h->live], h->force, rho, ux, uy, rhoN, stream);
+    hipError_t e = h->solid ? h->ops->solid_fields(h->p, h->g, h->pops[h->live], h->force, h->solid, h->solid_ws,
+                                                   rho, ux, uy, rhoN, stream)
+                            : h->ops->fields(h->p, h->g, h->pops[h->live], h->force, rho, ux, uy, rhoN, stream);
     if (e != hipSuccess) st = fail(LBM_EHIP, "fields launch: %s", hipGetErrorString(e));
   }
   if (st != LBM_OK || !mass_RB_dev) return st;
@@ -271,6 +277,7 @@ size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
 static int adjoint_supported(const lbm_handle* h) {
   if (!h->ops->adjoint) return fail(LBM_ENOTIMPL, "the adjoint is provided for F64 and F32 storage only");
   if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no adjoint of the streaming-only test mode");
+  if (h->solid) return fail(LBM_ENOTIMPL, "no adjoint on a lattice with a solid-site mask");
   return LBM_OK;
 }
 
@@ -311,6 +318,32 @@ int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, vo
   if (!rhoN0 || !adj_pops0 || !dL_drhoN0) return fail(LBM_EINVAL, "rhoN0, adj_pops0 and dL_drhoN0 must be non-NULL");
   hipError_t e = h->ops->init_adjoint(h->p, h->g, rhoN0, adj_pops0, dL_drhoN0, stream);
   if (e != hipSuccess) return fail(LBM_EHIP, "init adjoint launch: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+size_t lbm_solid_workspace_bytes(const lbm_params* p) {
+  if (validate(p) != LBM_OK) return 0;
+  if (!ops_of(p->storage)->solid_step || p->walls_y || (p->flags & LBM_FLAG_STREAM_ONLY)) return 0;
+  const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
+  return ((size_t)chromo::solid::P_N * (size_t)p->nx * (size_t)p->ny * elem + 255) / 256 * 256;
+}
+
+int lbm_set_solid(lbm_handle* h, const uint8_t* solid_dev, void* workspace, size_t ws_bytes, hipStream_t stream) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!solid_dev || !workspace) return fail(LBM_EINVAL, "solid mask and workspace must be non-NULL");
+  if (h->solid) return fail(LBM_EINVAL, "the handle already has a solid-site mask");
+  if (!h->ops->solid_step) return fail(LBM_ENOTIMPL, "solid-site masks are provided for F64 and F32 storage only");
+  if (h->p.walls_y) return fail(LBM_EINVAL, "with a solid-site mask walls_y must be 0 (put the wall rows in the mask)");
+  if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no solid-site mask in the streaming-only test mode");
+  if (h->p.nx < 4 || h->p.ny < 4) return fail(LBM_EINVAL, "a solid-site mask needs nx, ny >= 4");
+  const size_t need = lbm_solid_workspace_bytes(&h->p);
+  if (ws_bytes < need) return fail(LBM_EINVAL, "solid workspace too small: %zu < %zu", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
+  hipError_t e = h->ops->solid_prepare(h->g, h->pops[h->live], solid_dev, stream);
+  if (e != hipSuccess) return fail(LBM_EHIP, "solid mask launch: %s", hipGetErrorString(e));
+  h->solid = solid_dev;
+  h->solid_ws = workspace;
   return LBM_OK;
 }
 

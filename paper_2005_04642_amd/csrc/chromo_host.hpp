@@ -39,13 +39,21 @@ struct Ops {
   hipError_t (*init)(const lbm_params& p, const Geom& g, const void* rhoN0, void* dst, hipStream_t s);
   hipError_t (*mass)(const lbm_params& p, const Geom& g, const void* pops, double* partial, double* out,
                      hipStream_t s);
-  // adjoint (periodic lattices; null for formats without it)
+  // adjoint (F64/F32, periodic or walled; null for formats without it)
   // g: geometry planned for the adjoint workgroup shape (ntx_for(storage, true))
   hipError_t (*adjoint)(const lbm_params& p, const Geom& g, const void* pops, const void* force,
                         const void* lam_next, void* lam_out, void* ws, double* dsigma, void* dforce, hipStream_t s);
   hipError_t (*rhoN_adjoint)(const lbm_params& p, const Geom& g, const void* pops, const void* lrN, void* out,
                              hipStream_t s);
   hipError_t (*init_adjoint)(const lbm_params& p, const Geom& g, const void* rhoN0, const void* lam0, void* out,
+                             hipStream_t s);
+  // solid sites anywhere (F64/F32; null for the others).  mask: device
+  // [ny][nx] bytes, nonzero = solid; ws: solid::P_N planes of the arithmetic type
+  hipError_t (*solid_prepare)(const Geom& g, void* pops, const unsigned char* mask, hipStream_t s);
+  hipError_t (*solid_step)(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force,
+                           const unsigned char* mask, void* ws, hipStream_t s);
+  hipError_t (*solid_fields)(const lbm_params& p, const Geom& g, const void* src, const void* force,
+                             const unsigned char* mask, void* ws, void* rho, void* ux, void* uy, void* rhoN,
                              hipStream_t s);
   // batched periodic step: ntx in batch_ntx (0-terminated); tables in device memory
   hipError_t (*batch)(int ntx, const int* radii, const void* src, void* dst, const void* sims, const int* bin_start,

@@ -7,6 +7,7 @@
 
 #include "chromo_adjoint.hpp"
 #include "chromo_host.hpp"
+#include "chromo_solid.hpp"
 
 namespace chromo {
 namespace launch {
@@ -316,6 +317,80 @@ void sim_desc(const lbm_params& p, const Geom& g, unsigned long long off, void* 
   memcpy(out, &d, sizeof(d));
 }
 
+// ---------------------------------------------------------------------------
+// solid sites anywhere (chromo_solid.hpp): four passes per step over the
+// field planes of ws
+// ---------------------------------------------------------------------------
+template <typename S>
+hipError_t solid_prepare(const Geom& g0, void* pops, const unsigned char* mask, hipStream_t s) {
+  const Geom g = geom_for<S>(g0);
+  const dim3 grid((g.nx + 255) / 256, g.ny);
+  hipLaunchKernelGGL(solid::rebounce_kernel<S>, grid, dim3(256), 0, s, pops, mask, g);
+  hipLaunchKernelGGL(solid::clear_solid_kernel<S>, grid, dim3(256), 0, s, pops, mask, g);
+  return hipGetLastError();
+}
+
+// passes 1-3; FIELDS: pass 3 writes the caller's field arrays
+template <typename S, bool FIELDS>
+void solid_front(const StepArgs<typename S::math>& a, const int* r, const unsigned char* mask,
+                 typename S::math* ws, hipStream_t s) {
+  using T = typename S::math;
+  const Geom& g = a.g;
+  const dim3 grid((g.nx + 255) / 256, g.ny);
+  hipLaunchKernelGGL(solid::sites_kernel<S>, grid, dim3(256), 0, s, a.src, mask, g, a.c, ws);
+  if (r[0] == 3) {
+    hipLaunchKernelGGL((solid::director_kernel<T, 3>), grid, dim3(256), 0, s, mask, g, a.c, ws);
+  } else {
+    hipLaunchKernelGGL((solid::director_kernel<T, 1>), grid, dim3(256), 0, s, mask, g, a.c, ws);
+  }
+  if (r[1] == 3) {
+    hipLaunchKernelGGL((solid::force_kernel<T, 3, FIELDS>), grid, dim3(256), 0, s, mask, g, a.c, a.force, ws,
+                       a.out_rho, a.out_ux, a.out_uy, a.out_rhoN);
+  } else {
+    hipLaunchKernelGGL((solid::force_kernel<T, 1, FIELDS>), grid, dim3(256), 0, s, mask, g, a.c, a.force, ws,
+                       a.out_rho, a.out_ux, a.out_uy, a.out_rhoN);
+  }
+}
+
+template <typename S>
+hipError_t solid_step(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force,
+                      const unsigned char* mask, void* wsv, hipStream_t s) {
+  using T = typename S::math;
+  const StepArgs<T> a = args<S>(p, g, src, dst, force);
+  T* ws = static_cast<T*>(wsv);
+  solid_front<S, false>(a, p.stencil, mask, ws, s);
+  const dim3 grid((g.nx + 255) / 256, g.ny);
+  const int code = (p.stencil[2] == 3) * 2 + (p.stencil[3] == 3);
+  switch (code) {
+    case 0:
+      hipLaunchKernelGGL((solid::collide_kernel<S, 1, 1>), grid, dim3(256), 0, s, a, mask, (const T*)ws);
+      break;
+    case 1:
+      hipLaunchKernelGGL((solid::collide_kernel<S, 1, 3>), grid, dim3(256), 0, s, a, mask, (const T*)ws);
+      break;
+    case 2:
+      hipLaunchKernelGGL((solid::collide_kernel<S, 3, 1>), grid, dim3(256), 0, s, a, mask, (const T*)ws);
+      break;
+    default:
+      hipLaunchKernelGGL((solid::collide_kernel<S, 3, 3>), grid, dim3(256), 0, s, a, mask, (const T*)ws);
+  }
+  return hipGetLastError();
+}
+
+template <typename S>
+hipError_t solid_fields(const lbm_params& p, const Geom& g, const void* src, const void* force,
+                        const unsigned char* mask, void* wsv, void* rho, void* ux, void* uy, void* rhoN,
+                        hipStream_t s) {
+  using T = typename S::math;
+  StepArgs<T> a = args<S>(p, g, src, nullptr, force);
+  a.out_rho = static_cast<T*>(rho);
+  a.out_ux = static_cast<T*>(ux);
+  a.out_uy = static_cast<T*>(uy);
+  a.out_rhoN = static_cast<T*>(rhoN);
+  solid_front<S, true>(a, p.stencil, mask, static_cast<T*>(wsv), s);
+  return hipGetLastError();
+}
+
 template <typename S>
 Ops make_ops() {
   Ops o;
@@ -328,10 +403,16 @@ Ops make_ops() {
     o.adjoint = nullptr;
     o.rhoN_adjoint = nullptr;
     o.init_adjoint = nullptr;
+    o.solid_prepare = nullptr;
+    o.solid_step = nullptr;
+    o.solid_fields = nullptr;
   } else {
     o.adjoint = adjoint<S>;
     o.rhoN_adjoint = rhoN_adjoint<S>;
     o.init_adjoint = init_adjoint<S>;
+    o.solid_prepare = solid_prepare<S>;
+    o.solid_step = solid_step<S>;
+    o.solid_fields = solid_fields<S>;
   }
   o.batch_ntx[0] = o.batch_ntx[1] = o.batch_ntx[2] = 0;
   o.batch = batch<S>;

@@ -25,7 +25,8 @@ LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR = 1, 2, 4
 # every symbol the header declares
 EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_workspace_bytes", "lbm_init",
             "lbm_step", "lbm_fields", "lbm_masses_host", "lbm_adjoint_workspace_bytes", "lbm_adjoint_step",
-            "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_current_pops", "lbm_set_pops", "lbm_step_count",
+            "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_solid_workspace_bytes", "lbm_set_solid",
+            "lbm_current_pops", "lbm_set_pops", "lbm_step_count",
             "lbm_destroy", "lbm_last_error", "lbm_batch_pops_bytes", "lbm_batch_offsets", "lbm_batch_workspace_bytes",
             "lbm_batch_init", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_plan_info", "lbm_batch_fields",
             "lbm_batch_masses_host", "lbm_batch_current_pops", "lbm_batch_step_count", "lbm_batch_destroy")
@@ -88,6 +89,10 @@ def load_library(path=None):
     lib.lbm_rhoN_adjoint.restype = ctypes.c_int
     lib.lbm_init_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.lbm_init_adjoint.restype = ctypes.c_int
+    lib.lbm_solid_workspace_bytes.argtypes = [P]
+    lib.lbm_solid_workspace_bytes.restype = sz
+    lib.lbm_set_solid.argtypes = [vp, vp, vp, sz, vp]
+    lib.lbm_set_solid.restype = ctypes.c_int
     lib.lbm_current_pops.argtypes = [vp]
     lib.lbm_current_pops.restype = ctypes.c_int
     lib.lbm_set_pops.argtypes = [vp, vp, vp]
@@ -224,6 +229,15 @@ def lbm_init_adjoint(h, rhoN0_ptr, adj0_ptr, dL_drhoN0_ptr, stream):
     return _check(lib, lib.lbm_init_adjoint(h, rhoN0_ptr, adj0_ptr, dL_drhoN0_ptr, stream))
 
 
+def lbm_solid_workspace_bytes(p):
+    return load_library().lbm_solid_workspace_bytes(ctypes.byref(p))
+
+
+def lbm_set_solid(h, solid_ptr, ws_ptr, ws_bytes, stream):
+    lib = load_library()
+    return _check(lib, lib.lbm_set_solid(h, solid_ptr, ws_ptr, ws_bytes, stream))
+
+
 def lbm_current_pops(h):
     return load_library().lbm_current_pops(h)
 
@@ -255,11 +269,13 @@ class Simulation:
     params: dict of physical parameters (see ``workloads.base_params``);
     rhoN0: [ny, nx] initial colour index (numpy or torch); storage 'f64',
     'f32', or the 16-bit offset formats 'f16' / 'bf16' (FP32 arithmetic);
-    force: optional [2, ny, nx] per-site body force density.  Fields, rhoN0
-    and force use the arithmetic type (float64 for 'f64', else float32).
+    force: optional [2, ny, nx] per-site body force density; solid: optional
+    [ny, nx] mask of solid sites (lbm_set_solid; F64/F32 storage, no walls).
+    Fields, rhoN0 and force use the arithmetic type (float64 for 'f64', else
+    float32).
     """
 
-    def __init__(self, nx, ny, params, rhoN0, storage="f32", force=None, device="cuda:0", flags=0):
+    def __init__(self, nx, ny, params, rhoN0, storage="f32", force=None, device="cuda:0", flags=0, solid=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the chromodynamic LBM step runs only on the HIP device")
@@ -290,6 +306,24 @@ class Simulation:
                           None if self.force is None else self.force.data_ptr(),
                           self.pops[0].data_ptr(), self.pops[1].data_ptr(), self.ws.data_ptr(), wsb,
                           self.stream())
+        self.solid = None
+        if solid is not None:
+            self.set_solid(solid)
+
+    def set_solid(self, solid):
+        """Give the lattice a mask of solid sites ([ny, nx], nonzero = solid),
+        keeping the pre-collision populations of the fluid sites."""
+        t = self.torch
+        m = solid if t.is_tensor(solid) else t.as_tensor(np.asarray(solid))
+        m = (m != 0).to(device=self.device, dtype=t.uint8).contiguous()
+        if tuple(m.shape) != (self.ny, self.nx):
+            raise ValueError("solid mask must have shape (ny, nx)")
+        n = lbm_solid_workspace_bytes(self.params)
+        if n == 0:
+            raise LbmError(LBM_ENOTIMPL, "no solid-site mask for these parameters (needs F64/F32 storage, no walls)")
+        ws = t.empty(n, dtype=t.uint8, device=self.device)
+        lbm_set_solid(self.h, m.data_ptr(), ws.data_ptr(), n, self.stream())
+        self.solid, self._solid_ws = m, ws   # both must outlive the handle's use of them
 
     def stream(self):
         return self.torch.cuda.current_stream(self.device).cuda_stream

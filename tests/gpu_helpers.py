@@ -78,3 +78,35 @@ def perturbed_buffer(sim, scale, seed):
 
 def rel_err(a, b):
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def pull_gather_masked(S, solid):
+    """Pre-collision populations from a pull-layout buffer S [2, 9, ny, nx] on a
+    lattice with a solid-site mask: f_i(r) = S_i(r - c_i), or S_opp(i)(r) when
+    r - c_i is solid; zero at solid sites."""
+    S = np.asarray(S)
+    solid = np.asarray(solid, dtype=bool)
+    out = np.empty_like(S)
+    for i in range(Q):
+        cx, cy = C[i]
+        moved = np.roll(S[:, i], (cy, cx), axis=(-2, -1))
+        src_solid = np.roll(solid, (cy, cx), axis=(-2, -1))
+        out[:, i] = np.where(src_solid, S[:, OPP[i]], moved)
+    out[:, :, solid] = 0.0
+    return out
+
+
+def push_scatter_masked(P, solid):
+    """Inverse of pull_gather_masked: the buffer whose gather gives the
+    populations P [2, 9, ny, nx] (S_i(s) = P_i(s + c_i), or P_opp(i)(s) when
+    s + c_i is solid; zero at solid sites)."""
+    P = np.asarray(P)
+    solid = np.asarray(solid, dtype=bool)
+    S = np.empty_like(P)
+    for i in range(Q):
+        cx, cy = C[i]
+        moved = np.roll(P[:, i], (-cy, -cx), axis=(-2, -1))
+        dst_solid = np.roll(solid, (-cy, -cx), axis=(-2, -1))
+        S[:, i] = np.where(dst_solid, P[:, OPP[i]], moved)
+    S[:, :, solid] = 0.0
+    return S

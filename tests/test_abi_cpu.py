@@ -130,3 +130,18 @@ def test_batch_validation_and_layout():
     assert lbm.lbm_batch_pops_bytes(mixed) == 0
     radii = [ps[0], lbm.make_params(64, 64, "f32", **dict(prm, stencil=(1, 1, 1, 1)))]
     assert lbm.lbm_batch_pops_bytes(radii) == 0
+
+
+def test_solid_mask_availability_and_argument_errors():
+    """Masks of solid sites exist for F64/F32 storage without walls (14 field
+    planes of workspace); NULL arguments fail before any GPU call."""
+    lib = lbm.load_library()
+    prm = Wk.base_params(Lambda=10.0)
+    for storage, walls, ok in (("f32", False, True), ("f64", False, True), ("f16", False, False),
+                               ("bf16", False, False), ("f32", True, False)):
+        p = lbm.make_params(64, 48, storage, **dict(prm, walls=walls))
+        n = lbm.lbm_solid_workspace_bytes(p)
+        assert (n > 0) == ok, (storage, walls)
+        if ok:
+            assert n >= 14 * 64 * 48 * (8 if storage == "f64" else 4) and n % 256 == 0
+    assert lib.lbm_set_solid(None, None, None, 0, None) == lbm.LBM_EINVAL
