@@ -173,6 +173,44 @@ def storage16_measure(n, params, rn, torch, steps=200, warmup=20):
     return out
 
 
+def solid_measure(n, params, rn, torch, ms_fused, steps=100, warmup=10):
+    """Step with a solid-site mask (four launches per step): the benchmark
+    lattice inside a circular container wall of radius n/2 - 2 (FP32), and the
+    curved-interface transient's 724^2 container at Lambda = 5 (FP64)."""
+    import numpy as np
+    from paper_2005_04642_amd import lbm, workloads as Wk
+
+    def timed(sim, k):
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(k)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / k
+
+    solid = Wk.circular_wall(n, n, n / 2.0 - 2.0)
+    sim = lbm.Simulation(n, n, params, rn, storage="f32", device="cuda:0", solid=solid)
+    ms = timed(sim, steps)
+    sim.close()
+    fluid = int((~solid).sum())
+    out = {"workload": "%dx%d emulsion inside a circular wall of radius %g (%.1f %% of sites solid), FP32, "
+                       "%d steps" % (n, n, n / 2.0 - 2.0, 100.0 * (1 - fluid / (n * n)), steps),
+           "ms_per_step": round(ms, 5), "MLUPS_all_sites": round(n * n / ms / 1e3, 1),
+           "MLUPS_fluid_sites": round(fluid / ms / 1e3, 1),
+           "vs_fused_step_without_mask": round(ms_fused / ms, 4)}
+    nx, ny, p, rn2, _, _, solid2, _ = Wk.config_curved_transient(5.0)
+    sim = lbm.Simulation(nx, ny, p, rn2, storage="f64", device="cuda:0", solid=solid2)
+    ms2 = timed(sim, 200)
+    sim.close()
+    out["curved_transient"] = {"workload": "%dx%d container of the curved-interface transient, Lambda 5, FP64, "
+                                           "200 steps" % (nx, ny),
+                               "ms_per_step": round(ms2, 5), "MLUPS_all_sites": round(nx * ny / ms2 / 1e3, 1)}
+    return out
+
+
 def drop_to_ellipse(n=512):
     """The adjoint workload: n^2 periodic, circle of radius n/4 to a seeded
     ellipse target of equal area, 8 Gaussian force bumps (amplitude 1e-6).
@@ -286,6 +324,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-storage16", action="store_true")
+    ap.add_argument("--no-solid", action="store_true")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one plain 1 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -362,6 +401,8 @@ def main():
         out["roofline"]["frac_of_copy"] = round(achieved / out["copy_roof"]["GB_s"], 4)
     if not args.no_storage16 and args.storage == "f32":
         out["storage16"] = storage16_measure(n, params, rn, torch)
+    if not args.no_solid and args.storage == "f32":
+        out["solid_mask"] = solid_measure(n, params, rn, torch, ms_per_step)
     if not args.no_adjoint:
         out["adjoint"] = dict({"workload": "same lattice and state, one adjoint step vs one forward step, FP32"},
                               **adjoint_measure(n, params, rn, torch))

@@ -11,6 +11,7 @@
                          (Sec. IV, curved interfaces).
 * ``transient_error``   the error measure epsilon(t) of Sec. IV.
 """
+import functools
 import math
 import numpy as np
 
@@ -231,6 +232,7 @@ def _lommel(C, dC, k, r):
     return 0.5 * r * r * (dC(x) ** 2 + (1.0 - 1.0 / (x * x)) * C(x) ** 2)
 
 
+@functools.lru_cache(maxsize=32)
 def radial_modes(R0, R, rho1, rho2, eta, n_modes):
     """Eigen-pairs: c_n and the coefficients (a_n, b_n) of phi_n = a_n J1(k1 r)
     inside, b_n Z(r) outside, normalised so that int_0^R rho r phi_n^2 dr = 1."""
