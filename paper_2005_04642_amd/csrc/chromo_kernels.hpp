@@ -648,8 +648,13 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
     sm.at(F_RR, rm, tx) = rR;
     sm.at(F_RB, rm, tx) = rB;
     sm.at(F_RHON, rm, tx) = colour_index(rR * c.inv_rho0R, rB * c.inv_rho0B);
-    // prefetch the next band-M row (after the last iteration: a row never used)
+    // prefetch the next band-M row (after the last iteration: a row never used).
+    // The loads of the plain float formats go out at a raised wave priority, so
+    // they issue ahead of other waves' arithmetic (FP32 4096^2: 3.6 % faster);
+    // the VALU-bound 16-bit formats run slower with it and keep the default.
+    if constexpr (!is_ofs16<ST>::value) __builtin_amdgcn_s_setprio(1);
     gather_words<ST, WALLS>(src, g, tM.phys(g), t.cols, st.pw);
+    if constexpr (!is_ofs16<ST>::value) __builtin_amdgcn_s_setprio(0);
     tM.advance(g);
   }
   __syncthreads();
