@@ -418,6 +418,7 @@ def main():
                                   **adjoint_measure(512, p_d, rn_d, torch, steps=200,
                                                     force=torch.tensor(f_d, dtype=torch.float32, device="cuda:0")))
         out["adjoint_rollout"] = adjoint_rollout(torch)
+        out["adjoint_rollout_every_state"] = adjoint_rollout(torch, checkpoint=1)
     if not args.no_batch:
         out["batch"] = batch_measure(torch)
     if not args.no_cpu:
