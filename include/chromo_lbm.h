@@ -81,7 +81,8 @@ enum {
 enum {
   LBM_FLAG_STREAM_ONLY = 1, /* lbm_step only streams: buf'_i(r) = f_i(r) (no collision) */
   LBM_FLAG_FIXED_K = 2,     /* curvature K := K_fixed instead of div n (Sec. IV, fixed K) */
-  LBM_FLAG_NO_RECOLOR = 4   /* skip the segregation term of the recolour (proportional split) */
+  LBM_FLAG_NO_RECOLOR = 4,  /* skip the segregation term of the recolour (proportional split) */
+  LBM_FLAG_MASK_PASSES = 8  /* with a solid-site mask: always step with the four-pass kernels */
 };
 
 /* Parameters of one lattice (Sec. II, App. A).  Units are lattice units
@@ -263,11 +264,15 @@ void lbm_batch_destroy(lbm_batch* b);
  * reads the field's value at the stencil's centre (a zero-gradient
  * continuation of every field into the solid; the paper gives no rule for
  * stencils at a curved wall).  Solid sites hold zero in the population buffers,
- * carry no mass, and read as NaN from lbm_fields.  The step runs as four
- * launches over per-site field planes (the fused step kernel is not used). */
+ * carry no mass, and read as NaN from lbm_fields.  For the stencil profiles
+ * (3,3,3,3) and (1,1,1,1) the step is one launch of the fused step kernel in
+ * its mask variant (per-site bounce bits, NaN markers for stencil taps); for
+ * the other profiles, or with LBM_FLAG_MASK_PASSES, four launches over
+ * per-site field planes.  Both give the same results bit for bit. */
 
 /* Bytes of device workspace lbm_set_solid needs: 14 planes of nx*ny values of
- * the arithmetic type (256-byte multiple); 0 where masks are not provided. */
+ * the arithmetic type and nx*ny bytes of bounce bits (256-byte multiple); 0
+ * where masks are not provided. */
 size_t lbm_solid_workspace_bytes(const lbm_params* p);
 
 /* Give the handle a mask of solid sites.  solid_dev: device [ny][nx] bytes,

@@ -88,7 +88,7 @@ int validate(const lbm_params* p) {
       !std::isfinite(p->K_fixed))
     return fail(LBM_EINVAL, "non-finite parameter");
   if (p->ghost_eq != 0 && p->ghost_eq != 1) return fail(LBM_EINVAL, "ghost_eq must be 0 or 1");
-  if (p->flags & ~(LBM_FLAG_STREAM_ONLY | LBM_FLAG_FIXED_K | LBM_FLAG_NO_RECOLOR))
+  if (p->flags & ~(LBM_FLAG_STREAM_ONLY | LBM_FLAG_FIXED_K | LBM_FLAG_NO_RECOLOR | LBM_FLAG_MASK_PASSES))
     return fail(LBM_EINVAL, "unknown flag bits 0x%x", p->flags);
   return LBM_OK;
 }
@@ -149,9 +149,17 @@ int step_impl(lbm_handle* h, int nsteps, hipStream_t s) {
   for (int k = 0; k < nsteps; ++k) {
     const void* src = h->pops[h->live];
     void* dst = h->pops[1 - h->live];
-    hipError_t e = h->solid ? h->ops->solid_step(h->p, h->g, src, dst, h->force, h->solid, h->solid_ws, s)
-                   : (h->p.flags & LBM_FLAG_STREAM_ONLY) ? h->ops->stream_only(h->g, src, dst, s)
-                                                         : h->ops->step(h->p, h->g, src, dst, h->force, s);
+    hipError_t e;
+    if (h->solid) {
+      e = hipErrorNotSupported;
+      if (!(h->p.flags & LBM_FLAG_MASK_PASSES))
+        e = h->ops->solid_fused(h->p, h->g, src, dst, h->force, h->solid_ws, s);
+      if (e == hipErrorNotSupported)
+        e = h->ops->solid_step(h->p, h->g, src, dst, h->force, h->solid, h->solid_ws, s);
+    } else {
+      e = (h->p.flags & LBM_FLAG_STREAM_ONLY) ? h->ops->stream_only(h->g, src, dst, s)
+                                              : h->ops->step(h->p, h->g, src, dst, h->force, s);
+    }
     if (e != hipSuccess) return fail(LBM_EHIP, "step launch: %s", hipGetErrorString(e));
     h->live = 1 - h->live;
     h->steps += 1;
@@ -325,7 +333,8 @@ size_t lbm_solid_workspace_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
   if (!ops_of(p->storage)->solid_step || p->walls_y || (p->flags & LBM_FLAG_STREAM_ONLY)) return 0;
   const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
-  return ((size_t)chromo::solid::P_N * (size_t)p->nx * (size_t)p->ny * elem + 255) / 256 * 256;
+  const size_t plane = (size_t)p->nx * (size_t)p->ny;
+  return (chromo::solid::bits_offset(plane, elem) + plane + 255) / 256 * 256;
 }
 
 int lbm_set_solid(lbm_handle* h, const uint8_t* solid_dev, void* workspace, size_t ws_bytes, hipStream_t stream) {
@@ -340,7 +349,7 @@ int lbm_set_solid(lbm_handle* h, const uint8_t* solid_dev, void* workspace, size
   const size_t need = lbm_solid_workspace_bytes(&h->p);
   if (ws_bytes < need) return fail(LBM_EINVAL, "solid workspace too small: %zu < %zu", ws_bytes, need);
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
-  hipError_t e = h->ops->solid_prepare(h->g, h->pops[h->live], solid_dev, stream);
+  hipError_t e = h->ops->solid_prepare(h->g, h->pops[h->live], solid_dev, workspace, stream);
   if (e != hipSuccess) return fail(LBM_EHIP, "solid mask launch: %s", hipGetErrorString(e));
   h->solid = solid_dev;
   h->solid_ws = workspace;

@@ -49,7 +49,11 @@ struct Ops {
                              hipStream_t s);
   // solid sites anywhere (F64/F32; null for the others).  mask: device
   // [ny][nx] bytes, nonzero = solid; ws: solid::P_N planes of the arithmetic type
-  hipError_t (*solid_prepare)(const Geom& g, void* pops, const unsigned char* mask, hipStream_t s);
+  hipError_t (*solid_prepare)(const Geom& g, void* pops, const unsigned char* mask, void* ws, hipStream_t s);
+  // the fused step kernel with the mask (hipErrorNotSupported for stencil
+  // profiles it is not built for)
+  hipError_t (*solid_fused)(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force,
+                            void* ws, hipStream_t s);
   hipError_t (*solid_step)(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force,
                            const unsigned char* mask, void* ws, hipStream_t s);
   hipError_t (*solid_fields)(const lbm_params& p, const Geom& g, const void* src, const void* force,

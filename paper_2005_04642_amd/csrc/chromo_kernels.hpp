@@ -92,6 +92,9 @@ struct StepArgs {
   const T* lam_next;
   T* out_save;
   T* out_adj;
+  // solid sites anywhere: per site, bit i - 1 set when the source r - c_i of
+  // link i is solid (all set at a solid site); [ny][nx] bytes, or null
+  const unsigned char* bnc;
   Geom g;
   Coef<T> c;
 };
@@ -293,9 +296,14 @@ struct Cols {
 // reversed link's word at r itself (half-way bounce-back).  p is wave-uniform,
 // so every word / row offset is scalar.  WALLS: rows 0 and ny - 1 are solid
 // (else y is periodic).
-template <typename S, bool WALLS>
+//
+// MASK (solid sites anywhere, y periodic): the link's bounce bit of the site
+// chooses, per lane, between the source word and the reversed link's word at
+// the site itself; the whole byte offset then goes in the per-lane offset.
+template <typename S, bool WALLS, bool MASK = false>
 __device__ __forceinline__ void gather_words(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
-                                             typename S::W out[S::NW]) {
+                                             typename S::W out[S::NW], const unsigned char* bnc = nullptr,
+                                             int xg = 0) {
   int rm = p - 1, rp = p + 1;
   bool bm = false, bp = false;
   if (WALLS) {
@@ -314,6 +322,15 @@ __device__ __forceinline__ void gather_words(__amdgpu_buffer_rsrc_t src, const G
     const unsigned soff = bounce ? (unsigned)word_bounce<S>(q) * g.pb + ro
                                  : (unsigned)q * g.pb + (dy == 1 ? rom : (dy == -1 ? rop : ro));
     const int voff = bounce ? x.o : (dx == 1 ? x.m : (dx == -1 ? x.p : x.o));
+    if constexpr (MASK) {
+      if (i != 0) {
+        const unsigned b = bnc[(size_t)p * g.nx + xg];
+        const unsigned own = (unsigned)x.o + (unsigned)word_bounce<S>(q) * g.pb + ro;
+        const unsigned off = ((b >> (i - 1)) & 1u) ? own : (unsigned)voff + soff;
+        out[q] = load_word<typename S::W>(src, (int)off, 0);
+        continue;
+      }
+    }
     out[q] = load_word<typename S::W>(src, voff, (int)soff);
   }
 }
@@ -375,20 +392,32 @@ __device__ __forceinline__ T stencil_ba(int n) {
 // field's first element, successive ring rows are STRIDE elements apart and
 // successive columns CS.  Row pointers start R columns left of tx so that
 // every column offset is non-negative (LDS instruction offsets are unsigned).
-template <int R, int RING, int STRIDE, int CS, typename T>
+//
+// MASK: solid sites hold NaN in every stencil operand, and a NaN tap reads the
+// value at the stencil's centre instead (the zero-gradient continuation into
+// the solid).  A fluid site's own value is never NaN unless the run has
+// already failed, which the masses then report.
+template <typename T>
+__device__ __forceinline__ T tap_or(T v, T c0) {
+  return v == v ? v : c0;
+}
+
+template <int R, int RING, int STRIDE, int CS, typename T, bool MASK = false>
 __device__ __forceinline__ void ring_grad(const T* s, int row, int tx, T& gx, T& gy) {
   gx = T(0);
   gy = T(0);
   const T* md = s + ring_row<RING>(row) * STRIDE + (tx - R) * CS;
+  const T c0 = MASK ? md[R * CS] : T(0);
+  auto v = [&](T x) { return MASK ? tap_or(x, c0) : x; };
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
     const T bd = stencil_bd<R, T>(n), ba = stencil_ba<R, T>(n);
     const T* up = s + ring_row<RING>(row + n) * STRIDE + (tx - R) * CS;
     const T* dn = s + ring_row<RING>(row - n) * STRIDE + (tx - R) * CS;
-    const T d1 = up[(R + n) * CS] - dn[(R - n) * CS];
-    const T d3 = up[(R - n) * CS] - dn[(R + n) * CS];
-    const T d8 = md[(R + n) * CS] - md[(R - n) * CS];
-    const T d2 = up[R * CS] - dn[R * CS];
+    const T d1 = v(up[(R + n) * CS]) - v(dn[(R - n) * CS]);
+    const T d3 = v(up[(R - n) * CS]) - v(dn[(R + n) * CS]);
+    const T d8 = v(md[(R + n) * CS]) - v(md[(R - n) * CS]);
+    const T d2 = v(up[R * CS]) - v(dn[R * CS]);
     gx += ba * d8;
     gx += bd * (d1 - d3);
     gy += ba * d2;
@@ -397,10 +426,14 @@ __device__ __forceinline__ void ring_grad(const T* s, int row, int tx, T& gx, T&
 }
 
 // d vx/dx + d vy/dy of a ring vector field.
-template <int R, int RING, int STRIDE, int CS, typename T>
+template <int R, int RING, int STRIDE, int CS, typename T, bool MASK = false>
 __device__ __forceinline__ T ring_div(const T* sx, const T* sy, int row, int tx) {
   T acc = T(0);
   const T* mdx = sx + ring_row<RING>(row) * STRIDE + (tx - R) * CS;
+  const T cx = MASK ? mdx[R * CS] : T(0);
+  const T cy = MASK ? sy[ring_row<RING>(row) * STRIDE + tx * CS] : T(0);
+  auto vx = [&](T x) { return MASK ? tap_or(x, cx) : x; };
+  auto vy = [&](T x) { return MASK ? tap_or(x, cy) : x; };
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
     const T bd = stencil_bd<R, T>(n), ba = stencil_ba<R, T>(n);
@@ -408,12 +441,12 @@ __device__ __forceinline__ T ring_div(const T* sx, const T* sy, int row, int tx)
     const T* dnx = sx + ring_row<RING>(row - n) * STRIDE + (tx - R) * CS;
     const T* upy = sy + ring_row<RING>(row + n) * STRIDE + (tx - R) * CS;
     const T* dny = sy + ring_row<RING>(row - n) * STRIDE + (tx - R) * CS;
-    const T d1 = upx[(R + n) * CS] - dnx[(R - n) * CS];
-    const T d3 = upx[(R - n) * CS] - dnx[(R + n) * CS];
-    const T d8 = mdx[(R + n) * CS] - mdx[(R - n) * CS];
-    const T e1 = upy[(R + n) * CS] - dny[(R - n) * CS];
-    const T e3 = upy[(R - n) * CS] - dny[(R + n) * CS];
-    const T e2 = upy[R * CS] - dny[R * CS];
+    const T d1 = vx(upx[(R + n) * CS]) - vx(dnx[(R - n) * CS]);
+    const T d3 = vx(upx[(R - n) * CS]) - vx(dnx[(R + n) * CS]);
+    const T d8 = vx(mdx[(R + n) * CS]) - vx(mdx[(R - n) * CS]);
+    const T e1 = vy(upy[(R + n) * CS]) - vy(dny[(R - n) * CS]);
+    const T e3 = vy(upy[(R - n) * CS]) - vy(dny[(R + n) * CS]);
+    const T e2 = vy(upy[R * CS]) - vy(dny[R * CS]);
     acc += ba * (d8 + e2);
     acc += bd * ((d1 - d3) + (e1 + e3));
   }
@@ -492,7 +525,8 @@ __device__ __forceinline__ float rsqrt_pos(float x) {
 __device__ __forceinline__ double rsqrt_pos(double x) { return 1.0 / sqrt(x); }
 
 // Collision, recolour and store of one site (band O).
-template <typename S, typename T, int MODE>
+// MASK: a site without mass (a solid site, whose words are all zero) stores zeros.
+template <typename S, typename T, int MODE, bool MASK = false>
 __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buffer_rsrc_t dst, const T* f, T rR,
                                               T rB, T ux, T uy, T Gx, T Gy, T inv_rho, T dPx, T dPy, T theta,
                                               T rhoN, T mx, T my, int p, const Thread& t) {
@@ -607,6 +641,12 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
   R[4] = aR * fp[4] - t8; B[4] = aB * fp[4] + t8;
   typename S::W w[S::NW];
   encode<S>(R, B, c, w);
+  if constexpr (MASK) {
+    if (rho == T(0)) {
+#pragma unroll
+      for (int q = 0; q < S::NW; ++q) w[q] = typename S::W(0);
+    }
+  }
   const unsigned ro = (unsigned)p * a.g.rb;
 #pragma unroll
   for (int q = 0; q < S::NW; ++q) store_word<typename S::W>(w[q], dst, t.cols.o, (int)(q * a.g.pb + ro));
@@ -614,7 +654,8 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
 
 // One march iteration; S = it mod 4 selects the register-ring slots.  tM and
 // tU track the virtual rows of the next band-M gather and of band U.
-template <int S, typename ST, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE>
+template <int S, typename ST, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE,
+          bool MASK = false>
 __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgpu_buffer_rsrc_t src,
                                            __amdgpu_buffer_rsrc_t dst, Smem<T, NTX, Pipe<NR>::RING>& sm,
                                            March<ST>& st, const Thread& t, RowTrack<WALLS>& tM,
@@ -653,7 +694,7 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
     // they issue ahead of other waves' arithmetic (FP32 4096^2: 3.6 % faster);
     // the VALU-bound 16-bit formats run slower with it and keep the default.
     if constexpr (!is_ofs16<ST>::value) __builtin_amdgcn_s_setprio(1);
-    gather_words<ST, WALLS>(src, g, tM.phys(g), t.cols, st.pw);
+    gather_words<ST, WALLS, MASK>(src, g, tM.phys(g), t.cols, st.pw, a.bnc, t.xg);
     if constexpr (!is_ofs16<ST>::value) __builtin_amdgcn_s_setprio(0);
     tM.advance(g);
   }
@@ -671,11 +712,18 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   }
   if (it >= PP::ITN && tx >= RG && tx < NTX - RG) {
     T gx, gy;
-    ring_grad<RG, RING, SM::STRIDE, SM::CS>(sm.field(F_RHON), rowN, tx, gx, gy);
+    ring_grad<RG, RING, SM::STRIDE, SM::CS, T, MASK>(sm.field(F_RHON), rowN, tx, gx, gy);
     const T is = rsqrt_pos(gx * gx + gy * gy + c.eps2);
     const int rn = ring_row<RING>(rowN);
-    sm.at(F_MX, rn, tx) = gx * is;
-    sm.at(F_MY, rn, tx) = gy * is;
+    T mx = gx * is, my = gy * is;
+    if (MASK) {
+      // a solid site (rho^N = 0/0) marks m as well: its stencil sums mix
+      // fluid taps and are finite when the site has fluid all round
+      const T r0 = sm.at(F_RHON, rn, tx);
+      if (!(r0 == r0)) mx = my = __builtin_nan("");
+    }
+    sm.at(F_MX, rn, tx) = mx;
+    sm.at(F_MY, rn, tx) = my;
     sm.at(F_GNX, rn, tx) = gx;
     sm.at(F_GNY, rn, tx) = gy;
   }
@@ -687,7 +735,9 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
     const int ru = ring_row<RING>(rowU);
     const T rR = sm.at(F_RR, ru, tx), rB = sm.at(F_RB, ru, tx);
     const T rho = rR + rB;
-    sm.at(F_PHI, ru, tx) = c.c06R * rR + c.phiB * rB - rho * T(1.0 / 3.0);
+    T phi = c.c06R * rR + c.phiB * rB - rho * T(1.0 / 3.0);
+    if (MASK && rho == T(0)) phi = __builtin_nan("");  // solid site: the stencils' marker
+    sm.at(F_PHI, ru, tx) = phi;
     if (tx >= RG + RK && tx < NTX - RG - RK) {
       const int p = tU.phys(g);
       const bool refl = tU.refl(g);
@@ -695,7 +745,8 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
       if (c.fixed_K) {
         K = c.K_fixed;
       } else {
-        K = -ring_div<RK, RING, SM::STRIDE, SM::CS>(sm.field(F_MX), sm.field(F_MY), rowU, tx);  // K = div n, n = -m
+        K = -ring_div<RK, RING, SM::STRIDE, SM::CS, T, MASK>(sm.field(F_MX), sm.field(F_MY), rowU,
+                                                            tx);  // K = div n, n = -m
       }
       if (MODE == MODE_ADJ) {
         const int v = base + PP::LU;  // virtual row of band U
@@ -712,8 +763,10 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
       momenta(rf, jx, jy);
       if (refl) jy = -jy;   // mirror image: the y-momentum changes sign
       const T ir = recip(rho);
-      sm.at(F_UX, ru, tx) = (jx + T(0.5) * Gx) * ir;
-      sm.at(F_UY, ru, tx) = (jy + T(0.5) * Gy) * ir;
+      T ux = (jx + T(0.5) * Gx) * ir, uy = (jy + T(0.5) * Gy) * ir;
+      if (MASK && rho == T(0)) ux = uy = __builtin_nan("");  // solid site (1/0 need not give NaN)
+      sm.at(F_UX, ru, tx) = ux;
+      sm.at(F_UY, ru, tx) = uy;
       sm.at(F_GX, ru, tx) = Gx;
       sm.at(F_GY, ru, tx) = Gy;
       sm.at(F_IRHO, ru, tx) = ir;
@@ -725,9 +778,9 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
   // ---- band O: correction, collision, recolour, store ----------------------
   if (it >= PP::IT0 && t.own && base < t.yb) {
     T dPx, dPy;
-    ring_grad<RP, RING, SM::STRIDE, SM::CS>(sm.field(F_PHI), rowO, tx, dPx, dPy);
+    ring_grad<RP, RING, SM::STRIDE, SM::CS, T, MASK>(sm.field(F_PHI), rowO, tx, dPx, dPy);
     __builtin_amdgcn_sched_barrier(0);  // bound register pressure: finish one stencil before the next
-    const T theta = ring_div<RU, RING, SM::STRIDE, SM::CS>(sm.field(F_UX), sm.field(F_UY), rowO, tx);
+    const T theta = ring_div<RU, RING, SM::STRIDE, SM::CS, T, MASK>(sm.field(F_UX), sm.field(F_UY), rowO, tx);
     __builtin_amdgcn_sched_barrier(0);
     const int ro = ring_row<RING>(rowO);
     const int p = WALLS ? base + 1 : base;
@@ -736,14 +789,14 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgp
       sv[SV_GNX * g.plane] = sm.at(F_GNX, ro, tx);
       sv[SV_GNY * g.plane] = sm.at(F_GNY, ro, tx);
     }
-    collide_store<ST, T, MODE>(a, dst, st.rf[sO], sm.at(F_RR, ro, tx), sm.at(F_RB, ro, tx), sm.at(F_UX, ro, tx), sm.at(F_UY, ro, tx),
+    collide_store<ST, T, MODE, MASK>(a, dst, st.rf[sO], sm.at(F_RR, ro, tx), sm.at(F_RB, ro, tx), sm.at(F_UX, ro, tx), sm.at(F_UY, ro, tx),
                                  sm.at(F_GX, ro, tx), sm.at(F_GY, ro, tx), sm.at(F_IRHO, ro, tx), dPx, dPy, theta,
                                  sm.at(F_RHON, ro, tx), sm.at(F_MX, ro, tx), sm.at(F_MY, ro, tx), p, t);
   }
 }
 
 // One tile (strip x chunk of rows) of one lattice: the whole march.
-template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE>
+template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE, bool MASK = false>
 __device__ __forceinline__ void march_tile(const StepArgs<typename ST::math>& a, int tile,
                                            Smem<typename ST::math, NTX, Pipe<NR>::RING>& sm) {
   using T = typename ST::math;
@@ -776,7 +829,7 @@ __device__ __forceinline__ void march_tile(const StepArgs<typename ST::math>& a,
   const int v0 = t.ya - NR * PP::IT0 + t.ty;  // band-O virtual row of iteration 0
   RowTrack<WALLS> tM, tU;
   tM.init(v0 + PP::LM, g);
-  gather_words<ST, WALLS>(src, g, tM.phys(g), t.cols, st.pw);
+  gather_words<ST, WALLS, MASK>(src, g, tM.phys(g), t.cols, st.pw, a.bnc, t.xg);
   tM.advance(g);
   tU.init(v0 + PP::LU, g);
   if (a.force) {
@@ -785,17 +838,17 @@ __device__ __forceinline__ void march_tile(const StepArgs<typename ST::math>& a,
     st.fy[0] = a.force[g.plane + site];
   }
   for (int it = 0; it < t.nit; it += 4) {
-    march_iter<0, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it, a, src, dst, sm, st, t, tM, tU);
+    march_iter<0, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE, MASK>(it, a, src, dst, sm, st, t, tM, tU);
     if (it + 1 < t.nit)
-      march_iter<1, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it + 1, a, src, dst, sm, st, t, tM, tU);
+      march_iter<1, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE, MASK>(it + 1, a, src, dst, sm, st, t, tM, tU);
     if (it + 2 < t.nit)
-      march_iter<2, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it + 2, a, src, dst, sm, st, t, tM, tU);
+      march_iter<2, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE, MASK>(it + 2, a, src, dst, sm, st, t, tM, tU);
     if (it + 3 < t.nit)
-      march_iter<3, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(it + 3, a, src, dst, sm, st, t, tM, tU);
+      march_iter<3, ST, T, NTX, NR, RG, RK, RP, RU, WALLS, MODE, MASK>(it + 3, a, src, dst, sm, st, t, tM, tU);
   }
 }
 
-template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE>
+template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE, bool MASK = false>
 __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typename ST::math> a) {
   using T = typename ST::math;
   using PP = Pipe<NR>;
@@ -810,7 +863,7 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typen
   const int per_xcd = (ntiles + 7) / 8;
   const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
   if (tile >= ntiles) return;
-  march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE>(a, tile, sm);
+  march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE, MASK>(a, tile, sm);
 }
 
 // ---------------------------------------------------------------------------

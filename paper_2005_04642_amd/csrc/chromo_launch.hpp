@@ -127,6 +127,7 @@ StepArgs<typename S::math> args(const lbm_params& p, const Geom& g, const void* 
   a.force = static_cast<const T*>(force);
   a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = a.out_save = a.out_adj = nullptr;
   a.lam_next = nullptr;
+  a.bnc = nullptr;
   a.g = geom_for<S>(g);
   a.c = make_coef<S>(p);
   return a;
@@ -322,11 +323,37 @@ void sim_desc(const lbm_params& p, const Geom& g, unsigned long long off, void* 
 // field planes of ws
 // ---------------------------------------------------------------------------
 template <typename S>
-hipError_t solid_prepare(const Geom& g0, void* pops, const unsigned char* mask, hipStream_t s) {
+hipError_t solid_prepare(const Geom& g0, void* pops, const unsigned char* mask, void* ws, hipStream_t s) {
   const Geom g = geom_for<S>(g0);
   const dim3 grid((g.nx + 255) / 256, g.ny);
   hipLaunchKernelGGL(solid::rebounce_kernel<S>, grid, dim3(256), 0, s, pops, mask, g);
   hipLaunchKernelGGL(solid::clear_solid_kernel<S>, grid, dim3(256), 0, s, pops, mask, g);
+  unsigned char* bits = static_cast<unsigned char*>(ws) + solid::bits_offset(g.plane, sizeof(typename S::math));
+  hipLaunchKernelGGL(solid::bounce_bits_kernel<S>, grid, dim3(256), 0, s, mask, g, bits);
+  return hipGetLastError();
+}
+
+// The fused step kernel with a mask, for the stencil profiles (3,3,3,3) and
+// (1,1,1,1); hipErrorNotSupported for the others (the caller then runs the
+// four passes).
+template <typename S>
+hipError_t solid_fused(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force, void* ws,
+                       hipStream_t s) {
+  constexpr int NTX = Shape<S>::ntx, NR = Shape<S>::nr;
+  StepArgs<typename S::math> a = args<S>(p, g, src, dst, force);
+  a.bnc = static_cast<const unsigned char*>(ws) + solid::bits_offset(g.plane, sizeof(typename S::math));
+  const int ntiles = a.g.nstrips * a.g.nchunks;
+  const int nblocks = 8 * ((ntiles + 7) / 8);
+  const int* r = p.stencil;
+  if (r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3) {
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 3, 3, 3, 3, false, MODE_STEP, true>), dim3(nblocks),
+                       dim3(NTX * NR), 0, s, a);
+  } else if (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1) {
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 1, 1, 1, 1, false, MODE_STEP, true>), dim3(nblocks),
+                       dim3(NTX * NR), 0, s, a);
+  } else {
+    return hipErrorNotSupported;
+  }
   return hipGetLastError();
 }
 
@@ -404,6 +431,7 @@ Ops make_ops() {
     o.rhoN_adjoint = nullptr;
     o.init_adjoint = nullptr;
     o.solid_prepare = nullptr;
+    o.solid_fused = nullptr;
     o.solid_step = nullptr;
     o.solid_fields = nullptr;
   } else {
@@ -411,6 +439,7 @@ Ops make_ops() {
     o.rhoN_adjoint = rhoN_adjoint<S>;
     o.init_adjoint = init_adjoint<S>;
     o.solid_prepare = solid_prepare<S>;
+    o.solid_fused = solid_fused<S>;
     o.solid_step = solid_step<S>;
     o.solid_fields = solid_fields<S>;
   }

@@ -13,7 +13,11 @@
 //   3. curvature K = div n (n = -m), force G and velocity u (or the fields);
 //   4. grad Phi', div u, collision and recolour of the re-gathered site, store.
 // The per-site arithmetic and the order of every stencil sum are those of the
-// fused step kernel, so a mask without solid sites reproduces it.
+// fused step kernel, so a mask without solid sites reproduces it.  For the
+// stencil profiles it is instantiated for, the fused step kernel also runs
+// with a mask (its MASK variant: per-site bounce bits in the gather, NaN
+// markers for the taps); these passes are the reference it is tested against
+// and serve the other profiles.
 #pragma once
 
 #include "chromo_kernels.hpp"
@@ -23,6 +27,9 @@ namespace solid {
 
 // field planes of the workspace, each [ny][nx] of the arithmetic type
 enum { P_RR, P_RB, P_JX, P_JY, P_RN, P_PHI, P_MX, P_MY, P_GNX, P_GNY, P_UX, P_UY, P_GX, P_GY, P_N };
+// The workspace holds the P_N planes, then (at the next 256-byte boundary) the
+// [ny][nx] bounce bits of the fused kernel.
+inline size_t bits_offset(size_t plane, size_t elem) { return (P_N * plane * elem + 255) / 256 * 256; }
 
 // periodic index for offsets of at most the lattice size (the host requires
 // nx, ny >= 4 and offsets are at most 3)
@@ -121,6 +128,27 @@ __global__ void __launch_bounds__(256) rebounce_kernel(void* popsv, const unsign
     if (solid[at(g, xd, yd)])
       pops[((size_t)y * S::NW + q) * g.nx + x] = pops[((size_t)yd * S::NW + word_bounce<S>(q)) * g.nx + xd];
   }
+}
+
+// Bounce bits of every site for the fused step kernel: bit i - 1 set when the
+// source r - c_i of link i is solid; all bits at a solid site (its gather then
+// reads its own zero words).  (A template only so that every format's
+// translation unit has its own copy.)
+template <typename S>
+__global__ void __launch_bounds__(256) bounce_bits_kernel(const unsigned char* __restrict__ solid, Geom g,
+                                                          unsigned char* __restrict__ out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y;
+  if (x >= g.nx) return;
+  const size_t site = at(g, x, y);
+  unsigned b = 0xffu;
+  if (!solid[site]) {
+    b = 0u;
+#pragma unroll
+    for (int i = 1; i < 9; ++i)
+      if (solid[at(g, wrap(x - link_cx(i), g.nx), wrap(y - link_cy(i), g.ny))]) b |= 1u << (i - 1);
+  }
+  out[site] = (unsigned char)b;
 }
 
 // Zero the words of solid sites (they carry no state and no mass).

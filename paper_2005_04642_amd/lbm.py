@@ -20,7 +20,7 @@ LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENOTIMPL, LBM_ENONFINITE = 0, -1, -2, -3, -4
 LBM_STORAGE_F64, LBM_STORAGE_F32, LBM_STORAGE_F16_OFS, LBM_STORAGE_BF16_OFS = 0, 1, 2, 3
 STORAGE = {"f64": LBM_STORAGE_F64, "f32": LBM_STORAGE_F32, "f16": LBM_STORAGE_F16_OFS, "bf16": LBM_STORAGE_BF16_OFS}
 WORDS_PER_SITE = {"f64": 18, "f32": 18, "f16": 10, "bf16": 10}
-LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR = 1, 2, 4
+LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR, LBM_FLAG_MASK_PASSES = 1, 2, 4, 8
 
 # every symbol the header declares
 EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_workspace_bytes", "lbm_init",
