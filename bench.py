@@ -174,9 +174,10 @@ def storage16_measure(n, params, rn, torch, steps=200, warmup=20):
 
 
 def solid_measure(n, params, rn, torch, ms_fused, steps=100, warmup=10):
-    """Step with a solid-site mask (four launches per step): the benchmark
-    lattice inside a circular container wall of radius n/2 - 2 (FP32), and the
-    curved-interface transient's 724^2 container at Lambda = 5 (FP64)."""
+    """Step with a solid-site mask (the fused kernel's mask variant; the four
+    pass kernels timed beside it): the benchmark lattice inside a circular
+    container wall of radius n/2 - 2 (FP32), and the curved-interface
+    transient's 724^2 container at Lambda = 5 (FP64)."""
     import numpy as np
     from paper_2005_04642_amd import lbm, workloads as Wk
 
@@ -195,12 +196,17 @@ def solid_measure(n, params, rn, torch, ms_fused, steps=100, warmup=10):
     sim = lbm.Simulation(n, n, params, rn, storage="f32", device="cuda:0", solid=solid)
     ms = timed(sim, steps)
     sim.close()
+    sim = lbm.Simulation(n, n, params, rn, storage="f32", device="cuda:0", solid=solid,
+                         flags=lbm.LBM_FLAG_MASK_PASSES)
+    ms4 = timed(sim, max(10, steps // 5))
+    sim.close()
     fluid = int((~solid).sum())
     out = {"workload": "%dx%d emulsion inside a circular wall of radius %g (%.1f %% of sites solid), FP32, "
                        "%d steps" % (n, n, n / 2.0 - 2.0, 100.0 * (1 - fluid / (n * n)), steps),
            "ms_per_step": round(ms, 5), "MLUPS_all_sites": round(n * n / ms / 1e3, 1),
            "MLUPS_fluid_sites": round(fluid / ms / 1e3, 1),
-           "vs_fused_step_without_mask": round(ms_fused / ms, 4)}
+           "vs_fused_step_without_mask": round(ms_fused / ms, 4),
+           "four_pass_kernels_ms_per_step": round(ms4, 5)}
     nx, ny, p, rn2, _, _, solid2, _ = Wk.config_curved_transient(5.0)
     sim = lbm.Simulation(nx, ny, p, rn2, storage="f64", device="cuda:0", solid=solid2)
     ms2 = timed(sim, 200)
