@@ -160,10 +160,12 @@ int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN,
 int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream);
 
 /* ---- adjoint (reverse-mode derivative of lbm_step) ------------------------
- * Provided for LBM_STORAGE_F64 and LBM_STORAGE_F32, periodic or walled
+ * Provided for LBM_STORAGE_F64 and LBM_STORAGE_F32, periodic, walled
  * (walls_y = 1: the transposes of the wall-mirrored stencils and of the
- * bounce-back); the 16-bit formats return LBM_ENOTIMPL.  The words of solid
- * rows carry no state: their adjoints are written as 0.  Adjoint buffers have the
+ * bounce-back) or with a mask of solid sites (lbm_set_solid; stencil profiles
+ * (3,3,3,3) and (1,1,1,1), others LBM_ENOTIMPL); the 16-bit formats return
+ * LBM_ENOTIMPL.  The words of solid rows and sites carry no state: their
+ * adjoints are written as 0.  Adjoint buffers have the
  * layout of an F64/F32 population buffer ([ny][colour 2][link 9][nx], the
  * arithmetic type), aligned with the pull layout: adj[C][i](s) is dL/d of the
  * stored word buf[C][i](s).  The step that is differentiated is the one
@@ -286,8 +288,10 @@ size_t lbm_solid_workspace_bytes(const lbm_params* p);
  * then on lbm_step and lbm_fields use the mask.  A handle takes one mask:
  * LBM_EINVAL if it has one already, for NULL pointers, a small workspace,
  * walls_y = 1 or nx, ny < 4; LBM_ENOTIMPL for the 16-bit formats and the
- * streaming-only mode.  The adjoint entry points return LBM_ENOTIMPL on such
- * a handle. */
+ * streaming-only mode.  The adjoint entry points work on such a handle for
+ * the stencil profiles (3,3,3,3) and (1,1,1,1) (LBM_ENOTIMPL for the others);
+ * lbm_init_adjoint then differentiates the rest state as lbm_set_solid
+ * re-encoded it. */
 int lbm_set_solid(lbm_handle* h, const uint8_t* solid_dev, void* workspace, size_t ws_bytes, hipStream_t stream);
 
 /* 0 if pops_a holds the live state, 1 if pops_b does. */

@@ -1,5 +1,6 @@
 // Adjoint of one time step (reverse-mode derivative of the step of
-// chromo_kernels.hpp) on periodic lattices.
+// chromo_kernels.hpp) on periodic lattices, walled lattices and lattices with
+// a mask of solid sites.
 //
 // The step maps the stored populations buf_t (post-recolour, pull layout) to
 // buf_{t+1}.  Given lambda_{t+1} = dL/dbuf_{t+1} (same layout, arithmetic
@@ -19,7 +20,10 @@
 //   pass 5 (gather) : pre-collision populations from rho_C, f_i, j, and the
 //                     pull-streaming gather transposed (a push).
 // Every App. B stencil D is a sum of antisymmetric pair differences, so on a
-// periodic lattice its transpose is -D.
+// periodic lattice its transpose is -D.  With a mask, a tap on a solid site
+// reads the centre value; for an adjoint field lambda that is zero at solid
+// sites the transpose is then -D lambda plus lambda at the centre times the
+// summed weights of the centre's solid taps.
 #pragma once
 
 #include "chromo_kernels.hpp"
@@ -139,6 +143,47 @@ __device__ __forceinline__ bool solid_row(const Geom& g, int y) { return g.walls
 template <bool W>
 __device__ __forceinline__ bool solid_row_w(const Geom& g, int y) {
   return W && (y == 0 || y == g.ny - 1);
+}
+
+// solid site: a wall row (W) or a site of the mask (M)
+template <bool W, bool M>
+__device__ __forceinline__ bool solid_at(const Geom& g, const unsigned char* solid, int x, int y) {
+  if constexpr (M) return solid[(size_t)y * g.nx + x] != 0;
+  return solid_row_w<W>(g, y);
+}
+
+// Summed weights b_n w_i c_i of the taps of the radius-R stencil at (x, y)
+// that fall on solid sites of the mask (the weight the centre value takes).
+template <int R, typename T>
+__device__ __forceinline__ void solid_tap_weights(const unsigned char* solid, int nx, int ny, int x, int y, T& wx,
+                                                  T& wy) {
+  const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
+  wx = T(0);
+  wy = T(0);
+#pragma unroll
+  for (int n = 1; n <= R; ++n) {
+    const T b = stencil_b<R, T>(n);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int cx = link_cx(i), cy = link_cy(i);
+      const int xs = wrapi(x + n * cx, nx), ys = wrapi(y + n * cy, ny);
+      if (solid[(size_t)ys * nx + xs]) {
+        const T bw = b * ((i & 1) ? wd : wa);
+        wx += bw * T(cx);
+        wy += bw * T(cy);
+      }
+    }
+  }
+}
+
+template <typename T>
+__device__ __forceinline__ void solid_tap_weights_r(int r, const unsigned char* solid, int nx, int ny, int x, int y,
+                                                    T& wx, T& wy) {
+  if (r == 3) {
+    solid_tap_weights<3>(solid, nx, ny, x, y, wx, wy);
+  } else {
+    solid_tap_weights<1>(solid, nx, ny, x, y, wx, wy);
+  }
 }
 
 struct Radii {
@@ -361,17 +406,32 @@ static __device__ __forceinline__ double block_sum(double v) {
 // ---------------------------------------------------------------------------
 // pass 2: div u and grad Phi' transposed; u, Phi', G local
 // ---------------------------------------------------------------------------
-template <typename T, bool W>
+template <typename T, bool W, bool M = false>
 __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, Radii r, const T* __restrict__ sv,
                                                     const T* __restrict__ A, T* __restrict__ B,
-                                                    T* __restrict__ dforce, double* __restrict__ part) {
+                                                    T* __restrict__ dforce, double* __restrict__ part,
+                                                    const unsigned char* __restrict__ solid) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   const int P = g.plane, site = y * g.nx + x;
   double acc = 0.0;
-  if (x < g.nx && !solid_row_w<W>(g, y)) {
+  if (M && x < g.nx && solid_at<W, M>(g, solid, x, y)) {
+#pragma unroll
+    for (int k = 0; k < B_N; ++k) B[k * P + site] = T(0);   // read by the next passes' stencils
+  }
+  if (x < g.nx && !solid_at<W, M>(g, solid, x, y)) {
     T lux, luy, lphi;
-    if constexpr (W) {
+    if constexpr (M) {
+      T tx, ty, wx, wy;
+      grad_r(r.u, A + A_TH * P, g.nx, g.ny, x, y, tx, ty);
+      solid_tap_weights_r(r.u, solid, g.nx, g.ny, x, y, wx, wy);
+      const T lth = A[A_TH * P + site];
+      lux = A[A_UX * P + site] - tx + lth * wx;
+      luy = A[A_UY * P + site] - ty + lth * wy;
+      solid_tap_weights_r(r.p, solid, g.nx, g.ny, x, y, wx, wy);
+      lphi = -div_r(r.p, A + A_DPX * P, A + A_DPY * P, g.nx, g.ny, x, y) + A[A_DPX * P + site] * wx +
+             A[A_DPY * P + site] * wy;
+    } else if constexpr (W) {
       T ax, ay, bx, by;
       gradT_walls(r.u, A + A_TH * P, g.nx, g.ny, x, y, false, ax, ay);  // theta = D_x u_x + D_y u_y (u_y odd)
       gradT_walls(r.u, A + A_TH * P, g.nx, g.ny, x, y, true, bx, by);
@@ -431,11 +491,12 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, 
 // per-workgroup dL/dsigma partials to *dsigma while the other workgroups run
 // the pass.  Each thread sums a fixed strided subset in 8 interleaved
 // accumulators, combined in a fixed order (deterministic).
-template <typename T, bool W>
+template <typename T, bool W, bool M = false>
 __global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii r, const T* __restrict__ sv,
                                                        const T* __restrict__ A, const T* __restrict__ B,
                                                        T* __restrict__ C, const double* __restrict__ part,
-                                                       int npart, double* dsigma) {
+                                                       int npart, double* dsigma,
+                                                       const unsigned char* __restrict__ solid) {
   if (blockIdx.y == 0) {
     if (blockIdx.x == 0 && dsigma) {
       constexpr int U = 8, BS = 256;
@@ -455,10 +516,21 @@ __global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii 
   }
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y - 1;
-  if (x >= g.nx || solid_row_w<W>(g, y)) return;
+  if (x >= g.nx) return;
   const int P = g.plane, site = y * g.nx + x;
+  if (solid_at<W, M>(g, solid, x, y)) {
+    if (M) C[C_GX * P + site] = C[C_GY * P + site] = T(0);
+    return;
+  }
   T kx, ky;
-  if constexpr (W) {  // K = -(D_x m_x + D_y m_y), m_y odd: lambda_m = -D^T lambda_K
+  if constexpr (M) {  // lambda_m = -D^T lambda_K = D lambda_K - lambda_K(s) (solid tap weights)
+    T wx, wy;
+    grad_r(r.k, B + B_K * P, g.nx, g.ny, x, y, kx, ky);
+    solid_tap_weights_r(r.k, solid, g.nx, g.ny, x, y, wx, wy);
+    const T lk = B[B_K * P + site];
+    kx -= lk * wx;
+    ky -= lk * wy;
+  } else if constexpr (W) {  // K = -(D_x m_x + D_y m_y), m_y odd: lambda_m = -D^T lambda_K
     T ax, ay, bx, by;
     gradT_walls(r.k, B + B_K * P, g.nx, g.ny, x, y, false, ax, ay);
     gradT_walls(r.k, B + B_K * P, g.nx, g.ny, x, y, true, bx, by);
@@ -480,16 +552,26 @@ __global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii 
 // ---------------------------------------------------------------------------
 // pass 4: grad rho^N transposed; colour index
 // ---------------------------------------------------------------------------
-template <typename T, bool W>
+template <typename T, bool W, bool M = false>
 __global__ void __launch_bounds__(256) colour_kernel(Geom g, Coef<T> c, Radii r, const T* __restrict__ sv,
                                                      const T* __restrict__ A, const T* __restrict__ B,
-                                                     const T* __restrict__ C, T* __restrict__ D) {
+                                                     const T* __restrict__ C, T* __restrict__ D,
+                                                     const unsigned char* __restrict__ solid) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= g.nx || solid_row_w<W>(g, y)) return;
+  if (x >= g.nx) return;
   const int P = g.plane, site = y * g.nx + x;
+  if (solid_at<W, M>(g, solid, x, y)) {
+    if (M) D[D_RR * P + site] = D[D_RB * P + site] = T(0);
+    return;
+  }
   T dv;
-  if constexpr (W) {  // g = grad rho^N (even): lambda_rhoN += D_x^T lambda_gx + D_y^T lambda_gy
+  if constexpr (M) {  // lambda_rhoN += D^T lambda_g = -div lambda_g + lambda_g(s) . (solid tap weights)
+    T wx, wy;
+    solid_tap_weights_r(r.g, solid, g.nx, g.ny, x, y, wx, wy);
+    dv = div_r(r.g, C + C_GX * P, C + C_GY * P, g.nx, g.ny, x, y) - C[C_GX * P + site] * wx -
+         C[C_GY * P + site] * wy;
+  } else if constexpr (W) {  // g = grad rho^N (even): lambda_rhoN += D_x^T lambda_gx + D_y^T lambda_gy
     T ax, ay, bx, by;
     gradT_walls(r.g, C + C_GX * P, g.nx, g.ny, x, y, false, ax, ay);
     gradT_walls(r.g, C + C_GY * P, g.nx, g.ny, x, y, false, bx, by);
@@ -509,14 +591,15 @@ __global__ void __launch_bounds__(256) colour_kernel(Geom g, Coef<T> c, Radii r,
 // pass 5: pre-collision adjoints and the transposed pull gather:
 // lambda_t[C][i](s) = dL/dC_i(s + c_i), dL/dC_i = lambda_f_i + lambda_rho_C + lambda_j . c_i
 // ---------------------------------------------------------------------------
-template <typename T, bool W>
+template <typename T, bool W, bool M = false>
 __global__ void __launch_bounds__(256) push_kernel(Geom g, const T* __restrict__ A, const T* __restrict__ B,
-                                                   const T* __restrict__ D, T* __restrict__ out) {
+                                                   const T* __restrict__ D, T* __restrict__ out,
+                                                   const unsigned char* __restrict__ solid) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
   const int P = g.plane;
-  if (solid_row_w<W>(g, y)) {  // no fluid site reads a solid row's words
+  if (solid_at<W, M>(g, solid, x, y)) {  // no fluid site reads a solid site's words
 #pragma unroll
     for (int q = 0; q < 18; ++q) out[((size_t)y * 18 + q) * g.nx + x] = T(0);
     return;
@@ -529,7 +612,7 @@ __global__ void __launch_bounds__(256) push_kernel(Geom g, const T* __restrict__
     ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
     // the word is pulled by link i of site s + c_i, or, when that site is
     // solid, bounced back into link opp(i) of s itself
-    const bool bounce = solid_row_w<W>(g, ys);
+    const bool bounce = solid_at<W, M>(g, solid, xs, ys);
     const int k = bounce ? link_opp(i) : i;
     const int r = bounce ? y * g.nx + x : ys * g.nx + xs;
     const T common = A[(A_F + k) * P + r] + T(link_cx(k)) * B[B_JX * P + r] + T(link_cy(k)) * B[B_JY * P + r];
@@ -542,15 +625,19 @@ __global__ void __launch_bounds__(256) push_kernel(Geom g, const T* __restrict__
 // adjoint of the colour-index field of the pre-collision state:
 // lambda[C][i](s) = dL/drho^N(s + c_i) * drho^N/drho_C(s + c_i)
 // ---------------------------------------------------------------------------
-template <typename S>
+// M: a mask of solid sites (bnc: the bounce bits of the masked gather)
+template <typename S, bool M = false>
 __global__ void __launch_bounds__(256) rhoN_adjoint_kernel(const void* popsv, Geom g, Coef<typename S::math> c,
                                                            const typename S::math* __restrict__ lrN,
-                                                           typename S::math* __restrict__ out) {
+                                                           typename S::math* __restrict__ out,
+                                                           const unsigned char* __restrict__ solid,
+                                                           const unsigned char* __restrict__ bnc) {
   using T = typename S::math;
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
-  if (solid_row(g, y)) {
+  auto is_solid = [&](int xx, int yy) { return M ? solid[(size_t)yy * g.nx + xx] != 0 : solid_row(g, yy); };
+  if (is_solid(x, y)) {
 #pragma unroll
     for (int q = 0; q < 18; ++q) out[((size_t)y * 18 + q) * g.nx + x] = typename S::math(0);
     return;
@@ -563,7 +650,7 @@ __global__ void __launch_bounds__(256) rhoN_adjoint_kernel(const void* popsv, Ge
     int xs = x + link_cx(i), ys = y + link_cy(i);
     xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
     ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
-    if (solid_row(g, ys)) {
+    if (is_solid(xs, ys)) {
       xs = x;
       ys = y;
     }
@@ -572,7 +659,11 @@ __global__ void __launch_bounds__(256) rhoN_adjoint_kernel(const void* popsv, Ge
     cols.m = (xs == 0 ? g.nx - 1 : xs - 1) * E;
     cols.p = (xs == g.nx - 1 ? 0 : xs + 1) * E;
     typename S::W w[S::NW];
-    gather_words_any<S>(make_rsrc<S>(popsv, g.plane), g, ys, cols, w);
+    if constexpr (M) {
+      gather_words<S, false, true>(make_rsrc<S>(popsv, g.plane), g, ys, cols, w, bnc, xs);
+    } else {
+      gather_words_any<S>(make_rsrc<S>(popsv, g.plane), g, ys, cols, w);
+    }
     T R[9], B[9];
     decode<S>(w, c, R, B);
     T rR = T(0), rB = T(0);
@@ -593,13 +684,18 @@ __global__ void __launch_bounds__(256) rhoN_adjoint_kernel(const void* popsv, Ge
 // adjoint of the initial state (rest state of rho^N_0, written un-streamed):
 // dL/drho^N_0(r) = sum_{C,i} lambda_0[C][i](r - c_i) d(rho_C phi_i)(r)/drho^N_0
 // ---------------------------------------------------------------------------
-template <typename T>
+//
+// M: with a mask, a fluid site's word i holds the rest population of link
+// opp(i) at the site itself when s + c_i is solid (lbm_set_solid re-encodes
+// the rest state so), and solid sites hold nothing.
+template <typename T, bool M = false>
 __global__ void __launch_bounds__(256) init_adjoint_kernel(const T* __restrict__ rhoN0, const T* __restrict__ lam0,
                                                            Geom g, Coef<T> c, T rho0R, T rho0B,
-                                                           T* __restrict__ out) {
+                                                           T* __restrict__ out, const unsigned char* __restrict__ solid) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  if (x >= g.nx || solid_row(g, y)) return;
+  auto is_solid = [&](int xx, int yy) { return M ? solid[(size_t)yy * g.nx + xx] != 0 : solid_row(g, yy); };
+  if (x >= g.nx || is_solid(x, y)) return;
   const int site = y * g.nx + x;
   const T rn = rhoN0[site];
   const T rR = rho0R * (T(1) + rn) * T(0.5), rB = rho0B * (T(1) - rn) * T(0.5);
@@ -626,11 +722,11 @@ __global__ void __launch_bounds__(256) init_adjoint_kernel(const T* __restrict__
     // word i at s - c_i holds the rest population of link i at s when s - c_i
     // is fluid; with walls, word i at s itself holds that of link opp(i) (the
     // same rest fraction) when s + c_i is solid
-    if (!solid_row(g, ys)) {
+    if (!is_solid(xs, ys)) {
       const T* l = lam0 + (size_t)ys * 18 * g.nx + xs;  // [y][C i][x], as the populations
       acc += l[i * g.nx] * (dR * phi + rR * dphi) + l[(9 + i) * g.nx] * (dB * phi + rB * dphi);
     }
-    if (solid_row(g, y + link_cy(i))) {
+    if (M ? is_solid(wrapi(x + link_cx(i), g.nx), wrapi(y + link_cy(i), g.ny)) : solid_row(g, y + link_cy(i))) {
       const T* l = lam0 + (size_t)y * 18 * g.nx + x;
       acc += l[i * g.nx] * (dR * phi + rR * dphi) + l[(9 + i) * g.nx] * (dB * phi + rB * dphi);
     }

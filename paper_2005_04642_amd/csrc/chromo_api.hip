@@ -285,8 +285,21 @@ size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
 static int adjoint_supported(const lbm_handle* h) {
   if (!h->ops->adjoint) return fail(LBM_ENOTIMPL, "the adjoint is provided for F64 and F32 storage only");
   if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no adjoint of the streaming-only test mode");
-  if (h->solid) return fail(LBM_ENOTIMPL, "no adjoint on a lattice with a solid-site mask");
+  if (h->solid) {
+    const int* r = h->p.stencil;
+    const bool all3 = r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3;
+    const bool all1 = r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1;
+    if (!all3 && !all1)
+      return fail(LBM_ENOTIMPL, "the adjoint with a solid-site mask is built for stencil profiles 3333 and 1111");
+  }
   return LBM_OK;
+}
+
+// bounce bits of the handle's mask (inside its solid workspace), or null
+static const unsigned char* bounce_bits(const lbm_handle* h) {
+  if (!h->solid) return nullptr;
+  const size_t elem = h->p.storage == LBM_STORAGE_F64 ? 8 : 4;
+  return static_cast<const unsigned char*>(h->solid_ws) + chromo::solid::bits_offset((size_t)h->g.plane, elem);
 }
 
 int lbm_adjoint_step(lbm_handle* h, const void* pops_t, const void* adj_next, void* adj_out, void* workspace,
@@ -302,7 +315,7 @@ int lbm_adjoint_step(lbm_handle* h, const void* pops_t, const void* adj_next, vo
     return fail(LBM_EINVAL, "adjoint workspace too small: %zu < %zu", ws_bytes, lbm_adjoint_workspace_bytes(&h->p));
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
   hipError_t e = h->ops->adjoint(h->p, h->g_adj, pops_t, h->force, adj_next, adj_out, workspace, dL_dsigma_dev,
-                                 dL_dforce_dev, stream);
+                                 dL_dforce_dev, h->solid, bounce_bits(h), stream);
   if (e != hipSuccess) return fail(LBM_EHIP, "adjoint launch: %s", hipGetErrorString(e));
   return LBM_OK;
 }
@@ -313,7 +326,7 @@ int lbm_rhoN_adjoint(lbm_handle* h, const void* pops, const void* dL_drhoN, void
   int st = adjoint_supported(h);
   if (st != LBM_OK) return st;
   if (!pops || !dL_drhoN || !adj_out) return fail(LBM_EINVAL, "pops, dL_drhoN and adj_out must be non-NULL");
-  hipError_t e = h->ops->rhoN_adjoint(h->p, h->g, pops, dL_drhoN, adj_out, stream);
+  hipError_t e = h->ops->rhoN_adjoint(h->p, h->g, pops, dL_drhoN, adj_out, h->solid, bounce_bits(h), stream);
   if (e != hipSuccess) return fail(LBM_EHIP, "rhoN adjoint launch: %s", hipGetErrorString(e));
   return LBM_OK;
 }
@@ -324,7 +337,7 @@ int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, vo
   int st = adjoint_supported(h);
   if (st != LBM_OK) return st;
   if (!rhoN0 || !adj_pops0 || !dL_drhoN0) return fail(LBM_EINVAL, "rhoN0, adj_pops0 and dL_drhoN0 must be non-NULL");
-  hipError_t e = h->ops->init_adjoint(h->p, h->g, rhoN0, adj_pops0, dL_drhoN0, stream);
+  hipError_t e = h->ops->init_adjoint(h->p, h->g, rhoN0, adj_pops0, dL_drhoN0, h->solid, stream);
   if (e != hipSuccess) return fail(LBM_EHIP, "init adjoint launch: %s", hipGetErrorString(e));
   return LBM_OK;
 }

@@ -42,11 +42,12 @@ struct Ops {
   // adjoint (F64/F32, periodic or walled; null for formats without it)
   // g: geometry planned for the adjoint workgroup shape (ntx_for(storage, true))
   hipError_t (*adjoint)(const lbm_params& p, const Geom& g, const void* pops, const void* force,
-                        const void* lam_next, void* lam_out, void* ws, double* dsigma, void* dforce, hipStream_t s);
+                        const void* lam_next, void* lam_out, void* ws, double* dsigma, void* dforce,
+                        const unsigned char* solid, const unsigned char* bnc, hipStream_t s);
   hipError_t (*rhoN_adjoint)(const lbm_params& p, const Geom& g, const void* pops, const void* lrN, void* out,
-                             hipStream_t s);
+                             const unsigned char* solid, const unsigned char* bnc, hipStream_t s);
   hipError_t (*init_adjoint)(const lbm_params& p, const Geom& g, const void* rhoN0, const void* lam0, void* out,
-                             hipStream_t s);
+                             const unsigned char* solid, hipStream_t s);
   // solid sites anywhere (F64/F32; null for the others).  mask: device
   // [ny][nx] bytes, nonzero = solid; ws: solid::P_N planes of the arithmetic type
   hipError_t (*solid_prepare)(const Geom& g, void* pops, const unsigned char* mask, void* ws, hipStream_t s);

@@ -551,6 +551,13 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
       lB[i] = ln[(9 + i) * a.g.nx];
     }
     adj::local_backward(c, f, rR, rB, ux, uy, Gx, Gy, dPx, dPy, theta, rhoN, mx, my, lR, lB, out);
+    if constexpr (MASK) {
+      // a solid site has no adjoints (the transposed stencils read them as 0)
+      if (rho == T(0)) {
+#pragma unroll
+        for (int q = 0; q < adj::A_N; ++q) out[q] = T(0);
+      }
+    }
 #pragma unroll
     for (int q = 0; q < adj::A_N; ++q) a.out_adj[q * P + site] = out[q];
     T* sv = a.out_save + site;

@@ -179,19 +179,41 @@ hipError_t mass(const lbm_params& p, const Geom& g, const void* pops, double* pa
   return hipGetLastError();
 }
 
-// passes 2-5 of the adjoint, with the lattice kind (periodic or walled) fixed
-// at compile time
-template <typename T, bool W>
+// passes 2-5 of the adjoint, with the lattice kind (periodic, walled, or with
+// a mask of solid sites: M) fixed at compile time
+template <typename T, bool W, bool M>
 void adjoint_tail(const StepArgs<T>& a, const Geom& g, const adj::Radii& r, T sigma, const T* sv, const T* A, T* B,
-                  T* C, T* D, double* part, double* dsigma, T* dforce, T* lam_out, hipStream_t s) {
+                  T* C, T* D, double* part, double* dsigma, T* dforce, T* lam_out, const unsigned char* solid,
+                  hipStream_t s) {
   const dim3 grid((g.nx + 255) / 256, g.ny);
-  hipLaunchKernelGGL((adj::force_kernel<T, W>), grid, dim3(256), 0, s, g, a.c, sigma, r, sv, A, B, dforce, part);
+  hipLaunchKernelGGL((adj::force_kernel<T, W, M>), grid, dim3(256), 0, s, g, a.c, sigma, r, sv, A, B, dforce, part,
+                     solid);
   // pass 3, plus the sum of pass 2's dL/dsigma partials in one extra row of workgroups
-  hipLaunchKernelGGL((adj::director_kernel<T, W>), dim3(grid.x, g.ny + 1), dim3(256), 0, s, g, a.c, r, sv, A,
-                     (const T*)B, C, (const double*)part, adj::red_blocks(g.nx, g.ny), dsigma);
-  hipLaunchKernelGGL((adj::colour_kernel<T, W>), grid, dim3(256), 0, s, g, a.c, r, sv, A, (const T*)B,
-                     (const T*)C, D);
-  hipLaunchKernelGGL((adj::push_kernel<T, W>), grid, dim3(256), 0, s, g, A, (const T*)B, (const T*)D, lam_out);
+  hipLaunchKernelGGL((adj::director_kernel<T, W, M>), dim3(grid.x, g.ny + 1), dim3(256), 0, s, g, a.c, r, sv, A,
+                     (const T*)B, C, (const double*)part, adj::red_blocks(g.nx, g.ny), dsigma, solid);
+  hipLaunchKernelGGL((adj::colour_kernel<T, W, M>), grid, dim3(256), 0, s, g, a.c, r, sv, A, (const T*)B,
+                     (const T*)C, D, solid);
+  hipLaunchKernelGGL((adj::push_kernel<T, W, M>), grid, dim3(256), 0, s, g, A, (const T*)B, (const T*)D, lam_out,
+                     solid);
+}
+
+// pass 1 with a mask: the step kernel's mask variant in MODE_ADJ, built for the
+// stencil profiles (3,3,3,3) and (1,1,1,1)
+template <typename S>
+hipError_t march_adj_masked(const StepArgs<typename S::math>& a, const int* r, hipStream_t s) {
+  constexpr int NTX = Shape<S, MODE_ADJ>::ntx, NR = Shape<S, MODE_ADJ>::nr;
+  const int ntiles = a.g.nstrips * a.g.nchunks;
+  const int nblocks = 8 * ((ntiles + 7) / 8);
+  if (r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3) {
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 3, 3, 3, 3, false, MODE_ADJ, true>), dim3(nblocks),
+                       dim3(NTX * NR), 0, s, a);
+  } else if (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1) {
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 1, 1, 1, 1, false, MODE_ADJ, true>), dim3(nblocks),
+                       dim3(NTX * NR), 0, s, a);
+  } else {
+    return hipErrorNotSupported;
+  }
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -202,7 +224,8 @@ void adjoint_tail(const StepArgs<T>& a, const Geom& g, const adj::Radii& r, T si
 // ---------------------------------------------------------------------------
 template <typename S>
 hipError_t adjoint(const lbm_params& p, const Geom& g0, const void* pops, const void* force, const void* lam_next,
-                   void* lam_out, void* ws, double* dsigma, void* dforce, hipStream_t s) {
+                   void* lam_out, void* ws, double* dsigma, void* dforce, const unsigned char* solid,
+                   const unsigned char* bnc, hipStream_t s) {
   using T = typename S::math;
   StepArgs<T> a = args<S>(p, g0, pops, nullptr, force);
   const Geom& g = a.g;
@@ -216,39 +239,53 @@ hipError_t adjoint(const lbm_params& p, const Geom& g0, const void* pops, const 
   a.out_save = sv;
   a.out_adj = A;
   a.lam_next = static_cast<const T*>(lam_next);
-  hipError_t e = dispatch_radii<S, MODE_ADJ>(a, p.stencil, s);
+  a.bnc = bnc;
+  hipError_t e = solid ? march_adj_masked<S>(a, p.stencil, s) : dispatch_radii<S, MODE_ADJ>(a, p.stencil, s);
   if (e != hipSuccess) return e;
   const adj::Radii r = {p.stencil[0], p.stencil[1], p.stencil[2], p.stencil[3]};
-  if (g.walls) {
-    adjoint_tail<T, true>(a, g, r, (T)p.sigma, sv, A, B, C, D, part, dsigma, static_cast<T*>(dforce),
-                          static_cast<T*>(lam_out), s);
+  T* dfo = static_cast<T*>(dforce);
+  T* lo = static_cast<T*>(lam_out);
+  if (solid) {
+    adjoint_tail<T, false, true>(a, g, r, (T)p.sigma, sv, A, B, C, D, part, dsigma, dfo, lo, solid, s);
+  } else if (g.walls) {
+    adjoint_tail<T, true, false>(a, g, r, (T)p.sigma, sv, A, B, C, D, part, dsigma, dfo, lo, nullptr, s);
   } else {
-    adjoint_tail<T, false>(a, g, r, (T)p.sigma, sv, A, B, C, D, part, dsigma, static_cast<T*>(dforce),
-                           static_cast<T*>(lam_out), s);
+    adjoint_tail<T, false, false>(a, g, r, (T)p.sigma, sv, A, B, C, D, part, dsigma, dfo, lo, nullptr, s);
   }
   return hipGetLastError();
 }
 
 template <typename S>
 hipError_t rhoN_adjoint(const lbm_params& p, const Geom& g0, const void* pops, const void* lrN, void* out,
-                        hipStream_t s) {
+                        const unsigned char* solid, const unsigned char* bnc, hipStream_t s) {
   using T = typename S::math;
   const Geom g = geom_for<S>(g0);
   const dim3 grid((g.nx + 255) / 256, g.ny);
-  hipLaunchKernelGGL(adj::rhoN_adjoint_kernel<S>, grid, dim3(256), 0, s, pops, g, make_coef<S>(p),
-                     static_cast<const T*>(lrN), static_cast<T*>(out));
+  if (solid) {
+    hipLaunchKernelGGL((adj::rhoN_adjoint_kernel<S, true>), grid, dim3(256), 0, s, pops, g, make_coef<S>(p),
+                       static_cast<const T*>(lrN), static_cast<T*>(out), solid, bnc);
+  } else {
+    hipLaunchKernelGGL((adj::rhoN_adjoint_kernel<S, false>), grid, dim3(256), 0, s, pops, g, make_coef<S>(p),
+                       static_cast<const T*>(lrN), static_cast<T*>(out), nullptr, nullptr);
+  }
   return hipGetLastError();
 }
 
 template <typename S>
 hipError_t init_adjoint(const lbm_params& p, const Geom& g0, const void* rhoN0, const void* lam0, void* out,
-                        hipStream_t s) {
+                        const unsigned char* solid, hipStream_t s) {
   using T = typename S::math;
   const Geom g = geom_for<S>(g0);
   const dim3 grid((g.nx + 255) / 256, g.ny);
-  hipLaunchKernelGGL(adj::init_adjoint_kernel<T>, grid, dim3(256), 0, s, static_cast<const T*>(rhoN0),
-                     static_cast<const T*>(lam0), g, make_coef<S>(p), (T)p.rho0_R, (T)p.rho0_B,
-                     static_cast<T*>(out));
+  if (solid) {
+    hipLaunchKernelGGL((adj::init_adjoint_kernel<T, true>), grid, dim3(256), 0, s, static_cast<const T*>(rhoN0),
+                       static_cast<const T*>(lam0), g, make_coef<S>(p), (T)p.rho0_R, (T)p.rho0_B,
+                       static_cast<T*>(out), solid);
+  } else {
+    hipLaunchKernelGGL((adj::init_adjoint_kernel<T, false>), grid, dim3(256), 0, s, static_cast<const T*>(rhoN0),
+                       static_cast<const T*>(lam0), g, make_coef<S>(p), (T)p.rho0_R, (T)p.rho0_B,
+                       static_cast<T*>(out), nullptr);
+  }
   return hipGetLastError();
 }
 

@@ -46,7 +46,28 @@ def torch_pull_walls(S):
     return torch.stack(out, dim=1)[:, :, 1:ny - 1]
 
 
-def state_and_params(nx, ny, seed, stencil=(3, 3, 3, 3), **extra):
+def torch_pull_masked(S, solid, rest):
+    """Pre-collision populations of a pull-layout buffer S on a lattice with a
+    solid-site mask: C_i(r) = S_i(r - c_i), or S_opp(i)(r) when r - c_i is
+    solid.  Solid sites take the constant state ``rest`` (finite, so that the
+    oracle's arithmetic there, which nothing reads, stays finite under autograd)."""
+    m = torch.as_tensor(solid)
+    out = []
+    for i in range(9):
+        cx, cy = C[i]
+        v = torch.roll(S[:, i], shifts=(cy, cx), dims=(-2, -1))
+        src = torch.roll(m, shifts=(cy, cx), dims=(-2, -1))
+        v = torch.where(src, S[:, OPP[i]], v)
+        out.append(torch.where(m, rest[:, i], v))
+    return torch.stack(out, dim=1)
+
+
+def masked_container(nx, ny, seed):
+    m = Wk.circular_wall(nx, ny, 0.5 * min(nx, ny) - 1.0)
+    return m | Wk.random_solid_sites(nx, ny, max(3, nx * ny // 60), seed)
+
+
+def state_and_params(nx, ny, seed, stencil=(3, 3, 3, 3), solid=None, **extra):
     params = Wk.base_params(Lambda=10.0, sigma=0.02, stencil=stencil)
     params.update(gx=3e-5, gy=-2e-5, nu_B=0.4)
     params.update(extra)
@@ -63,30 +84,41 @@ def state_and_params(nx, ny, seed, stencil=(3, 3, 3, 3), **extra):
         for a in (S, lam):
             a[..., 0, :] = 0.0
             a[..., ny - 1, :] = 0.0
+    if solid is not None:        # nor do solid sites
+        S[:, :, solid] = 0.0
+        lam[:, :, solid] = 0.0
     return params, rn, S, lam, force
 
 
-def oracle_vjp(params, S, lam, force):
+def oracle_vjp(params, S, lam, force, solid=None):
     """Autograd of L = <lam, step(S)> through the oracle (FP64)."""
     ny, nx = S.shape[-2:]
-    p = O.Params(nx=nx, ny=ny, **params)
+    p = O.Params(nx=nx, ny=ny, solid=solid, **params)
     S_t = torch.tensor(S, dtype=torch.float64, requires_grad=True)
     sig = torch.tensor(float(params["sigma"]), dtype=torch.float64, requires_grad=True)
     p.sigma = sig
     F_t = None if force is None else torch.tensor(force, dtype=torch.float64, requires_grad=True)
-    P = torch_pull_walls(S_t) if p.walls else torch_pull(S_t)
+    if solid is not None:
+        rest = torch.full((2, 9, ny, nx), 0.05, dtype=torch.float64)
+        P = torch_pull_masked(S_t, solid, rest)
+    else:
+        P = torch_pull_walls(S_t) if p.walls else torch_pull(S_t)
     R, B = O.collide_and_recolour(P[0], P[1], p, force=F_t)
     lam_t = torch.tensor(lam, dtype=torch.float64)
     if p.walls:
         lam_t = lam_t[..., 1:ny - 1, :]
+    if solid is not None:        # solid sites store nothing
+        m = torch.as_tensor(solid)
+        R = torch.where(m, torch.zeros_like(R), R)
+        B = torch.where(m, torch.zeros_like(B), B)
     L = (R * lam_t[0]).sum() + (B * lam_t[1]).sum()
     L.backward()
     return S_t.grad.numpy(), float(sig.grad), None if F_t is None else F_t.grad.numpy()
 
 
-def gpu_vjp(params, rn, S, lam, force, storage="f64"):
+def gpu_vjp(params, rn, S, lam, force, storage="f64", solid=None):
     ny, nx = S.shape[-2:]
-    sim = lbm.Simulation(nx, ny, params, rn, storage=storage, device=DEV, force=force)
+    sim = lbm.Simulation(nx, ny, params, rn, storage=storage, device=DEV, force=force, solid=solid)
     T = sim.dtype
     S_d = torch.tensor(S, dtype=T, device=DEV)
     lam_d = torch.tensor(lam, dtype=T, device=DEV)
@@ -131,6 +163,31 @@ def test_adjoint_one_step_walls_f64_matches_oracle_autograd(stencil, shape):
     e = (rel(aS, gS), abs(asig - gsig) / abs(gsig), rel(aF, gF))
     print("adjoint walls f64 %s %s: pops %.2e sigma %.2e force %.2e" % (shape, stencil, *e))
     assert e[0] < 1e-11 and e[1] < 1e-10 and e[2] < 1e-11
+
+
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (1, 1, 1, 1)])
+@pytest.mark.parametrize("shape", [(14, 12), (41, 34)])
+def test_adjoint_one_step_mask_f64_matches_oracle_autograd(stencil, shape):
+    """A mask of solid sites (a staircase circle and scattered obstacles): the
+    transposed centre-value continuation of the stencils and the bounce-back."""
+    nx, ny = shape
+    solid = masked_container(nx, ny, nx)
+    params, rn, S, lam, force = state_and_params(nx, ny, seed=5 * nx + ny, stencil=stencil, solid=solid)
+    gS, gsig, gF = oracle_vjp(params, S, lam, force, solid=solid)
+    aS, asig, aF = gpu_vjp(params, rn, S, lam, force, solid=solid)
+    e = (rel(aS, gS), abs(asig - gsig) / abs(gsig), rel(aF, gF))
+    print("adjoint mask f64 %s %s: pops %.2e sigma %.2e force %.2e" % (shape, stencil, *e))
+    assert e[0] < 1e-11 and e[1] < 1e-10 and e[2] < 1e-11
+    assert np.all(aS[:, :, solid] == 0.0)
+
+
+def test_adjoint_with_mask_rejects_other_stencil_profiles():
+    nx, ny = 20, 16
+    solid = masked_container(nx, ny, 1)
+    params, rn, S, lam, force = state_and_params(nx, ny, seed=2, stencil=(3, 1, 3, 1), solid=solid)
+    with pytest.raises(lbm.LbmError) as e:
+        gpu_vjp(params, rn, S, lam, force, solid=solid)
+    assert e.value.code == lbm.LBM_ENOTIMPL
 
 
 @pytest.mark.parametrize("extra", [dict(ghost_eq=1), dict(fixed_K=0.05), dict(recolor=False)])
@@ -199,6 +256,52 @@ def test_rhoN_and_init_adjoints_match_autograd(walls):
     e2 = rel(g0.cpu().numpy(), rn_t.grad.numpy())
     sim.close()
     print("rhoN adjoint %.2e, init adjoint %.2e" % (e1, e2))
+    assert e1 < 1e-12 and e2 < 1e-12
+
+
+def test_rhoN_and_init_adjoints_with_mask_match_autograd():
+    nx, ny = 22, 18
+    solid = masked_container(nx, ny, 3)
+    m = torch.as_tensor(solid)
+    params, rn, S, lam, force = state_and_params(nx, ny, seed=6, solid=solid)
+    rng = np.random.default_rng(8)
+    w = rng.standard_normal((ny, nx))
+    w[solid] = 0.0
+    S_t = torch.tensor(S, requires_grad=True)
+    P = torch_pull_masked(S_t, solid, torch.full((2, 9, ny, nx), 0.05, dtype=torch.float64))
+    p = O.Params(nx=nx, ny=ny, **params)
+    rhoN = O.colour_index(P[0].sum(0), P[1].sum(0), p)
+    (rhoN * torch.tensor(w)).sum().backward()
+    sim = lbm.Simulation(nx, ny, params, rn, storage="f64", device=DEV, solid=solid)
+    out = torch.empty((2, 9, ny, nx), dtype=torch.float64, device=DEV)
+    sim.rhoN_adjoint(torch.tensor(S, device=DEV), torch.tensor(w, device=DEV), out)
+    torch.cuda.synchronize()
+    e1 = rel(out.cpu().numpy(), S_t.grad.numpy())
+    # the rest state after lbm_set_solid: word i at a fluid s holds link i's
+    # rest population of s + c_i, or link opp(i)'s of s itself when s + c_i is
+    # solid; solid sites hold nothing
+    rn_t = torch.tensor(rn, requires_grad=True)
+    rhoR = p.rho0_R * (1.0 + rn_t) / 2.0
+    rhoB = p.rho0_B * (1.0 - rn_t) / 2.0
+    phi = O.rest_fractions(rhoR, rhoB, p)
+    pre = torch.stack([rhoR * phi, rhoB * phi])
+    words = []
+    for i in range(9):
+        cx, cy = C[i]
+        moved = torch.roll(pre[:, i], shifts=(-cy, -cx), dims=(-2, -1))
+        dst_solid = torch.roll(m, shifts=(-cy, -cx), dims=(-2, -1))
+        v = torch.where(dst_solid, pre[:, OPP[i]], moved)
+        words.append(torch.where(m, torch.zeros_like(v), v))
+    buf = torch.stack(words, dim=1)
+    (buf * torch.tensor(lam)).sum().backward()
+    g0 = torch.zeros((ny, nx), dtype=torch.float64, device=DEV)
+    sim.init_adjoint(torch.tensor(lam, device=DEV), g0)
+    torch.cuda.synchronize()
+    grad = rn_t.grad.numpy().copy()
+    grad[solid] = 0.0
+    e2 = rel(g0.cpu().numpy(), grad)
+    sim.close()
+    print("mask: rhoN adjoint %.2e, init adjoint %.2e" % (e1, e2))
     assert e1 < 1e-12 and e2 < 1e-12
 
 
