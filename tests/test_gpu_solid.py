@@ -145,9 +145,6 @@ def test_set_solid_argument_errors():
     with pytest.raises(lbm.LbmError) as e:
         sim.set_solid(solid)            # one mask per handle
     assert e.value.code == lbm.LBM_EINVAL
-    with pytest.raises(lbm.LbmError) as e:
-        sim.adjoint_step(sim.live_pops(), sim.pops_like().zero_(), sim.pops_like())
-    assert e.value.code == lbm.LBM_ENOTIMPL
     sim.close()
     s16 = lbm.Simulation(nx, ny, params, rn, storage="f16", device=DEV)
     with pytest.raises(lbm.LbmError) as e:
