@@ -9,6 +9,10 @@
   1e-13 of the largest population, FP32 to 2e-6;
 * a drop beside obstacles in a circular container for 300 steps: FP64 fields
   to 1e-11, masses conserved;
+* the fused step kernel's mask variant against the four passes, bit for bit;
+* the benchmark's masked workload at full size (4096^2, FP32): sampled sites
+  against the oracle on windows (measured 1.3e-7), the whole lattice against
+  the four passes;
 * argument errors of the entry point.
 """
 import numpy as np
@@ -193,3 +197,55 @@ def test_fused_masked_step_equals_four_passes(storage, stencil, shape):
     d = float(np.max(np.abs(out[0] - out[1])))
     print("fused vs four passes %s %s %s: max |diff| %.3e" % (shape, storage, stencil, d))
     assert np.array_equal(out[0], out[1]), d
+
+
+def test_full_size_masked_emulsion_sampled_sites():
+    """The benchmark lattice inside a circular wall (the bench's masked leg):
+    4096^2 emulsion, FP32, solid outside r = 2046.  After 20 steps, one step of
+    the fused mask variant at sampled sites (beside the wall, on drop
+    interfaces, anywhere) against the oracle on windows of the state, and the
+    whole lattice against the four-pass kernels, bit for bit."""
+    cfg = Wk.config_emulsion()
+    n = cfg["nx"]
+    params = cfg["params"]
+    solid = Wk.circular_wall(n, n, n / 2.0 - 2.0)
+    sims = [lbm.Simulation(n, n, params, cfg["rhoN0"], storage="f32", device=DEV, solid=solid, flags=f)
+            for f in (0, lbm.LBM_FLAG_MASK_PASSES)]
+    for sim in sims:
+        sim.step(20)
+    before = sims[0].live_pops().clone()
+    for sim in sims:
+        sim.step(1)
+    after = sims[0].live_pops()
+    assert torch.equal(after, sims[1].live_pops())
+    rng = np.random.default_rng(321)
+    fl = ~solid
+    yy, xx = np.mgrid[0:n, 0:n]
+    r = np.hypot(xx - (n - 1) / 2.0, yy - (n - 1) / 2.0)
+    near_wall = np.argwhere(fl & (r > n / 2.0 - 6.0))
+    rn = cfg["rhoN0"]
+    edge = np.argwhere(fl & (np.abs(np.roll(rn, 1, 0) - rn) + np.abs(np.roll(rn, 1, 1) - rn) > 0))
+    anywhere = np.argwhere(fl)
+    picks = [tuple(near_wall[k]) for k in rng.choice(len(near_wall), 8, replace=False)]
+    picks += [tuple(edge[k]) for k in rng.choice(len(edge), 6, replace=False)]
+    picks += [tuple(anywhere[k]) for k in rng.choice(len(anywhere), 4, replace=False)]
+    half = 16
+    worst = 0.0
+    m_dev = torch.as_tensor(solid, device=DEV)
+    for (y, x) in picks:
+        ys = torch.arange(y - half, y + half + 1, device=DEV) % n
+        xs = torch.arange(x - half, x + half + 1, device=DEV) % n
+        S = before[:, :, ys][:, :, :, xs].double().cpu().numpy()
+        msk = m_dev[ys][:, xs].cpu().numpy()
+        w = 2 * half + 1
+        o = O.Oracle(oracle_params(w, w, dict(params, solid=msk)))
+        P = pull_gather_masked(S, msk)
+        o.set_state(torch.from_numpy(P[0]), torch.from_numpy(P[1]))
+        R, B = o.post_collision()
+        ref = np.stack([R.numpy(), B.numpy()])[:, :, half, half]
+        got = after[:, :, y, x].double().cpu().numpy()
+        worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
+    print("masked emulsion 4096^2 sampled sites: max rel err %.3e" % worst)
+    assert worst < 2e-5
+    for sim in sims:
+        sim.close()
