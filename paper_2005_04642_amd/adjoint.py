@@ -22,9 +22,10 @@ class _Rollout(torch.autograd.Function):
     def forward(ctx, rhoN0, sigma, force, params, nsteps, checkpoint, storage, device):
         p = dict(params)
         p["sigma"] = float(sigma)
+        solid = p.pop("solid", None)
         ny, nx = rhoN0.shape
         sim = lbm.Simulation(nx, ny, p, rhoN0.detach(), storage=storage, device=device,
-                             force=None if force is None else force.detach())
+                             force=None if force is None else force.detach(), solid=solid)
         # Every checkpointed state (and the final one) gets a buffer of its own,
         # written directly by the step that produces it (lbm_set_pops); the steps
         # in between alternate between two scratch buffers.  No state is copied
@@ -104,7 +105,13 @@ class _Rollout(torch.autograd.Function):
 def rollout(rhoN0, sigma, force, params, nsteps, checkpoint=100, storage="f32", device="cuda:0"):
     """rho^N after ``nsteps`` steps from the rest state of ``rhoN0`` ([ny, nx]);
     differentiable with respect to rhoN0, sigma (0-dim tensor) and force
-    ([2, ny, nx] tensor or None)."""
+    ([2, ny, nx] tensor or None).
+
+    Device memory: ceil(nsteps / checkpoint) + 3 population states are held
+    from the forward pass to the end of the backward one (checkpoint = 1 keeps
+    every state and recomputes nothing), plus ``checkpoint`` states during the
+    backward recompute of one segment.  ``params`` may hold ``solid``, a mask of
+    solid sites ([ny, nx]; F64/F32 storage, stencil profiles 3333 and 1111)."""
     if not torch.is_tensor(sigma):
         sigma = torch.tensor(float(sigma), dtype=torch.float64)
     return _Rollout.apply(rhoN0, sigma, force, params, int(nsteps), int(checkpoint), storage, device)
