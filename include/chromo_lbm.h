@@ -285,7 +285,10 @@ size_t lbm_solid_workspace_bytes(const lbm_params* p);
  * pre-collision populations it had (the words its links now bounce into take
  * the values those links pulled before), and zeroes the words of solid sites;
  * call it on the state to start from (usually right after lbm_init).  From
- * then on lbm_step and lbm_fields use the mask.  A handle takes one mask:
+ * then on lbm_step and lbm_fields use the mask.  Every state the handle
+ * steps from (lbm_set_pops buffers, lbm_adjoint_step's pops_t) must hold zero
+ * words at solid sites, as the re-encoded buffer and every step's output do:
+ * the fused kernel recognises solid sites by their zero mass.  A handle takes one mask:
  * LBM_EINVAL if it has one already, for NULL pointers, a small workspace,
  * walls_y = 1 or nx, ny < 4; LBM_ENOTIMPL for the 16-bit formats and the
  * streaming-only mode.  The adjoint entry points work on such a handle for
