@@ -200,8 +200,8 @@ int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, vo
 
 /* ---- batches: many independent periodic lattices, one launch per step ------
  * All lattices of a batch share the storage format and the stencil radii; each
- * has its own size and physical parameters (lbm_params), and none has walls or
- * a force field.  Their population buffers are packed one after the other (each
+ * has its own size and physical parameters (lbm_params) and, optionally, its
+ * own per-site force field (lbm_batch_set_force); none has walls or a mask.  Their population buffers are packed one after the other (each
  * at a 256-byte aligned offset, lbm_batch_offsets) in two caller-owned buffers
  * of lbm_batch_pops_bytes() bytes.  Every lbm_batch_step is one launch of a
  * persistent-style kernel: each workgroup owns a bin of (lattice, tile) work
@@ -240,6 +240,13 @@ int lbm_batch_step(lbm_batch* b, int32_t nsteps, hipStream_t stream);
  * Synchronises the stream. */
 int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_t steps_per_trial,
                        hipStream_t stream, int32_t* chosen);
+
+/* Give lattice k a per-site force density G_ext (device [2][ny_k][nx_k],
+ * arithmetic type, as in lbm_init; caller-owned, kept valid while the batch
+ * steps), or remove it (NULL).  Updates the lattice's entry of the batch's
+ * device table and waits for that copy on `stream`.  LBM_EINVAL for a bad
+ * batch or index. */
+int lbm_batch_set_force(lbm_batch* b, int32_t k, const void* force, hipStream_t stream);
 
 /* info[5]: workgroup width, chunk-height cap, number of bins, number of work
  * items, largest bin cost in march iterations. */

@@ -469,7 +469,7 @@ struct BatchPlan {
 // Longest-processing-time-first assignment of the tiles of every lattice to
 // nbins bins (one workgroup each), costs counted in march iterations.
 BatchPlan batch_plan(const lbm_params* p, int nsim, const std::vector<size_t>& off, int nbins, int ntx, int tycap,
-                     const chromo::Ops& ops, int nr, int it0) {
+                     const chromo::Ops& ops, int nr, int it0, const std::vector<const void*>& force) {
   BatchPlan b;
   b.ntx = ntx;
   b.tycap = tycap;
@@ -482,7 +482,7 @@ BatchPlan batch_plan(const lbm_params* p, int nsim, const std::vector<size_t>& o
   std::vector<Tile> tiles;
   for (int k = 0; k < nsim; ++k) {
     const chromo::Geom g = batch_geom(p[k], ntx, tycap);
-    ops.sim_desc(p[k], g, (unsigned long long)off[k], &b.sims[(size_t)k * ops.sim_desc_bytes]);
+    ops.sim_desc(p[k], g, (unsigned long long)off[k], force[k], &b.sims[(size_t)k * ops.sim_desc_bytes]);
     for (int t = 0; t < g.nstrips * g.nchunks; ++t) {
       const int chunk = t / g.nstrips;
       const int rows = std::min(g.TY, g.F - chunk * g.TY);
@@ -519,6 +519,7 @@ struct lbm_batch {
   int nsim;
   std::vector<lbm_params> p;
   std::vector<size_t> off;
+  std::vector<const void*> force;  // per-lattice force fields (lbm_batch_set_force), or null
   char* pops[2];
   int live;
   int64_t steps;
@@ -625,6 +626,7 @@ int lbm_batch_init(const lbm_params* p, int nsim, const void* const* rhoN0, void
   if (!b) return fail(LBM_EINVAL, "out of host memory");
   b->nsim = nsim;
   b->p.assign(p, p + nsim);
+  b->force.assign(nsim, nullptr);
   batch_offsets(p, nsim, &b->off);
   b->pops[0] = static_cast<char*>(pops_a);
   b->pops[1] = static_cast<char*>(pops_b);
@@ -665,7 +667,7 @@ int lbm_batch_init(const lbm_params* p, int nsim, const void* const* rhoN0, void
   const int it0 = 3 * ((nr * ((3 + nr - 1) / nr) + 3 + nr - 1) / nr);
   int ntx0 = b->ops->batch_ntx[0];
   for (int i = 1; i < 3 && b->ops->batch_ntx[i]; ++i) ntx0 = std::max(ntx0, b->ops->batch_ntx[i]);
-  st = batch_upload(b, batch_plan(p, nsim, b->off, ncu, ntx0, 128, *b->ops, nr, it0), stream);
+  st = batch_upload(b, batch_plan(p, nsim, b->off, ncu, ntx0, 128, *b->ops, nr, it0, b->force), stream);
   if (st != LBM_OK) {
     delete b;
     return st;
@@ -702,7 +704,7 @@ int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_
   for (int i = 0; i < 3 && b->ops->batch_ntx[i] && st == LBM_OK; ++i) {
     for (int tc : BATCH_TYCAPS) {
       st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, b->ops->batch_ntx[i], tc, *b->ops, nr,
-                                      it0),
+                                      it0, b->force),
                         stream);
       if (st != LBM_OK) break;
       if (hipMemcpyAsync(b->pops[live0], scratch, total, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
@@ -736,13 +738,27 @@ int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_
   b->live = live0;
   b->steps = steps0;
   if (st != LBM_OK) return st;
-  st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, best_ntx, best_tycap, *b->ops, nr, it0),
+  st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, best_ntx, best_tycap, *b->ops, nr, it0, b->force),
                     stream);
   if (st != LBM_OK) return st;
   if (chosen) {
     chosen[0] = best_ntx;
     chosen[1] = best_tycap;
   }
+  return LBM_OK;
+}
+
+int lbm_batch_set_force(lbm_batch* b, int32_t k, const void* force, hipStream_t stream) {
+  g_last_error.clear();
+  if (!b || k < 0 || k >= b->nsim) return fail(LBM_EINVAL, "bad batch or lattice index");
+  b->force[k] = force;
+  b->view[k].force = force;
+  const chromo::Geom g = batch_geom(b->p[k], b->plan.ntx, b->plan.tycap);
+  unsigned char* desc = &b->plan.sims[(size_t)k * b->ops->sim_desc_bytes];
+  b->ops->sim_desc(b->p[k], g, (unsigned long long)b->off[k], force, desc);
+  HIP_TRY(hipMemcpyAsync(static_cast<char*>(b->d_sims) + (size_t)k * b->ops->sim_desc_bytes, desc,
+                         b->ops->sim_desc_bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));  // the host copy may change with the next plan
   return LBM_OK;
 }
 

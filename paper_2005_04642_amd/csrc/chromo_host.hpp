@@ -63,8 +63,9 @@ struct Ops {
   // batched periodic step: ntx in batch_ntx (0-terminated); tables in device memory
   hipError_t (*batch)(int ntx, const int* radii, const void* src, void* dst, const void* sims, const int* bin_start,
                       const int* items, int nbins, hipStream_t s);
-  // one SimDesc<math> of lattice p with tile plan g and byte offset off, written to out
-  void (*sim_desc)(const lbm_params& p, const Geom& g, unsigned long long off, void* out);
+  // one SimDesc<math> of lattice p with tile plan g, byte offset off and force
+  // field (device [2][ny][nx] or null), written to out
+  void (*sim_desc)(const lbm_params& p, const Geom& g, unsigned long long off, const void* force, void* out);
   int sim_desc_bytes;
   int batch_ntx[3];
   int words;        // words per site

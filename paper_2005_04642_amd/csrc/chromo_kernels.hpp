@@ -883,6 +883,7 @@ struct SimDesc {
   Geom g;                 // per-lattice geometry and tile plan
   Coef<T> c;              // per-lattice constants
   unsigned long long off; // byte offset of the lattice's populations in both packed buffers
+  const T* force;         // per-site force density [2][ny][nx] of the lattice, or null
 };
 
 template <typename T>
@@ -906,9 +907,10 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_batch_kernel(BatchArgs<typ
     StepArgs<T> a;
     a.src = b.src + b.sims[sim].off;
     a.dst = b.dst + b.sims[sim].off;
-    a.force = nullptr;
+    a.force = b.sims[sim].force;
     a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = a.out_save = a.out_adj = nullptr;
     a.lam_next = nullptr;
+    a.bnc = nullptr;
     a.g = b.sims[sim].g;
     a.c = b.sims[sim].c;
     march_tile<ST, NTX, NR, RG, RK, RP, RU, false, MODE_STEP>(a, tile, sm);

@@ -347,11 +347,12 @@ hipError_t batch(int ntx, const int* radii, const void* src, void* dst, const vo
 }
 
 template <typename S>
-void sim_desc(const lbm_params& p, const Geom& g, unsigned long long off, void* out) {
+void sim_desc(const lbm_params& p, const Geom& g, unsigned long long off, const void* force, void* out) {
   SimDesc<typename S::math> d;
   d.g = geom_for<S>(g);
   d.c = make_coef<S>(p);
   d.off = off;
+  d.force = static_cast<const typename S::math*>(force);
   memcpy(out, &d, sizeof(d));
 }
 

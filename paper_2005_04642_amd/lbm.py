@@ -28,7 +28,8 @@ EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_work
             "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_solid_workspace_bytes", "lbm_set_solid",
             "lbm_current_pops", "lbm_set_pops", "lbm_step_count",
             "lbm_destroy", "lbm_last_error", "lbm_batch_pops_bytes", "lbm_batch_offsets", "lbm_batch_workspace_bytes",
-            "lbm_batch_init", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_plan_info", "lbm_batch_fields",
+            "lbm_batch_init", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_set_force", "lbm_batch_plan_info",
+            "lbm_batch_fields",
             "lbm_batch_masses_host", "lbm_batch_current_pops", "lbm_batch_step_count", "lbm_batch_destroy")
 
 
@@ -116,6 +117,8 @@ def load_library(path=None):
     lib.lbm_batch_step.restype = ctypes.c_int
     lib.lbm_batch_autotune.argtypes = [vp, vp, sz, i32, vp, i32p]
     lib.lbm_batch_autotune.restype = ctypes.c_int
+    lib.lbm_batch_set_force.argtypes = [vp, i32, vp, vp]
+    lib.lbm_batch_set_force.restype = ctypes.c_int
     lib.lbm_batch_plan_info.argtypes = [vp, i32p]
     lib.lbm_batch_plan_info.restype = ctypes.c_int
     lib.lbm_batch_fields.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -515,6 +518,22 @@ class Batch:
         _check(self.lib, self.lib.lbm_batch_autotune(self.h, scratch.data_ptr(), scratch.numel(),
                                                      int(steps_per_trial), self.stream(), chosen))
         return chosen[0], chosen[1]
+
+    def set_force(self, k, force):
+        """Per-site force density of lattice k ([2, ny, nx], or None to remove it)."""
+        t = None
+        if force is not None:
+            t = force if self.torch.is_tensor(force) else self.torch.as_tensor(np.asarray(force))
+            t = t.to(device=self.device, dtype=self.dtype).contiguous()
+            nx, ny = self.shapes[k]
+            if tuple(t.shape) != (2, ny, nx):
+                raise ValueError("force of lattice %d must have shape (2, %d, %d)" % (k, ny, nx))
+        if not hasattr(self, "_forces"):
+            self._forces = {}
+        _check(self.lib, self.lib.lbm_batch_set_force(self.h, int(k), None if t is None else t.data_ptr(),
+                                                      self.stream()))
+        self._forces[k] = t          # kept alive while the batch uses it
+        return self
 
     def plan_info(self):
         info = (ctypes.c_int32 * 5)()

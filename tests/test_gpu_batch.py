@@ -86,3 +86,34 @@ def test_batch_of_the_benchmark_workload_runs():
         m = b.masses(k)
         assert np.isfinite(m).all()
     b.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_batch_with_force_fields_matches_single_lattices(storage):
+    """Per-lattice force fields (lbm_batch_set_force) on some lattices of the
+    batch, set before and changed after the autotuner: each lattice evolves as
+    a single Simulation with the same force, bit for bit."""
+    lats = lattices()
+    forces = {k: Wk.gaussian_bumps(nx, ny, nbumps=2, width=max(3.0, min(nx, ny) / 6.0), amplitude=2e-5, seed=k)
+              for k, (nx, ny, _, _) in enumerate(lats) if k in (1, 2, 4)}
+    b = lbm.Batch(lats, storage=storage, device=DEV)
+    for k, f in forces.items():
+        b.set_force(k, f)
+    b.step(6)
+    b.autotune(steps_per_trial=2)
+    b.set_force(2, None)            # lattice 2 runs on without its force
+    b.step(6)
+    for k, (nx, ny, prm, rn) in enumerate(lats):
+        s = lbm.Simulation(nx, ny, prm, rn, storage=storage, device=DEV, force=forces.get(k))
+        s.step(6)
+        if k == 2:
+            # continue without the force from the same state
+            state = s.live_pops().clone()
+            s.close()
+            s = lbm.Simulation(nx, ny, prm, rn, storage=storage, device=DEV)
+            s.live_pops().copy_(state)
+        s.step(6)
+        torch.cuda.synchronize()
+        assert torch.equal(b.state(k), s.live_pops()), k
+        s.close()
+    b.close()
