@@ -201,7 +201,10 @@ int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, vo
 /* ---- batches: many independent periodic lattices, one launch per step ------
  * All lattices of a batch share the storage format and the stencil radii; each
  * has its own size and physical parameters (lbm_params) and, optionally, its
- * own per-site force field (lbm_batch_set_force); none has walls or a mask.  Their population buffers are packed one after the other (each
+ * own per-site force field (lbm_batch_set_force).  A batch is all periodic or
+ * all walled (walls_y; walled batches are built for the stencil profiles
+ * (3,3,3,3) and (1,1,1,1), LBM_ENOTIMPL for the others); no lattice of a batch
+ * has a solid-site mask.  Their population buffers are packed one after the other (each
  * at a 256-byte aligned offset, lbm_batch_offsets) in two caller-owned buffers
  * of lbm_batch_pops_bytes() bytes.  Every lbm_batch_step is one launch of a
  * persistent-style kernel: each workgroup owns a bin of (lattice, tile) work

@@ -415,11 +415,18 @@ int batch_validate(const lbm_params* p, int nsim) {
   for (int k = 0; k < nsim; ++k) {
     const int st = validate(&p[k]);
     if (st != LBM_OK) return fail(st, "lattice %d: %s", k, g_last_error.c_str());
-    if (p[k].walls_y) return fail(LBM_ENOTIMPL, "lattice %d: batches hold periodic lattices only", k);
+    if (p[k].walls_y != p[0].walls_y)
+      return fail(LBM_EINVAL, "lattice %d: walls differ from lattice 0 (a batch is all periodic or all walled)", k);
     if (p[k].flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_EINVAL, "lattice %d: no stream-only mode in batches", k);
     if (p[k].storage != p[0].storage) return fail(LBM_EINVAL, "lattice %d: storage differs from lattice 0", k);
     for (int r = 0; r < 4; ++r)
       if (p[k].stencil[r] != p[0].stencil[r]) return fail(LBM_EINVAL, "lattice %d: stencil radii differ", k);
+  }
+  if (p[0].walls_y) {
+    const int* r = p[0].stencil;
+    const bool all3 = r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3;
+    const bool all1 = r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1;
+    if (!all3 && !all1) return fail(LBM_ENOTIMPL, "batches of walled lattices are built for stencils 3333 and 1111");
   }
   return LBM_OK;
 }
@@ -429,8 +436,8 @@ chromo::Geom batch_geom(const lbm_params& p, int ntx, int tycap) {
   chromo::Geom g;
   g.nx = p.nx;
   g.ny = p.ny;
-  g.walls = 0;
-  g.F = p.ny;
+  g.walls = p.walls_y;
+  g.F = p.walls_y ? p.ny - 2 : p.ny;
   g.plane = p.nx * p.ny;
   const int txmax = ntx - 2 * halo(p);
   g.nstrips = (p.nx + txmax - 1) / txmax;
@@ -553,7 +560,8 @@ int batch_upload(lbm_batch* b, BatchPlan&& pl, hipStream_t s) {
 
 int batch_step_impl(lbm_batch* b, int nsteps, hipStream_t s) {
   for (int k = 0; k < nsteps; ++k) {
-    hipError_t e = b->ops->batch(b->plan.ntx, b->p[0].stencil, b->pops[b->live], b->pops[1 - b->live], b->d_sims,
+    hipError_t e = b->ops->batch(b->plan.ntx, b->p[0].stencil, b->p[0].walls_y, b->pops[b->live],
+                                 b->pops[1 - b->live], b->d_sims,
                                  b->d_bin_start, b->d_items, b->plan.nbins, s);
     if (e != hipSuccess) return fail(LBM_EHIP, "batch step launch: %s", hipGetErrorString(e));
     b->live = 1 - b->live;

@@ -61,8 +61,8 @@ struct Ops {
                              const unsigned char* mask, void* ws, void* rho, void* ux, void* uy, void* rhoN,
                              hipStream_t s);
   // batched periodic step: ntx in batch_ntx (0-terminated); tables in device memory
-  hipError_t (*batch)(int ntx, const int* radii, const void* src, void* dst, const void* sims, const int* bin_start,
-                      const int* items, int nbins, hipStream_t s);
+  hipError_t (*batch)(int ntx, const int* radii, int walls, const void* src, void* dst, const void* sims,
+                      const int* bin_start, const int* items, int nbins, hipStream_t s);
   // one SimDesc<math> of lattice p with tile plan g, byte offset off and force
   // field (device [2][ny][nx] or null), written to out
   void (*sim_desc)(const lbm_params& p, const Geom& g, unsigned long long off, const void* force, void* out);

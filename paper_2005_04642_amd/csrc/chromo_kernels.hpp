@@ -895,7 +895,7 @@ struct BatchArgs {
   const int* items;             // pairs (lattice, tile)
 };
 
-template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU>
+template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS = false>
 __global__ void __launch_bounds__(NTX * NR, 1) chromo_batch_kernel(BatchArgs<typename ST::math> b) {
   using T = typename ST::math;
   using PP = Pipe<NR>;
@@ -913,7 +913,7 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_batch_kernel(BatchArgs<typ
     a.bnc = nullptr;
     a.g = b.sims[sim].g;
     a.c = b.sims[sim].c;
-    march_tile<ST, NTX, NR, RG, RK, RP, RU, false, MODE_STEP>(a, tile, sm);
+    march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE_STEP>(a, tile, sm);
     __syncthreads();  // the next tile reuses the LDS rings
   }
 }

@@ -12,12 +12,13 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-def lattices():
+def lattices(walls=False):
     rng = np.random.default_rng(0)
     out = []
     for (nx, ny, Lam, sigma) in [(5, 7, 10.0, 0.005), (64, 64, 1.0, 0.001), (100, 60, 100.0, 0.01),
                                  (130, 40, 10.0, 0.01), (200, 200, 10.0, 0.005), (37, 300, 2.0, 0.02)]:
         prm = Wk.base_params(Lambda=Lam, sigma=sigma)
+        prm["walls"] = walls
         y, x = np.mgrid[0:ny, 0:nx]
         d = np.hypot((x - (nx - 1) / 2.0) / 1.15, (y - (ny - 1) / 2.0) * 1.15)
         rn = 0.3 * np.tanh(rng.standard_normal((ny, nx))) if nx < 10 else np.tanh((min(nx, ny) / 4.0 - d) / 2.0)
@@ -115,5 +116,33 @@ def test_batch_with_force_fields_matches_single_lattices(storage):
         s.step(6)
         torch.cuda.synchronize()
         assert torch.equal(b.state(k), s.live_pops()), k
+        s.close()
+    b.close()
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
+def test_batch_of_walled_lattices_matches_single_lattices(storage):
+    """A batch of walled lattices (rows 0 and ny-1 solid), with a force field
+    on one of them: each evolves as it does alone, bit for bit, before and
+    after the autotuner."""
+    lats = lattices(walls=True)
+    b = lbm.Batch(lats, storage=storage, device=DEV)
+    nx3, ny3 = lats[3][0], lats[3][1]
+    f3 = Wk.gaussian_bumps(nx3, ny3, nbumps=2, width=6.0, amplitude=2e-5, seed=3)
+    b.set_force(3, f3)
+    b.step(6)
+    b.autotune(steps_per_trial=2)
+    b.step(6)
+    for k, (nx, ny, prm, rn) in enumerate(lats):
+        s = lbm.Simulation(nx, ny, prm, rn, storage=storage, device=DEV, force=f3 if k == 3 else None)
+        s.step(12)
+        torch.cuda.synchronize()
+        got = b.pops[b.lib.lbm_batch_current_pops(b.h)]
+        words = lbm.WORDS_PER_SITE[storage] * nx * ny
+        esz = 8 if storage == "f64" else 4
+        raw = s.pops[lbm.lbm_current_pops(s.h)].cpu().numpy().reshape(-1).view(np.uint8)
+        assert np.array_equal(got[b.offsets[k]:b.offsets[k] + words * esz].cpu().numpy(), raw), k
+        m = b.masses(k)
+        assert m == s.masses(), k
         s.close()
     b.close()
