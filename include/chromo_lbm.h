@@ -198,7 +198,7 @@ int lbm_rhoN_adjoint(lbm_handle* h, const void* pops, const void* dL_drhoN, void
  * colour index rhoN0, given adj_pops0 = dL/d(initial populations). */
 int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, void* dL_drhoN0, hipStream_t stream);
 
-/* ---- batches: many independent periodic lattices, one launch per step ------
+/* ---- batches: many independent lattices, one launch per step ---------------
  * All lattices of a batch share the storage format and the stencil radii; each
  * has its own size and physical parameters (lbm_params) and, optionally, its
  * own per-site force field (lbm_batch_set_force).  A batch is all periodic or

@@ -390,7 +390,7 @@ const char* lbm_last_error(void) { return g_last_error.c_str(); }
 }  // extern "C"
 
 // ===========================================================================
-// Batches of independent periodic lattices stepped by one launch
+// Batches of independent lattices (all periodic or all walled) stepped by one launch
 // ===========================================================================
 namespace {
 

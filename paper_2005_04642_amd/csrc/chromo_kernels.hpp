@@ -874,7 +874,7 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_step_kernel(StepArgs<typen
 }
 
 // ---------------------------------------------------------------------------
-// Batched step: many independent periodic lattices in one launch.  Each
+// Batched step: many independent lattices in one launch.  Each
 // workgroup owns a bin of work items (lattice, tile), planned on the host so
 // that the bins' costs are balanced, and runs them one after the other.
 // ---------------------------------------------------------------------------

@@ -447,7 +447,7 @@ class Simulation:
 
 
 # ---------------------------------------------------------------------------
-# batches of independent periodic lattices
+# batches of independent lattices
 # ---------------------------------------------------------------------------
 
 def lbm_batch_pops_bytes(plist):
@@ -469,7 +469,8 @@ def lbm_batch_workspace_bytes(plist):
 
 
 class Batch:
-    """Independent periodic lattices stepped together by one launch per step.
+    """Independent lattices (all periodic or all walled) stepped together by one
+    launch per step.
 
     lattices: list of (nx, ny, params, rhoN0); every lattice shares the
     storage format and the stencil radii.  ``state(k)`` is a view of lattice
