@@ -269,14 +269,15 @@ void lbm_batch_destroy(lbm_batch* b);
 /* ---- solid sites anywhere (a mask) -----------------------------------------
  * For obstacles that are not whole rows, such as the staircase circular
  * no-slip wall of the curved-interface transient (Sec. IV, dynamics of curved
- * interfaces; App. D).  Provided for LBM_STORAGE_F64 and LBM_STORAGE_F32 on a
- * handle with walls_y = 0 (put wall rows in the mask instead); both x and y
+ * interfaces; App. D).  Provided for every storage format on a handle with
+ * walls_y = 0 (put wall rows in the mask instead); both x and y
  * are periodic around the mask.  A link whose target is solid is bounced back
  * half-way (as at the walls); an App. B stencil tap that falls on a solid site
  * reads the field's value at the stencil's centre (a zero-gradient
  * continuation of every field into the solid; the paper gives no rule for
- * stencils at a curved wall).  Solid sites hold zero in the population buffers,
- * carry no mass, and read as NaN from lbm_fields.  For the stencil profiles
+ * stencils at a curved wall).  Solid sites hold zero populations (all-zero
+ * words in F64/F32, the offset encoding of zero in the 16-bit formats), carry
+ * no mass, and read as NaN from lbm_fields.  For the stencil profiles
  * (3,3,3,3) and (1,1,1,1) the step is one launch of the fused step kernel in
  * its mask variant (per-site bounce bits, NaN markers for stencil taps); for
  * the other profiles, or with LBM_FLAG_MASK_PASSES, four launches over
@@ -297,11 +298,10 @@ size_t lbm_solid_workspace_bytes(const lbm_params* p);
  * call it on the state to start from (usually right after lbm_init).  From
  * then on lbm_step and lbm_fields use the mask.  Every state the handle
  * steps from (lbm_set_pops buffers, lbm_adjoint_step's pops_t) must hold zero
- * words at solid sites, as the re-encoded buffer and every step's output do:
+ * populations at solid sites, as the re-encoded buffer and every step's output do:
  * the fused kernel recognises solid sites by their zero mass.  A handle takes one mask:
  * LBM_EINVAL if it has one already, for NULL pointers, a small workspace,
- * walls_y = 1 or nx, ny < 4; LBM_ENOTIMPL for the 16-bit formats and the
- * streaming-only mode.  The adjoint entry points work on such a handle for
+ * walls_y = 1 or nx, ny < 4; LBM_ENOTIMPL for the streaming-only mode.  The adjoint entry points work on such a handle for
  * the stencil profiles (3,3,3,3) and (1,1,1,1) (LBM_ENOTIMPL for the others);
  * lbm_init_adjoint then differentiates the rest state as lbm_set_solid
  * re-encoded it. */

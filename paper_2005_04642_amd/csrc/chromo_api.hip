@@ -355,14 +355,13 @@ int lbm_set_solid(lbm_handle* h, const uint8_t* solid_dev, void* workspace, size
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   if (!solid_dev || !workspace) return fail(LBM_EINVAL, "solid mask and workspace must be non-NULL");
   if (h->solid) return fail(LBM_EINVAL, "the handle already has a solid-site mask");
-  if (!h->ops->solid_step) return fail(LBM_ENOTIMPL, "solid-site masks are provided for F64 and F32 storage only");
   if (h->p.walls_y) return fail(LBM_EINVAL, "with a solid-site mask walls_y must be 0 (put the wall rows in the mask)");
   if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no solid-site mask in the streaming-only test mode");
   if (h->p.nx < 4 || h->p.ny < 4) return fail(LBM_EINVAL, "a solid-site mask needs nx, ny >= 4");
   const size_t need = lbm_solid_workspace_bytes(&h->p);
   if (ws_bytes < need) return fail(LBM_EINVAL, "solid workspace too small: %zu < %zu", ws_bytes, need);
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
-  hipError_t e = h->ops->solid_prepare(h->g, h->pops[h->live], solid_dev, workspace, stream);
+  hipError_t e = h->ops->solid_prepare(h->p, h->g, h->pops[h->live], solid_dev, workspace, stream);
   if (e != hipSuccess) return fail(LBM_EHIP, "solid mask launch: %s", hipGetErrorString(e));
   h->solid = solid_dev;
   h->solid_ws = workspace;

@@ -48,9 +48,10 @@ struct Ops {
                              const unsigned char* solid, const unsigned char* bnc, hipStream_t s);
   hipError_t (*init_adjoint)(const lbm_params& p, const Geom& g, const void* rhoN0, const void* lam0, void* out,
                              const unsigned char* solid, hipStream_t s);
-  // solid sites anywhere (F64/F32; null for the others).  mask: device
-  // [ny][nx] bytes, nonzero = solid; ws: solid::P_N planes of the arithmetic type
-  hipError_t (*solid_prepare)(const Geom& g, void* pops, const unsigned char* mask, void* ws, hipStream_t s);
+  // solid sites anywhere (every format).  mask: device [ny][nx] bytes, nonzero
+  // = solid; ws: solid::P_N planes of the arithmetic type, then the bounce bits
+  hipError_t (*solid_prepare)(const lbm_params& p, const Geom& g, void* pops, const unsigned char* mask, void* ws,
+                              hipStream_t s);
   // the fused step kernel with the mask (hipErrorNotSupported for stencil
   // profiles it is not built for)
   hipError_t (*solid_fused)(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force,

@@ -525,7 +525,8 @@ __device__ __forceinline__ float rsqrt_pos(float x) {
 __device__ __forceinline__ double rsqrt_pos(double x) { return 1.0 / sqrt(x); }
 
 // Collision, recolour and store of one site (band O).
-// MASK: a site without mass (a solid site, whose words are all zero) stores zeros.
+// MASK: a site without mass (a solid site, whose words encode zero populations)
+// stores zero populations.
 template <typename S, typename T, int MODE, bool MASK = false>
 __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buffer_rsrc_t dst, const T* f, T rR,
                                               T rB, T ux, T uy, T Gx, T Gy, T inv_rho, T dPx, T dPy, T theta,
@@ -646,14 +647,14 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
   R[6] = aR * fp[6] - t2; B[6] = aB * fp[6] + t2;
   R[8] = aR * fp[8] + t8; B[8] = aB * fp[8] - t8;
   R[4] = aR * fp[4] - t8; B[4] = aB * fp[4] + t8;
-  typename S::W w[S::NW];
-  encode<S>(R, B, c, w);
   if constexpr (MASK) {
-    if (rho == T(0)) {
+    if (rho == T(0)) {  // a solid site keeps the encoding of zero populations
 #pragma unroll
-      for (int q = 0; q < S::NW; ++q) w[q] = typename S::W(0);
+      for (int i = 0; i < 9; ++i) R[i] = B[i] = T(0);
     }
   }
+  typename S::W w[S::NW];
+  encode<S>(R, B, c, w);
   const unsigned ro = (unsigned)p * a.g.rb;
 #pragma unroll
   for (int q = 0; q < S::NW; ++q) store_word<typename S::W>(w[q], dst, t.cols.o, (int)(q * a.g.pb + ro));

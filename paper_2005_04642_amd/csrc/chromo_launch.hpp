@@ -370,11 +370,12 @@ void sim_desc(const lbm_params& p, const Geom& g, unsigned long long off, const 
 // field planes of ws
 // ---------------------------------------------------------------------------
 template <typename S>
-hipError_t solid_prepare(const Geom& g0, void* pops, const unsigned char* mask, void* ws, hipStream_t s) {
+hipError_t solid_prepare(const lbm_params& p, const Geom& g0, void* pops, const unsigned char* mask, void* ws,
+                         hipStream_t s) {
   const Geom g = geom_for<S>(g0);
   const dim3 grid((g.nx + 255) / 256, g.ny);
   hipLaunchKernelGGL(solid::rebounce_kernel<S>, grid, dim3(256), 0, s, pops, mask, g);
-  hipLaunchKernelGGL(solid::clear_solid_kernel<S>, grid, dim3(256), 0, s, pops, mask, g);
+  hipLaunchKernelGGL(solid::clear_solid_kernel<S>, grid, dim3(256), 0, s, pops, mask, g, make_coef<S>(p));
   unsigned char* bits = static_cast<unsigned char*>(ws) + solid::bits_offset(g.plane, sizeof(typename S::math));
   hipLaunchKernelGGL(solid::bounce_bits_kernel<S>, grid, dim3(256), 0, s, mask, g, bits);
   return hipGetLastError();
@@ -477,19 +478,15 @@ Ops make_ops() {
     o.adjoint = nullptr;
     o.rhoN_adjoint = nullptr;
     o.init_adjoint = nullptr;
-    o.solid_prepare = nullptr;
-    o.solid_fused = nullptr;
-    o.solid_step = nullptr;
-    o.solid_fields = nullptr;
   } else {
     o.adjoint = adjoint<S>;
     o.rhoN_adjoint = rhoN_adjoint<S>;
     o.init_adjoint = init_adjoint<S>;
-    o.solid_prepare = solid_prepare<S>;
-    o.solid_fused = solid_fused<S>;
-    o.solid_step = solid_step<S>;
-    o.solid_fields = solid_fields<S>;
   }
+  o.solid_prepare = solid_prepare<S>;
+  o.solid_fused = solid_fused<S>;
+  o.solid_step = solid_step<S>;
+  o.solid_fields = solid_fields<S>;
   o.batch_ntx[0] = o.batch_ntx[1] = o.batch_ntx[2] = 0;
   o.batch = batch<S>;
   o.sim_desc = sim_desc<S>;

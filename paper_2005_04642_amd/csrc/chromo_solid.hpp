@@ -151,17 +151,30 @@ __global__ void __launch_bounds__(256) bounce_bits_kernel(const unsigned char* _
   out[site] = (unsigned char)b;
 }
 
-// Zero the words of solid sites (they carry no state and no mass).
+// The words of zero populations (all-zero bits for the float formats, the
+// offset encoding of zero for the 16-bit ones).
+template <typename S>
+__device__ __forceinline__ void zero_words(const Coef<typename S::math>& c, typename S::W w[S::NW]) {
+  using T = typename S::math;
+  T R[9], B[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = B[i] = T(0);
+  encode<S>(R, B, c, w);
+}
+
+// Clear the words of solid sites (they carry no state and no mass).
 template <typename S>
 __global__ void __launch_bounds__(256) clear_solid_kernel(void* popsv, const unsigned char* __restrict__ solid,
-                                                          Geom g) {
+                                                          Geom g, Coef<typename S::math> c) {
   using W = typename S::W;
   W* pops = static_cast<W*>(popsv);
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx || !solid[at(g, x, y)]) return;
+  W w[S::NW];
+  zero_words<S>(c, w);
 #pragma unroll
-  for (int q = 0; q < S::NW; ++q) pops[((size_t)y * S::NW + q) * g.nx + x] = W(0);
+  for (int q = 0; q < S::NW; ++q) pops[((size_t)y * S::NW + q) * g.nx + x] = w[q];
 }
 
 // pass 1: colour densities, raw momentum, colour index, Phi'
@@ -278,8 +291,10 @@ __global__ void __launch_bounds__(256) collide_kernel(StepArgs<typename S::math>
   const size_t site = at(g, x, y), P = g.plane;
   if (solid[site]) {
     W* dst = static_cast<W*>(a.dst);
+    W w[S::NW];
+    zero_words<S>(a.c, w);
 #pragma unroll
-    for (int q = 0; q < S::NW; ++q) dst[((size_t)y * S::NW + q) * g.nx + x] = W(0);
+    for (int q = 0; q < S::NW; ++q) dst[((size_t)y * S::NW + q) * g.nx + x] = w[q];
     return;
   }
   T dPx, dPy;

@@ -137,12 +137,12 @@ def test_batch_validation_and_layout():
 
 
 def test_solid_mask_availability_and_argument_errors():
-    """Masks of solid sites exist for F64/F32 storage without walls (14 field
-    planes of workspace); NULL arguments fail before any GPU call."""
+    """Masks of solid sites exist for every storage format without walls (14
+    field planes of workspace); NULL arguments fail before any GPU call."""
     lib = lbm.load_library()
     prm = Wk.base_params(Lambda=10.0)
-    for storage, walls, ok in (("f32", False, True), ("f64", False, True), ("f16", False, False),
-                               ("bf16", False, False), ("f32", True, False)):
+    for storage, walls, ok in (("f32", False, True), ("f64", False, True), ("f16", False, True),
+                               ("bf16", False, True), ("f32", True, False)):
         p = lbm.make_params(64, 48, storage, **dict(prm, walls=walls))
         n = lbm.lbm_solid_workspace_bytes(p)
         assert (n > 0) == ok, (storage, walls)

@@ -229,3 +229,58 @@ def test_ofs16_largest_lattice_class_streaming(fmt):
             cx, cy = C[i]
             assert torch.equal(after[q, y, x], before[q, (y - cy) % n, (x - cx) % n]), (y, x, q)
     sim.close()
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (1, 1, 1, 1), (3, 1, 3, 1)])
+@pytest.mark.parametrize("shape", [(47, 29), (100, 60)])
+def test_ofs16_one_step_with_mask(fmt, stencil, shape):
+    """A mask of solid sites (circular wall and scattered obstacles) with the
+    16-bit formats: one step from a random state within the format's rounding
+    plus the arithmetic allowance of the FP64 oracle; solid sites keep the
+    encoding of zero populations."""
+    from gpu_helpers import pull_gather_masked, push_scatter_masked
+    nx, ny = shape
+    solid = Wk.circular_wall(nx, ny, 0.5 * min(nx, ny) - 1.5) | Wk.random_solid_sites(nx, ny, 10, nx)
+    params = Wk.base_params(Lambda=10.0, sigma=0.02, stencil=stencil)
+    params.update(gx=3e-5, gy=-2e-5, nu_B=0.4)
+    P = pull_gather(perturbed_rest_state(nx, ny, params, seed=nx + ny).astype(np.float64), False)
+    P[:, :, solid] = 0.0
+    W = ofs16.encode(*push_scatter_masked(P, solid).astype(np.float32), params, fmt)
+    sim = sim_for(nx, ny, params, -np.ones((ny, nx)), fmt, solid=solid)
+    upload_words(sim, W)
+    S = pull_gather_masked(ofs16.decode_pair(W, params, fmt), solid)   # the state the device starts from
+    o = O.Oracle(oracle_params(nx, ny, dict(params, solid=solid))).set_state(torch.from_numpy(S[0]),
+                                                                            torch.from_numpy(S[1]))
+    R, B = o.post_collision()
+    ref = np.stack([R.numpy(), B.numpy()])
+    sim.step(1)
+    got = ofs16.decode_pair(host_words(sim), params, fmt)
+    fl = ~solid
+    tol = ofs16.rounding_bound(ref[:, :, fl], params, fmt) + ARITH * np.max(np.abs(ref[:, :, fl]))
+    excess = np.abs(got[:, :, fl] - ref[:, :, fl]) / tol
+    print("%s mask one step %s %s: max err/tol %.3f" % (fmt, shape, stencil, excess.max()))
+    assert np.all(excess <= 1.0)
+    assert np.all(got[:, :, solid] == 0.0)
+    sim.close()
+
+
+@pytest.mark.parametrize("fmt", FMTS)
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (1, 1, 1, 1)])
+def test_ofs16_fused_masked_step_equals_four_passes(fmt, stencil):
+    nx, ny = 130, 70
+    solid = Wk.circular_wall(nx, ny, 0.5 * ny - 1.5) | Wk.random_solid_sites(nx, ny, 20, 4)
+    params = Wk.base_params(Lambda=10.0, sigma=0.01, stencil=stencil)
+    params.update(gx=3e-5, nu_B=0.4)
+    yy, xx = np.mgrid[0:ny, 0:nx]
+    rn = np.maximum(np.tanh((9.0 - np.hypot(xx - 60.0, yy - 35.0)) / 2.0),
+                    np.tanh((7.0 - np.hypot(xx - 75.0, yy - 30.0)) / 2.0))
+    out = []
+    for flags in (0, lbm.LBM_FLAG_MASK_PASSES):
+        sim = sim_for(nx, ny, params, rn, fmt, solid=solid, flags=flags)
+        sim.step(25)
+        out.append(host_words(sim))
+        m = sim.masses()
+        assert all(np.isfinite(m))
+        sim.close()
+    assert np.array_equal(out[0], out[1])

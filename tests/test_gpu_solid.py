@@ -150,11 +150,6 @@ def test_set_solid_argument_errors():
         sim.set_solid(solid)            # one mask per handle
     assert e.value.code == lbm.LBM_EINVAL
     sim.close()
-    s16 = lbm.Simulation(nx, ny, params, rn, storage="f16", device=DEV)
-    with pytest.raises(lbm.LbmError) as e:
-        s16.set_solid(solid)
-    assert e.value.code == lbm.LBM_ENOTIMPL
-    s16.close()
     pw = dict(params, walls=True)
     sw = lbm.Simulation(nx, ny, pw, rn, storage="f32", device=DEV)
     m = torch.zeros((ny, nx), dtype=torch.uint8, device=DEV)
