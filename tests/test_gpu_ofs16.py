@@ -282,5 +282,8 @@ def test_ofs16_fused_masked_step_equals_four_passes(fmt, stencil):
         out.append(host_words(sim))
         m = sim.masses()
         assert all(np.isfinite(m))
+        f = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+        assert np.all(np.isnan(f["rho"][solid])) and np.all(np.isfinite(f["rho"][~solid]))
+        assert np.all(np.isfinite(f["ux"][~solid])) and np.all(np.abs(f["rhoN"][~solid]) <= 1.0)
         sim.close()
     assert np.array_equal(out[0], out[1])
