@@ -9,7 +9,7 @@ from the state saved at its start, and returns dL/drho^N_0, dL/dsigma and
 dL/dG_ext (the per-site force density).  Every step, forward or adjoint, runs
 in the HIP library; torch only holds buffers.
 
-F64 or F32 storage, periodic or walled lattices.  dL/dsigma is summed in FP64 on the
+F64 or F32 storage; periodic, walled or masked lattices.  dL/dsigma is summed in FP64 on the
 device.
 """
 import torch

@@ -346,7 +346,7 @@ class Simulation:
     def masses(self):
         return lbm_masses_host(self.h, self.stream())
 
-    # -- adjoint (F64/F32 storage, periodic or walled) --------------------------
+    # -- adjoint (F64/F32 storage; periodic, walled or masked) ------------------
     def adjoint_workspace(self):
         """Device workspace of lbm_adjoint_step (allocated on first use)."""
         if getattr(self, "_adj_ws", None) is None:
