@@ -80,12 +80,27 @@ def test_autotune_keeps_state_and_results():
 
 
 def test_batch_of_the_benchmark_workload_runs():
-    lats = Wk.config_batch(nsim=32, seed=1)
+    """The benchmark's batch (256 drops of side 64..512) in the launch
+    configuration the benchmark times (3 steps, autotune, more steps): every
+    lattice finite, and sampled lattices of each size bit for bit as alone."""
+    lats = Wk.config_batch(nsim=256, seed=1)
     b = lbm.Batch(lats, storage="f32", device=DEV)
-    b.step(20)
+    b.step(3)
+    b.autotune(2)
+    b.step(17)
     for k in range(len(lats)):
         m = b.masses(k)
         assert np.isfinite(m).all()
+    picks = {}
+    for k, (nx, ny, _, _) in enumerate(lats):
+        picks.setdefault(nx, k)
+    for k in sorted(picks.values()):
+        nx, ny, prm, rn = lats[k]
+        s = lbm.Simulation(nx, ny, prm, rn, storage="f32", device=DEV)
+        s.step(20)
+        torch.cuda.synchronize()
+        assert torch.equal(b.state(k), s.live_pops()), (k, nx)
+        s.close()
     b.close()
 
 
