@@ -203,8 +203,9 @@ int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, vo
  * has its own size and physical parameters (lbm_params) and, optionally, its
  * own per-site force field (lbm_batch_set_force).  A batch is all periodic or
  * all walled (walls_y; walled batches are built for the stencil profiles
- * (3,3,3,3) and (1,1,1,1), LBM_ENOTIMPL for the others); no lattice of a batch
- * has a solid-site mask.  Their population buffers are packed one after the other (each
+ * (3,3,3,3) and (1,1,1,1), LBM_ENOTIMPL for the others); lattices of a
+ * periodic batch may have solid-site masks (lbm_batch_set_solid; same two
+ * profiles).  Their population buffers are packed one after the other (each
  * at a 256-byte aligned offset, lbm_batch_offsets) in two caller-owned buffers
  * of lbm_batch_pops_bytes() bytes.  Every lbm_batch_step is one launch of a
  * persistent-style kernel: each workgroup owns a bin of (lattice, tile) work
@@ -250,6 +251,17 @@ int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_
  * device table and waits for that copy on `stream`.  LBM_EINVAL for a bad
  * batch or index. */
 int lbm_batch_set_force(lbm_batch* b, int32_t k, const void* force, hipStream_t stream);
+
+/* Give lattice k of a periodic batch a mask of solid sites, as lbm_set_solid
+ * does for a single lattice (same mask and workspace contract, workspace of
+ * lbm_solid_workspace_bytes(&p[k]) bytes); from then on the batch steps with
+ * the kernel's mask variant (lattices without a mask are unaffected) and
+ * lbm_batch_fields reads NaN at lattice k's solid sites.  Waits for the
+ * update of the batch table on `stream`.  LBM_EINVAL for a bad index, NULL
+ * pointers, a small workspace, a walled batch or a lattice that has a mask;
+ * LBM_ENOTIMPL for stencil profiles other than 3333 and 1111. */
+int lbm_batch_set_solid(lbm_batch* b, int32_t k, const uint8_t* solid_dev, void* workspace, size_t ws_bytes,
+                        hipStream_t stream);
 
 /* info[5]: workgroup width, chunk-height cap, number of bins, number of work
  * items, largest bin cost in march iterations. */

@@ -475,7 +475,8 @@ struct BatchPlan {
 // Longest-processing-time-first assignment of the tiles of every lattice to
 // nbins bins (one workgroup each), costs counted in march iterations.
 BatchPlan batch_plan(const lbm_params* p, int nsim, const std::vector<size_t>& off, int nbins, int ntx, int tycap,
-                     const chromo::Ops& ops, int nr, int it0, const std::vector<const void*>& force) {
+                     const chromo::Ops& ops, int nr, int it0, const std::vector<const void*>& force,
+                     const std::vector<const unsigned char*>& bnc) {
   BatchPlan b;
   b.ntx = ntx;
   b.tycap = tycap;
@@ -488,7 +489,7 @@ BatchPlan batch_plan(const lbm_params* p, int nsim, const std::vector<size_t>& o
   std::vector<Tile> tiles;
   for (int k = 0; k < nsim; ++k) {
     const chromo::Geom g = batch_geom(p[k], ntx, tycap);
-    ops.sim_desc(p[k], g, (unsigned long long)off[k], force[k], &b.sims[(size_t)k * ops.sim_desc_bytes]);
+    ops.sim_desc(p[k], g, (unsigned long long)off[k], force[k], bnc[k], &b.sims[(size_t)k * ops.sim_desc_bytes]);
     for (int t = 0; t < g.nstrips * g.nchunks; ++t) {
       const int chunk = t / g.nstrips;
       const int rows = std::min(g.TY, g.F - chunk * g.TY);
@@ -526,6 +527,8 @@ struct lbm_batch {
   std::vector<lbm_params> p;
   std::vector<size_t> off;
   std::vector<const void*> force;  // per-lattice force fields (lbm_batch_set_force), or null
+  std::vector<const unsigned char*> bnc;  // per-lattice mask bounce bits (lbm_batch_set_solid), or null
+  int masked;                      // some lattice has a mask: step with the mask variant
   char* pops[2];
   int live;
   int64_t steps;
@@ -559,7 +562,7 @@ int batch_upload(lbm_batch* b, BatchPlan&& pl, hipStream_t s) {
 
 int batch_step_impl(lbm_batch* b, int nsteps, hipStream_t s) {
   for (int k = 0; k < nsteps; ++k) {
-    hipError_t e = b->ops->batch(b->plan.ntx, b->p[0].stencil, b->p[0].walls_y, b->pops[b->live],
+    hipError_t e = b->ops->batch(b->plan.ntx, b->p[0].stencil, b->p[0].walls_y, b->masked, b->pops[b->live],
                                  b->pops[1 - b->live], b->d_sims,
                                  b->d_bin_start, b->d_items, b->plan.nbins, s);
     if (e != hipSuccess) return fail(LBM_EHIP, "batch step launch: %s", hipGetErrorString(e));
@@ -634,6 +637,8 @@ int lbm_batch_init(const lbm_params* p, int nsim, const void* const* rhoN0, void
   b->nsim = nsim;
   b->p.assign(p, p + nsim);
   b->force.assign(nsim, nullptr);
+  b->bnc.assign(nsim, nullptr);
+  b->masked = 0;
   batch_offsets(p, nsim, &b->off);
   b->pops[0] = static_cast<char*>(pops_a);
   b->pops[1] = static_cast<char*>(pops_b);
@@ -674,7 +679,7 @@ int lbm_batch_init(const lbm_params* p, int nsim, const void* const* rhoN0, void
   const int it0 = 3 * ((nr * ((3 + nr - 1) / nr) + 3 + nr - 1) / nr);
   int ntx0 = b->ops->batch_ntx[0];
   for (int i = 1; i < 3 && b->ops->batch_ntx[i]; ++i) ntx0 = std::max(ntx0, b->ops->batch_ntx[i]);
-  st = batch_upload(b, batch_plan(p, nsim, b->off, ncu, ntx0, 128, *b->ops, nr, it0, b->force), stream);
+  st = batch_upload(b, batch_plan(p, nsim, b->off, ncu, ntx0, 128, *b->ops, nr, it0, b->force, b->bnc), stream);
   if (st != LBM_OK) {
     delete b;
     return st;
@@ -711,7 +716,7 @@ int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_
   for (int i = 0; i < 3 && b->ops->batch_ntx[i] && st == LBM_OK; ++i) {
     for (int tc : BATCH_TYCAPS) {
       st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, b->ops->batch_ntx[i], tc, *b->ops, nr,
-                                      it0, b->force),
+                                      it0, b->force, b->bnc),
                         stream);
       if (st != LBM_OK) break;
       if (hipMemcpyAsync(b->pops[live0], scratch, total, hipMemcpyDeviceToDevice, stream) != hipSuccess) {
@@ -745,7 +750,8 @@ int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_
   b->live = live0;
   b->steps = steps0;
   if (st != LBM_OK) return st;
-  st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, best_ntx, best_tycap, *b->ops, nr, it0, b->force),
+  st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, best_ntx, best_tycap, *b->ops, nr, it0,
+                                  b->force, b->bnc),
                     stream);
   if (st != LBM_OK) return st;
   if (chosen) {
@@ -762,10 +768,43 @@ int lbm_batch_set_force(lbm_batch* b, int32_t k, const void* force, hipStream_t 
   b->view[k].force = force;
   const chromo::Geom g = batch_geom(b->p[k], b->plan.ntx, b->plan.tycap);
   unsigned char* desc = &b->plan.sims[(size_t)k * b->ops->sim_desc_bytes];
-  b->ops->sim_desc(b->p[k], g, (unsigned long long)b->off[k], force, desc);
+  b->ops->sim_desc(b->p[k], g, (unsigned long long)b->off[k], force, b->bnc[k], desc);
   HIP_TRY(hipMemcpyAsync(static_cast<char*>(b->d_sims) + (size_t)k * b->ops->sim_desc_bytes, desc,
                          b->ops->sim_desc_bytes, hipMemcpyHostToDevice, stream));
   HIP_TRY(hipStreamSynchronize(stream));  // the host copy may change with the next plan
+  return LBM_OK;
+}
+
+int lbm_batch_set_solid(lbm_batch* b, int32_t k, const uint8_t* solid_dev, void* workspace, size_t ws_bytes,
+                        hipStream_t stream) {
+  g_last_error.clear();
+  if (!b || k < 0 || k >= b->nsim) return fail(LBM_EINVAL, "bad batch or lattice index");
+  if (!solid_dev || !workspace) return fail(LBM_EINVAL, "solid mask and workspace must be non-NULL");
+  if (b->bnc[k]) return fail(LBM_EINVAL, "lattice %d already has a solid-site mask", k);
+  const lbm_params& p = b->p[k];
+  if (p.walls_y) return fail(LBM_EINVAL, "masks go in batches of periodic lattices (put wall rows in the mask)");
+  const int* r = p.stencil;
+  const bool all3 = r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3;
+  const bool all1 = r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1;
+  if (!all3 && !all1) return fail(LBM_ENOTIMPL, "masks in batches are built for stencil profiles 3333 and 1111");
+  if (p.nx < 4 || p.ny < 4) return fail(LBM_EINVAL, "a solid-site mask needs nx, ny >= 4");
+  const size_t need = lbm_solid_workspace_bytes(&p);
+  if (ws_bytes < need) return fail(LBM_EINVAL, "solid workspace too small: %zu < %zu", ws_bytes, need);
+  if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
+  lbm_handle* h = batch_view(b, k);
+  hipError_t e = b->ops->solid_prepare(p, h->g, h->pops[h->live], solid_dev, workspace, stream);
+  if (e != hipSuccess) return fail(LBM_EHIP, "solid mask launch: %s", hipGetErrorString(e));
+  h->solid = solid_dev;
+  h->solid_ws = workspace;
+  b->bnc[k] = static_cast<const unsigned char*>(workspace) +
+              chromo::solid::bits_offset((size_t)p.nx * (size_t)p.ny, (size_t)b->ops->math_bytes);
+  b->masked = 1;
+  const chromo::Geom g = batch_geom(p, b->plan.ntx, b->plan.tycap);
+  unsigned char* desc = &b->plan.sims[(size_t)k * b->ops->sim_desc_bytes];
+  b->ops->sim_desc(p, g, (unsigned long long)b->off[k], b->force[k], b->bnc[k], desc);
+  HIP_TRY(hipMemcpyAsync(static_cast<char*>(b->d_sims) + (size_t)k * b->ops->sim_desc_bytes, desc,
+                         b->ops->sim_desc_bytes, hipMemcpyHostToDevice, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
   return LBM_OK;
 }
 

@@ -62,11 +62,12 @@ struct Ops {
                              const unsigned char* mask, void* ws, void* rho, void* ux, void* uy, void* rhoN,
                              hipStream_t s);
   // batched periodic step: ntx in batch_ntx (0-terminated); tables in device memory
-  hipError_t (*batch)(int ntx, const int* radii, int walls, const void* src, void* dst, const void* sims,
-                      const int* bin_start, const int* items, int nbins, hipStream_t s);
-  // one SimDesc<math> of lattice p with tile plan g, byte offset off and force
-  // field (device [2][ny][nx] or null), written to out
-  void (*sim_desc)(const lbm_params& p, const Geom& g, unsigned long long off, const void* force, void* out);
+  hipError_t (*batch)(int ntx, const int* radii, int walls, int masked, const void* src, void* dst,
+                      const void* sims, const int* bin_start, const int* items, int nbins, hipStream_t s);
+  // one SimDesc<math> of lattice p with tile plan g, byte offset off, force
+  // field (device [2][ny][nx] or null) and mask bounce bits (or null), written to out
+  void (*sim_desc)(const lbm_params& p, const Geom& g, unsigned long long off, const void* force,
+                   const unsigned char* bnc, void* out);
   int sim_desc_bytes;
   int batch_ntx[3];
   int words;        // words per site

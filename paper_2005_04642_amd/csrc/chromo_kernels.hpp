@@ -324,7 +324,7 @@ __device__ __forceinline__ void gather_words(__amdgpu_buffer_rsrc_t src, const G
     const int voff = bounce ? x.o : (dx == 1 ? x.m : (dx == -1 ? x.p : x.o));
     if constexpr (MASK) {
       if (i != 0) {
-        const unsigned b = bnc[(size_t)p * g.nx + xg];
+        const unsigned b = bnc ? bnc[(size_t)p * g.nx + xg] : 0u;  // (a batch lattice without a mask: null)
         const unsigned own = (unsigned)x.o + (unsigned)word_bounce<S>(q) * g.pb + ro;
         const unsigned off = ((b >> (i - 1)) & 1u) ? own : (unsigned)voff + soff;
         out[q] = load_word<typename S::W>(src, (int)off, 0);
@@ -885,6 +885,7 @@ struct SimDesc {
   Coef<T> c;              // per-lattice constants
   unsigned long long off; // byte offset of the lattice's populations in both packed buffers
   const T* force;         // per-site force density [2][ny][nx] of the lattice, or null
+  const unsigned char* bnc;  // bounce bits of the lattice's solid-site mask, or null
 };
 
 template <typename T>
@@ -896,7 +897,7 @@ struct BatchArgs {
   const int* items;             // pairs (lattice, tile)
 };
 
-template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS = false>
+template <typename ST, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS = false, bool MASK = false>
 __global__ void __launch_bounds__(NTX * NR, 1) chromo_batch_kernel(BatchArgs<typename ST::math> b) {
   using T = typename ST::math;
   using PP = Pipe<NR>;
@@ -911,10 +912,10 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_batch_kernel(BatchArgs<typ
     a.force = b.sims[sim].force;
     a.out_rho = a.out_ux = a.out_uy = a.out_rhoN = a.out_save = a.out_adj = nullptr;
     a.lam_next = nullptr;
-    a.bnc = nullptr;
+    a.bnc = b.sims[sim].bnc;
     a.g = b.sims[sim].g;
     a.c = b.sims[sim].c;
-    march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE_STEP>(a, tile, sm);
+    march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE_STEP, MASK>(a, tile, sm);
     __syncthreads();  // the next tile reuses the LDS rings
   }
 }

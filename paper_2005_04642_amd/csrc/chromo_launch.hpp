@@ -292,18 +292,21 @@ hipError_t init_adjoint(const lbm_params& p, const Geom& g0, const void* rhoN0, 
 // ---------------------------------------------------------------------------
 // batched periodic step (chromo_batch_kernel)
 // ---------------------------------------------------------------------------
-template <typename S, int NTX, int RG, int RK, int RP, int RU, bool WALLS = false>
+template <typename S, int NTX, int RG, int RK, int RP, int RU, bool WALLS = false, bool MASK = false>
 hipError_t batch_launch(const BatchArgs<typename S::math>& b, int nbins, hipStream_t s) {
-  hipLaunchKernelGGL((chromo_batch_kernel<S, NTX, Shape<S>::nr, RG, RK, RP, RU, WALLS>), dim3(nbins),
+  hipLaunchKernelGGL((chromo_batch_kernel<S, NTX, Shape<S>::nr, RG, RK, RP, RU, WALLS, MASK>), dim3(nbins),
                      dim3(NTX * Shape<S>::nr), 0, s, b);
   return hipGetLastError();
 }
 
-// batches of walled lattices: built for the stencil profiles (3,3,3,3) and (1,1,1,1)
-template <typename S, int NTX>
-hipError_t batch_walls(const BatchArgs<typename S::math>& b, const int* r, int nbins, hipStream_t s) {
-  if (r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3) return batch_launch<S, NTX, 3, 3, 3, 3, true>(b, nbins, s);
-  if (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1) return batch_launch<S, NTX, 1, 1, 1, 1, true>(b, nbins, s);
+// batches of walled lattices, or with solid-site masks on some lattices
+// (MASK): built for the stencil profiles (3,3,3,3) and (1,1,1,1)
+template <typename S, int NTX, bool WALLS, bool MASK>
+hipError_t batch_special(const BatchArgs<typename S::math>& b, const int* r, int nbins, hipStream_t s) {
+  if (r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3)
+    return batch_launch<S, NTX, 3, 3, 3, 3, WALLS, MASK>(b, nbins, s);
+  if (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1)
+    return batch_launch<S, NTX, 1, 1, 1, 1, WALLS, MASK>(b, nbins, s);
   return hipErrorNotSupported;
 }
 
@@ -335,8 +338,16 @@ hipError_t batch_radii(const BatchArgs<typename S::math>& b, const int* r, int n
   return hipErrorInvalidValue;
 }
 
+template <typename S, int NTX>
+hipError_t batch_kind(const BatchArgs<typename S::math>& b, const int* r, int walls, int masked, int nbins,
+                      hipStream_t s) {
+  if (walls) return batch_special<S, NTX, true, false>(b, r, nbins, s);
+  if (masked) return batch_special<S, NTX, false, true>(b, r, nbins, s);
+  return batch_radii<S, NTX>(b, r, nbins, s);
+}
+
 template <typename S>
-hipError_t batch(int ntx, const int* radii, int walls, const void* src, void* dst, const void* sims,
+hipError_t batch(int ntx, const int* radii, int walls, int masked, const void* src, void* dst, const void* sims,
                  const int* bin_start, const int* items, int nbins, hipStream_t s) {
   using T = typename S::math;
   BatchArgs<T> b;
@@ -346,22 +357,23 @@ hipError_t batch(int ntx, const int* radii, int walls, const void* src, void* ds
   b.bin_start = bin_start;
   b.items = items;
   if constexpr (Shape<S>::f64) {
-    if (ntx == NTX_F64) return walls ? batch_walls<S, NTX_F64>(b, radii, nbins, s)
-                                     : batch_radii<S, NTX_F64>(b, radii, nbins, s);
+    if (ntx == NTX_F64) return batch_kind<S, NTX_F64>(b, radii, walls, masked, nbins, s);
   } else {
-    if (ntx == 128) return walls ? batch_walls<S, 128>(b, radii, nbins, s) : batch_radii<S, 128>(b, radii, nbins, s);
-    if (ntx == 192) return walls ? batch_walls<S, 192>(b, radii, nbins, s) : batch_radii<S, 192>(b, radii, nbins, s);
+    if (ntx == 128) return batch_kind<S, 128>(b, radii, walls, masked, nbins, s);
+    if (ntx == 192) return batch_kind<S, 192>(b, radii, walls, masked, nbins, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <typename S>
-void sim_desc(const lbm_params& p, const Geom& g, unsigned long long off, const void* force, void* out) {
+void sim_desc(const lbm_params& p, const Geom& g, unsigned long long off, const void* force,
+              const unsigned char* bnc, void* out) {
   SimDesc<typename S::math> d;
   d.g = geom_for<S>(g);
   d.c = make_coef<S>(p);
   d.off = off;
   d.force = static_cast<const typename S::math*>(force);
+  d.bnc = bnc;
   memcpy(out, &d, sizeof(d));
 }
 

@@ -28,7 +28,8 @@ EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_work
             "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_solid_workspace_bytes", "lbm_set_solid",
             "lbm_current_pops", "lbm_set_pops", "lbm_step_count",
             "lbm_destroy", "lbm_last_error", "lbm_batch_pops_bytes", "lbm_batch_offsets", "lbm_batch_workspace_bytes",
-            "lbm_batch_init", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_set_force", "lbm_batch_plan_info",
+            "lbm_batch_init", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_set_force", "lbm_batch_set_solid",
+            "lbm_batch_plan_info",
             "lbm_batch_fields",
             "lbm_batch_masses_host", "lbm_batch_current_pops", "lbm_batch_step_count", "lbm_batch_destroy")
 
@@ -119,6 +120,8 @@ def load_library(path=None):
     lib.lbm_batch_autotune.restype = ctypes.c_int
     lib.lbm_batch_set_force.argtypes = [vp, i32, vp, vp]
     lib.lbm_batch_set_force.restype = ctypes.c_int
+    lib.lbm_batch_set_solid.argtypes = [vp, i32, vp, vp, sz, vp]
+    lib.lbm_batch_set_solid.restype = ctypes.c_int
     lib.lbm_batch_plan_info.argtypes = [vp, i32p]
     lib.lbm_batch_plan_info.restype = ctypes.c_int
     lib.lbm_batch_fields.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -534,6 +537,23 @@ class Batch:
         _check(self.lib, self.lib.lbm_batch_set_force(self.h, int(k), None if t is None else t.data_ptr(),
                                                       self.stream()))
         self._forces[k] = t          # kept alive while the batch uses it
+        return self
+
+    def set_solid(self, k, solid):
+        """Mask of solid sites of lattice k ([ny, nx], nonzero = solid)."""
+        t = self.torch
+        nx, ny = self.shapes[k]
+        m = solid if t.is_tensor(solid) else t.as_tensor(np.asarray(solid))
+        m = (m != 0).to(device=self.device, dtype=t.uint8).contiguous()
+        if tuple(m.shape) != (ny, nx):
+            raise ValueError("mask of lattice %d must have shape (%d, %d)" % (k, ny, nx))
+        n = self.lib.lbm_solid_workspace_bytes(ctypes.byref(self.plist[k]))
+        ws = t.empty(max(n, 256), dtype=t.uint8, device=self.device)
+        _check(self.lib, self.lib.lbm_batch_set_solid(self.h, int(k), m.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                      self.stream()))
+        if not hasattr(self, "_solids"):
+            self._solids = {}
+        self._solids[k] = (m, ws)    # kept alive while the batch uses them
         return self
 
     def plan_info(self):
