@@ -324,7 +324,7 @@ __device__ __forceinline__ void gather_words(__amdgpu_buffer_rsrc_t src, const G
     const int voff = bounce ? x.o : (dx == 1 ? x.m : (dx == -1 ? x.p : x.o));
     if constexpr (MASK) {
       if (i != 0) {
-        const unsigned b = bnc ? bnc[(size_t)p * g.nx + xg] : 0u;  // (a batch lattice without a mask: null)
+        const unsigned b = bnc[(size_t)p * g.nx + xg];
         const unsigned own = (unsigned)x.o + (unsigned)word_bounce<S>(q) * g.pb + ro;
         const unsigned off = ((b >> (i - 1)) & 1u) ? own : (unsigned)voff + soff;
         out[q] = load_word<typename S::W>(src, (int)off, 0);
@@ -915,7 +915,16 @@ __global__ void __launch_bounds__(NTX * NR, 1) chromo_batch_kernel(BatchArgs<typ
     a.bnc = b.sims[sim].bnc;
     a.g = b.sims[sim].g;
     a.c = b.sims[sim].c;
-    march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE_STEP, MASK>(a, tile, sm);
+    // in a batch with masks, lattices without one take the plain march
+    if constexpr (MASK) {
+      if (a.bnc) {
+        march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE_STEP, true>(a, tile, sm);
+      } else {
+        march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE_STEP, false>(a, tile, sm);
+      }
+    } else {
+      march_tile<ST, NTX, NR, RG, RK, RP, RU, WALLS, MODE_STEP, false>(a, tile, sm);
+    }
     __syncthreads();  // the next tile reuses the LDS rings
   }
 }
