@@ -1,7 +1,8 @@
 """Physics of the GPU path itself (not only its agreement with the oracle):
 * Laplace's law for a static drop (Sec. IV, curved interfaces: the pressure
   step across a drop follows sigma / R), in FP32 on the static-drop
-  workload's lattice, for two tensions and two radii;
+  workload's lattice, for two tensions and two radii, and inside a circular
+  wall given as a mask of solid sites;
 * the flat-interface transient of Sec. IV / App. C on the paper's lattice
   (interface at 500 of H = 1000, eta = 0.166, beta = 0.5, the four density
   ratios and times of Table 3), epsilon(t) against the Sturm-Liouville
@@ -112,3 +113,34 @@ def test_stratified_steady_flow_ba_full_size():
     eps = A.transient_error(f["ux"], ua)
     print("Ba flow H %d: epsilon %.4f %%, max|u| %.3e" % (H, 100 * eps, np.max(np.abs(f["ux"]))))
     assert eps < 0.01
+
+
+def test_laplace_law_inside_a_circular_wall():
+    """A drop of radius 14 at rest inside a staircase circular no-slip wall of
+    radius 44 (solid-site mask), Lambda = 10, sigma = 0.01, FP32, 3000 steps:
+    the pressure step from the drop's centre to the ring half-way to the wall
+    follows sigma / R_eff within 5 %, and the wall adds no flow (max |u| of
+    the order of the open lattice's micro-current).  Measured 1.016 and
+    9.3e-6."""
+    n, R, Rw, sigma = 96, 14.0, 44.0, 0.01
+    d = Wk.base_params(Lambda=10.0, sigma=sigma)
+    solid = Wk.circular_wall(n, n, Rw)
+    yy, xx = np.mgrid[0:n, 0:n]
+    c = (n - 1) / 2.0
+    r = np.hypot(xx - c, yy - c)
+    rn = np.tanh((R - r) / 2.0)
+    sim = lbm.Simulation(n, n, d, rn, storage="f32", device=DEV, solid=solid)
+    sim.step(3000)
+    f = {k: v.double().cpu().numpy() for k, v in sim.fields().items()}
+    sim.close()
+    fl = ~solid
+    rR, rB = colour_densities(f["rho"], f["rhoN"], d)
+    P = O.isotropic_pressure(np.nan_to_num(rR), np.nan_to_num(rB), O.Params(nx=n, ny=n, **d))
+    inner = P[r < 3.0].mean()
+    outer = P[fl & (np.abs(r - (R + Rw) / 2.0) < 1.0)].mean()
+    Reff = math.sqrt(float(((1 + f["rhoN"][fl]) / 2).sum()) / math.pi)
+    ratio = (inner - outer) / A.laplace_pressure(sigma, Reff)
+    umax = float(np.nanmax(np.hypot(f["ux"], f["uy"])))
+    print("Laplace inside a wall: dp / (sigma / R_eff) = %.4f, R_eff %.2f, max|u| %.2e" % (ratio, Reff, umax))
+    assert abs(ratio - 1.0) < 0.05
+    assert umax < 1e-4
