@@ -149,3 +149,5 @@ def test_solid_mask_availability_and_argument_errors():
         if ok:
             assert n >= 14 * 64 * 48 * (8 if storage == "f64" else 4) and n % 256 == 0
     assert lib.lbm_set_solid(None, None, None, 0, None) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_set_solid(None, 0, None, None, 0, None) == lbm.LBM_EINVAL
+    assert lib.lbm_batch_set_force(None, 0, None, None) == lbm.LBM_EINVAL
