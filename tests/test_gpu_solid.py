@@ -244,3 +244,31 @@ def test_full_size_masked_emulsion_sampled_sites():
     assert worst < 2e-5
     for sim in sims:
         sim.close()
+
+
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (3, 1, 3, 1)])
+def test_one_step_options_with_mask_f64(stencil):
+    """Fixed curvature, literal ghost equilibrium and no recolour on a masked
+    lattice (the fused mask variant for 3333, the four passes for 3131)."""
+    nx, ny = 44, 38
+    solid = container(nx, ny, 6, nobst=10)
+    rng = np.random.default_rng(12)
+    rn = np.clip(np.tanh(2.0 * rng.standard_normal((ny, nx))), -1, 1)
+    for extra in (dict(fixed_K=0.05), dict(ghost_eq=1), dict(recolor=False)):
+        params = Wk.base_params(Lambda=4.0, sigma=0.02, stencil=stencil)
+        params.update(**extra)
+        sim = lbm.Simulation(nx, ny, params, rn, storage="f64", device=DEV, solid=solid)
+        o0 = O.Oracle(oracle_params(nx, ny, dict(params, solid=solid))).init(rn)
+        P = np.stack([o0.R.numpy(), o0.B.numpy()]) * Wk.random_state_perturbation((2, 9, ny, nx), 0.05, 7)
+        P[:, :, solid] = 0.0
+        sim.live_pops().copy_(torch.from_numpy(push_scatter_masked(P, solid)))
+        o = O.Oracle(oracle_params(nx, ny, dict(params, solid=solid)))
+        o.set_state(torch.from_numpy(P[0]), torch.from_numpy(P[1]))
+        R, B = o.post_collision()
+        ref = np.stack([R.numpy(), B.numpy()])
+        sim.step(1)
+        got = host(sim.live_pops())
+        fl = ~solid
+        err = np.max(np.abs(got[:, :, fl] - ref[:, :, fl])) / np.max(np.abs(ref[:, :, fl]))
+        assert err < 1e-13, (extra, err)
+        sim.close()
