@@ -272,3 +272,35 @@ def test_one_step_options_with_mask_f64(stencil):
         err = np.max(np.abs(got[:, :, fl] - ref[:, :, fl])) / np.max(np.abs(ref[:, :, fl]))
         assert err < 1e-13, (extra, err)
         sim.close()
+
+
+def test_drop_in_container_1000_steps_f32():
+    """FP32 storage and arithmetic, 1000 steps of the container drop against the
+    FP64 oracle: rho within 1e-5 relative; u, a micro-current of ~3e-5 here
+    (ten times smaller than the open static drop's, so one FP32 ulp of a
+    population is a larger part of it), no further from the FP64 oracle than
+    the oracle itself run in FP32 arithmetic.  Measured: e_rho 5.2e-6; e_u
+    7.0e-3 against the FP32 oracle's 9.3e-3 (max |u| 2.8e-5)."""
+    n = 64
+    solid = Wk.circular_wall(n, n, 30.0)
+    for x, y in ((50, 20), (51, 20), (14, 44), (40, 48), (32, 10)):
+        solid[y, x] = True
+    yy, xx = np.mgrid[0:n, 0:n]
+    rn = np.tanh((11.0 - np.hypot(xx - 29.0, yy - 33.5)) / 2.0)
+    params = Wk.base_params(Lambda=10.0, sigma=0.005)
+    sim = lbm.Simulation(n, n, params, rn, storage="f32", device=DEV, solid=solid)
+    sim.step(1000)
+    f = {k: host(v).astype(np.float64) for k, v in sim.fields().items()}
+    sim.close()
+    o = O.Oracle(oracle_params(n, n, dict(params, solid=solid))).init(rn).step(1000)
+    fo = {k: v.numpy() for k, v in o.fields().items()}
+    fl = ~solid
+    e_rho = rel_err(f["rho"][fl], fo["rho"][fl])
+    umax = np.max(np.hypot(fo["ux"][fl], fo["uy"][fl]))
+    e_u = np.max(np.hypot(f["ux"][fl] - fo["ux"][fl], f["uy"][fl] - fo["uy"][fl])) / umax
+    o32 = O.Oracle(oracle_params(n, n, dict(params, solid=solid)), dtype=torch.float32).init(rn).step(1000)
+    f32 = {k: v.double().numpy() for k, v in o32.fields().items()}
+    floor_u = np.max(np.hypot(f32["ux"][fl] - fo["ux"][fl], f32["uy"][fl] - fo["uy"][fl])) / umax
+    print("drop in container, 1000 steps FP32: e_rho %.2e e_u %.2e (max|u| %.2e; FP32 oracle e_u %.2e)"
+          % (e_rho, e_u, umax, floor_u))
+    assert e_rho < 1e-5 and e_u <= floor_u
