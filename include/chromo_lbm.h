@@ -163,7 +163,7 @@ int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream);
  * Provided for LBM_STORAGE_F64 and LBM_STORAGE_F32, periodic, walled
  * (walls_y = 1: the transposes of the wall-mirrored stencils and of the
  * bounce-back) or with a mask of solid sites (lbm_set_solid; stencil profiles
- * (3,3,3,3) and (1,1,1,1), others LBM_ENOTIMPL); the 16-bit formats return
+ * (3,3,3,3), (3,1,3,1) and (1,1,1,1), others LBM_ENOTIMPL); the 16-bit formats return
  * LBM_ENOTIMPL.  The words of solid rows and sites carry no state: their
  * adjoints are written as 0.  Adjoint buffers have the
  * layout of an F64/F32 population buffer ([ny][colour 2][link 9][nx], the
@@ -203,8 +203,8 @@ int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, vo
  * has its own size and physical parameters (lbm_params) and, optionally, its
  * own per-site force field (lbm_batch_set_force).  A batch is all periodic or
  * all walled (walls_y; walled batches are built for the stencil profiles
- * (3,3,3,3) and (1,1,1,1), LBM_ENOTIMPL for the others); lattices of a
- * periodic batch may have solid-site masks (lbm_batch_set_solid; same two
+ * (3,3,3,3), (3,1,3,1) and (1,1,1,1), LBM_ENOTIMPL for the others); lattices of a
+ * periodic batch may have solid-site masks (lbm_batch_set_solid; same three
  * profiles).  Their population buffers are packed one after the other (each
  * at a 256-byte aligned offset, lbm_batch_offsets) in two caller-owned buffers
  * of lbm_batch_pops_bytes() bytes.  Every lbm_batch_step is one launch of a
@@ -259,7 +259,7 @@ int lbm_batch_set_force(lbm_batch* b, int32_t k, const void* force, hipStream_t 
  * lbm_batch_fields reads NaN at lattice k's solid sites.  Waits for the
  * update of the batch table on `stream`.  LBM_EINVAL for a bad index, NULL
  * pointers, a small workspace, a walled batch or a lattice that has a mask;
- * LBM_ENOTIMPL for stencil profiles other than 3333 and 1111. */
+ * LBM_ENOTIMPL for stencil profiles other than 3333, 3131 and 1111. */
 int lbm_batch_set_solid(lbm_batch* b, int32_t k, const uint8_t* solid_dev, void* workspace, size_t ws_bytes,
                         hipStream_t stream);
 
@@ -290,7 +290,7 @@ void lbm_batch_destroy(lbm_batch* b);
  * stencils at a curved wall).  Solid sites hold zero populations (all-zero
  * words in F64/F32, the offset encoding of zero in the 16-bit formats), carry
  * no mass, and read as NaN from lbm_fields.  For the stencil profiles
- * (3,3,3,3) and (1,1,1,1) the step is one launch of the fused step kernel in
+ * (3,3,3,3), (3,1,3,1) and (1,1,1,1) the step is one launch of the fused step kernel in
  * its mask variant (per-site bounce bits, NaN markers for stencil taps); for
  * the other profiles, or with LBM_FLAG_MASK_PASSES, four launches over
  * per-site field planes.  Both give the same results bit for bit. */
@@ -314,7 +314,7 @@ size_t lbm_solid_workspace_bytes(const lbm_params* p);
  * the fused kernel recognises solid sites by their zero mass.  A handle takes one mask:
  * LBM_EINVAL if it has one already, for NULL pointers, a small workspace,
  * walls_y = 1 or nx, ny < 4; LBM_ENOTIMPL for the streaming-only mode.  The adjoint entry points work on such a handle for
- * the stencil profiles (3,3,3,3) and (1,1,1,1) (LBM_ENOTIMPL for the others);
+ * the stencil profiles (3,3,3,3), (3,1,3,1) and (1,1,1,1) (LBM_ENOTIMPL for the others);
  * lbm_init_adjoint then differentiates the rest state as lbm_set_solid
  * re-encoded it. */
 int lbm_set_solid(lbm_handle* h, const uint8_t* solid_dev, void* workspace, size_t ws_bytes, hipStream_t stream);

@@ -111,7 +111,7 @@ def rollout(rhoN0, sigma, force, params, nsteps, checkpoint=100, storage="f32", 
     from the forward pass to the end of the backward one (checkpoint = 1 keeps
     every state and recomputes nothing), plus ``checkpoint`` states during the
     backward recompute of one segment.  ``params`` may hold ``solid``, a mask of
-    solid sites ([ny, nx]; F64/F32 storage, stencil profiles 3333 and 1111)."""
+    solid sites ([ny, nx]; F64/F32 storage, stencil profiles 3333, 3131 and 1111)."""
     if not torch.is_tensor(sigma):
         sigma = torch.tensor(float(sigma), dtype=torch.float64)
     return _Rollout.apply(rhoN0, sigma, force, params, int(nsteps), int(checkpoint), storage, device)

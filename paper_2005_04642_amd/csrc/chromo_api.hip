@@ -41,6 +41,14 @@ bool radius_ok(int r) { return r == 1 || r == 3; }
 
 int halo(const lbm_params& p) { return p.stencil[0] + p.stencil[1] + p.stencil[3]; }
 
+// Stencil profiles with instantiations of the step kernel's mask variant, the
+// walled batch kernel and the masked adjoint: (3,3,3,3), the "fast" (3,1,3,1)
+// and the "compact" (1,1,1,1).
+bool special_profile(const int* r) {
+  return (r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3) || (r[0] == 3 && r[1] == 1 && r[2] == 3 && r[3] == 1) ||
+         (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1);
+}
+
 using chromo::MASS_BLOCKS;
 
 const chromo::Ops* ops_of(int storage) {
@@ -285,13 +293,8 @@ size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
 static int adjoint_supported(const lbm_handle* h) {
   if (!h->ops->adjoint) return fail(LBM_ENOTIMPL, "the adjoint is provided for F64 and F32 storage only");
   if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no adjoint of the streaming-only test mode");
-  if (h->solid) {
-    const int* r = h->p.stencil;
-    const bool all3 = r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3;
-    const bool all1 = r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1;
-    if (!all3 && !all1)
-      return fail(LBM_ENOTIMPL, "the adjoint with a solid-site mask is built for stencil profiles 3333 and 1111");
-  }
+  if (h->solid && !special_profile(h->p.stencil))
+    return fail(LBM_ENOTIMPL, "the adjoint with a solid-site mask is built for stencil profiles 3333, 3131 and 1111");
   return LBM_OK;
 }
 
@@ -421,12 +424,8 @@ int batch_validate(const lbm_params* p, int nsim) {
     for (int r = 0; r < 4; ++r)
       if (p[k].stencil[r] != p[0].stencil[r]) return fail(LBM_EINVAL, "lattice %d: stencil radii differ", k);
   }
-  if (p[0].walls_y) {
-    const int* r = p[0].stencil;
-    const bool all3 = r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3;
-    const bool all1 = r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1;
-    if (!all3 && !all1) return fail(LBM_ENOTIMPL, "batches of walled lattices are built for stencils 3333 and 1111");
-  }
+  if (p[0].walls_y && !special_profile(p[0].stencil))
+    return fail(LBM_ENOTIMPL, "batches of walled lattices are built for stencils 3333, 3131 and 1111");
   return LBM_OK;
 }
 
@@ -783,10 +782,8 @@ int lbm_batch_set_solid(lbm_batch* b, int32_t k, const uint8_t* solid_dev, void*
   if (b->bnc[k]) return fail(LBM_EINVAL, "lattice %d already has a solid-site mask", k);
   const lbm_params& p = b->p[k];
   if (p.walls_y) return fail(LBM_EINVAL, "masks go in batches of periodic lattices (put wall rows in the mask)");
-  const int* r = p.stencil;
-  const bool all3 = r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3;
-  const bool all1 = r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1;
-  if (!all3 && !all1) return fail(LBM_ENOTIMPL, "masks in batches are built for stencil profiles 3333 and 1111");
+  if (!special_profile(p.stencil))
+    return fail(LBM_ENOTIMPL, "masks in batches are built for stencil profiles 3333, 3131 and 1111");
   if (p.nx < 4 || p.ny < 4) return fail(LBM_EINVAL, "a solid-site mask needs nx, ny >= 4");
   const size_t need = lbm_solid_workspace_bytes(&p);
   if (ws_bytes < need) return fail(LBM_EINVAL, "solid workspace too small: %zu < %zu", ws_bytes, need);

@@ -198,7 +198,7 @@ void adjoint_tail(const StepArgs<T>& a, const Geom& g, const adj::Radii& r, T si
 }
 
 // pass 1 with a mask: the step kernel's mask variant in MODE_ADJ, built for the
-// stencil profiles (3,3,3,3) and (1,1,1,1)
+// stencil profiles (3,3,3,3), (3,1,3,1) and (1,1,1,1)
 template <typename S>
 hipError_t march_adj_masked(const StepArgs<typename S::math>& a, const int* r, hipStream_t s) {
   constexpr int NTX = Shape<S, MODE_ADJ>::ntx, NR = Shape<S, MODE_ADJ>::nr;
@@ -207,7 +207,10 @@ hipError_t march_adj_masked(const StepArgs<typename S::math>& a, const int* r, h
   if (r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3) {
     hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 3, 3, 3, 3, false, MODE_ADJ, true>), dim3(nblocks),
                        dim3(NTX * NR), 0, s, a);
-  } else if (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1) {
+  } else if (r[0] == 3 && r[1] == 1 && r[2] == 3 && r[3] == 1) {
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 3, 1, 3, 1, false, MODE_ADJ, true>), dim3(nblocks),
+                       dim3(NTX * NR), 0, s, a);
+} else if (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1) {
     hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 1, 1, 1, 1, false, MODE_ADJ, true>), dim3(nblocks),
                        dim3(NTX * NR), 0, s, a);
   } else {
@@ -300,11 +303,13 @@ hipError_t batch_launch(const BatchArgs<typename S::math>& b, int nbins, hipStre
 }
 
 // batches of walled lattices, or with solid-site masks on some lattices
-// (MASK): built for the stencil profiles (3,3,3,3) and (1,1,1,1)
+// (MASK): built for the stencil profiles (3,3,3,3), (3,1,3,1) and (1,1,1,1)
 template <typename S, int NTX, bool WALLS, bool MASK>
 hipError_t batch_special(const BatchArgs<typename S::math>& b, const int* r, int nbins, hipStream_t s) {
   if (r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3)
     return batch_launch<S, NTX, 3, 3, 3, 3, WALLS, MASK>(b, nbins, s);
+  if (r[0] == 3 && r[1] == 1 && r[2] == 3 && r[3] == 1)
+    return batch_launch<S, NTX, 3, 1, 3, 1, WALLS, MASK>(b, nbins, s);
   if (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1)
     return batch_launch<S, NTX, 1, 1, 1, 1, WALLS, MASK>(b, nbins, s);
   return hipErrorNotSupported;
@@ -393,9 +398,9 @@ hipError_t solid_prepare(const lbm_params& p, const Geom& g0, void* pops, const 
   return hipGetLastError();
 }
 
-// The fused step kernel with a mask, for the stencil profiles (3,3,3,3) and
-// (1,1,1,1); hipErrorNotSupported for the others (the caller then runs the
-// four passes).
+// The fused step kernel with a mask, for the stencil profiles (3,3,3,3),
+// (3,1,3,1) and (1,1,1,1); hipErrorNotSupported for the others (the caller
+// then runs the four passes).
 template <typename S>
 hipError_t solid_fused(const lbm_params& p, const Geom& g, const void* src, void* dst, const void* force, void* ws,
                        hipStream_t s) {
@@ -408,7 +413,10 @@ hipError_t solid_fused(const lbm_params& p, const Geom& g, const void* src, void
   if (r[0] == 3 && r[1] == 3 && r[2] == 3 && r[3] == 3) {
     hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 3, 3, 3, 3, false, MODE_STEP, true>), dim3(nblocks),
                        dim3(NTX * NR), 0, s, a);
-  } else if (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1) {
+  } else if (r[0] == 3 && r[1] == 1 && r[2] == 3 && r[3] == 1) {
+    hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 3, 1, 3, 1, false, MODE_STEP, true>), dim3(nblocks),
+                       dim3(NTX * NR), 0, s, a);
+} else if (r[0] == 1 && r[1] == 1 && r[2] == 1 && r[3] == 1) {
     hipLaunchKernelGGL((chromo_step_kernel<S, NTX, NR, 1, 1, 1, 1, false, MODE_STEP, true>), dim3(nblocks),
                        dim3(NTX * NR), 0, s, a);
   } else {

@@ -128,8 +128,10 @@ def test_batch_validation_and_layout():
              lbm.make_params(40, 30, "f32", **dict(prm, walls=True))]
     assert lbm.lbm_batch_pops_bytes(walls) > 0                      # all walled: allowed
     assert lbm.lbm_batch_pops_bytes([ps[0], walls[0]]) == 0          # periodic and walled mixed
-    odd = [lbm.make_params(64, 64, "f32", **dict(prm, walls=True, stencil=(3, 1, 3, 1)))]
-    assert lbm.lbm_batch_pops_bytes(odd) == 0                        # walled batches: 3333 or 1111
+    fast = [lbm.make_params(64, 64, "f32", **dict(prm, walls=True, stencil=(3, 1, 3, 1)))]
+    assert lbm.lbm_batch_pops_bytes(fast) > 0                        # walled: 3333, 3131, 1111
+    odd = [lbm.make_params(64, 64, "f32", **dict(prm, walls=True, stencil=(1, 3, 1, 3)))]
+    assert lbm.lbm_batch_pops_bytes(odd) == 0
     mixed = [ps[0], lbm.make_params(64, 64, "f64", **prm)]
     assert lbm.lbm_batch_pops_bytes(mixed) == 0
     radii = [ps[0], lbm.make_params(64, 64, "f32", **dict(prm, stencil=(1, 1, 1, 1)))]

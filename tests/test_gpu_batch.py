@@ -12,12 +12,12 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 
-def lattices(walls=False):
+def lattices(walls=False, stencil=(3, 3, 3, 3)):
     rng = np.random.default_rng(0)
     out = []
     for (nx, ny, Lam, sigma) in [(5, 7, 10.0, 0.005), (64, 64, 1.0, 0.001), (100, 60, 100.0, 0.01),
                                  (130, 40, 10.0, 0.01), (200, 200, 10.0, 0.005), (37, 300, 2.0, 0.02)]:
-        prm = Wk.base_params(Lambda=Lam, sigma=sigma)
+        prm = Wk.base_params(Lambda=Lam, sigma=sigma, stencil=stencil)
         prm["walls"] = walls
         y, x = np.mgrid[0:ny, 0:nx]
         d = np.hypot((x - (nx - 1) / 2.0) / 1.15, (y - (ny - 1) / 2.0) * 1.15)
@@ -136,11 +136,12 @@ def test_batch_with_force_fields_matches_single_lattices(storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
-def test_batch_of_walled_lattices_matches_single_lattices(storage):
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (3, 1, 3, 1)])
+def test_batch_of_walled_lattices_matches_single_lattices(storage, stencil):
     """A batch of walled lattices (rows 0 and ny-1 solid), with a force field
     on one of them: each evolves as it does alone, bit for bit, before and
     after the autotuner."""
-    lats = lattices(walls=True)
+    lats = lattices(walls=True, stencil=stencil)
     b = lbm.Batch(lats, storage=storage, device=DEV)
     nx3, ny3 = lats[3][0], lats[3][1]
     f3 = Wk.gaussian_bumps(nx3, ny3, nbumps=2, width=6.0, amplitude=2e-5, seed=3)
@@ -164,11 +165,12 @@ def test_batch_of_walled_lattices_matches_single_lattices(storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f64", "f16"])
-def test_batch_with_masks_matches_single_lattices(storage):
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (3, 1, 3, 1)])
+def test_batch_with_masks_matches_single_lattices(storage, stencil):
     """Solid-site masks on two lattices of a periodic batch (one also forced):
     every lattice evolves as alone, bit for bit, before and after the
     autotuner; fields read NaN at the solid sites."""
-    lats = lattices()
+    lats = lattices(stencil=stencil)
     masks = {4: Wk.circular_wall(200, 200, 97.0) | Wk.random_solid_sites(200, 200, 30, 4),
              2: Wk.random_solid_sites(100, 60, 25, 2)}
     f2 = Wk.gaussian_bumps(100, 60, nbumps=2, width=6.0, amplitude=2e-5, seed=2)

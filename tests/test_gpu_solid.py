@@ -161,7 +161,7 @@ def test_set_solid_argument_errors():
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (1, 1, 1, 1)])
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (3, 1, 3, 1), (1, 1, 1, 1)])
 @pytest.mark.parametrize("shape", [(97, 61), (300, 90)])
 def test_fused_masked_step_equals_four_passes(storage, stencil, shape):
     """The fused step kernel's mask variant and the four-pass kernels give the
@@ -246,10 +246,10 @@ def test_full_size_masked_emulsion_sampled_sites():
         sim.close()
 
 
-@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (3, 1, 3, 1)])
+@pytest.mark.parametrize("stencil", [(3, 3, 3, 3), (1, 3, 1, 3)])
 def test_one_step_options_with_mask_f64(stencil):
     """Fixed curvature, literal ghost equilibrium and no recolour on a masked
-    lattice (the fused mask variant for 3333, the four passes for 3131)."""
+    lattice (the fused mask variant for 3333, the four passes for 1313)."""
     nx, ny = 44, 38
     solid = container(nx, ny, 6, nobst=10)
     rng = np.random.default_rng(12)
