@@ -187,6 +187,29 @@ def test_recolour_matches_per_site_brute_force():
         assert max(abs(b[i] - float(Bpp[i, s])) for i in range(Q)) < 1e-16
 
 
+@pytest.mark.parametrize("Lam", [10.0, 100.0])
+def test_colour_index_of_the_printed_profile_pair(Lam):
+    """Sec. II prints the kinematic solution twice: as colour densities,
+    rho_R = rho_0R (1 + t)/2 with the equivalent rho_B = rho_0B (1 - t)/2, and,
+    substituted in the definition of the colour index, as rho^N = t (eq.
+    equ_rhoN), t = tanh(beta n.(r - u t)).  So the colour index of that pair is
+    t itself at every interior value, for any density ratio; the oracle's
+    initial state (which writes that pair for a given rho^N) reads back the
+    same through fields().  Without the 1/rho_0C normalisation of the
+    definition the pair's index is (Lambda (1 + t) - (1 - t))/(Lambda (1 + t) + (1 - t)),
+    off by O(1) for Lambda = 10, 100."""
+    d = dict(rho0_R=1.0, rho0_B=1.0 / Lam, alpha_B=0.5, alpha_R=1.0 - 0.5 / Lam)
+    p = O.Params(nx=7, ny=5, **d)
+    t = torch.linspace(-0.999, 0.999, 35, dtype=torch.float64)
+    rR = p.rho0_R * (1.0 + t) / 2.0
+    rB = p.rho0_B * (1.0 - t) / 2.0
+    assert float((O.colour_index(rR, rB, p) - t).abs().max()) < 4e-16
+    f = O.Oracle(p).init(t.reshape(5, 7)).fields()
+    assert float((f["rhoN"].reshape(-1) - t).abs().max()) < 1e-15  # through the summed populations
+    unnormalised = (rR - rB) / (rR + rB)
+    assert float((unnormalised - t).abs().max()) > 0.5
+
+
 @pytest.mark.parametrize("walls", [False, True])
 @pytest.mark.parametrize("shape", [(4, 4), (5, 6), (4, 3)])
 def test_streaming_matches_brute_force_bit_exact(walls, shape):
