@@ -63,28 +63,55 @@ def measured_traffic(storage):
     return d.get("bytes_per_launch")
 
 
-def cpu_baseline(seconds_target=15.0):
-    """The oracle (torch-CPU float64, untuned) on a 256x256 crop of the emulsion
-    workload: Lambda = 10, sigma = 0.005, drops with the emulsion's radius law."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_threads():
+    """Threads the oracle may use: the CPUs this process may run on, capped by
+    OMP_NUM_THREADS when that is set (the host's share of a shared machine)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(warmup=1, steps=3, drop_steps=1000):
+    """The oracle (torch-CPU float64, untuned) on the host: the full 4096^2
+    emulsion workload for `steps` steps after `warmup` (the benchmark's own
+    lattice, the value reported), and the 64^2 static drop for `drop_steps`."""
     import torch
     from oracle import chromo as O
     from paper_2005_04642_amd import workloads as Wk
-    threads = os.cpu_count() or 1
-    torch.set_num_threads(threads)
-    n = 256
-    cfg = Wk.config_emulsion(nx=n, ny=n)
-    rn = Wk.emulsion(n, n, ndrops=3, rmin=20.0, rmax=40.0, gap=6.0, seed=0)
-    o = O.Oracle(O.Params(nx=n, ny=n, **cfg["params"])).init(rn)
-    o.step(1)                      # warm-up
+    torch.set_num_threads(cpu_threads())
+    threads = torch.get_num_threads()
+    cfg = Wk.config_emulsion()
+    n = cfg["nx"]
+    o = O.Oracle(O.Params(nx=n, ny=n, **cfg["params"])).init(cfg["rhoN0"])
+    o.step(warmup)
     t0 = time.time()
-    steps = 0
-    while time.time() - t0 < seconds_target:
-        o.step(1)
-        steps += 1
+    o.step(steps)
     dt = time.time() - t0
+    del o
+    c1 = Wk.config_static_drop()
+    o = O.Oracle(O.Params(nx=c1["nx"], ny=c1["ny"], **c1["params"])).init(c1["rhoN0"])
+    t1 = time.time()
+    o.step(drop_steps)
+    dt1 = time.time() - t1
     return {"value": round(n * n * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": "%d steps of a %dx%d crop of the emulsion workload (3 drops, Lambda=10, sigma=0.005), "
-                      "torch-CPU float64, %.1f s" % (steps, n, n, dt)}
+            "cpu": cpu_model(),
+            "sample": "%dx%d emulsion workload (50 drops, Lambda=10, sigma=0.005), %d steps after %d warm-up, "
+                      "torch-CPU float64, %.1f s on %d threads" % (n, n, steps, warmup, dt, threads),
+            "static_drop": {"value": round(c1["nx"] * c1["ny"] * drop_steps / dt1 / 1e6, 4), "unit": "MLUPS",
+                            "sample": "%dx%d static drop, %d steps, %.1f s" % (c1["nx"], c1["ny"], drop_steps, dt1)}}
 
 
 def copy_roof(n, params, rn, torch, storage, steps=200):

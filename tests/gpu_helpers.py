@@ -6,6 +6,15 @@ from oracle import chromo as O
 from oracle.lattice import C, OPP, Q
 from paper_2005_04642_amd import lbm
 
+# FP32 bars of the parity tests: rho within 1e-5 relative; u within
+# FP32_FLOOR_FACTOR times the error FP32 storage alone leaves on the same
+# workload (the FP64 oracle with its state rounded to FP32 after every step).
+# The FP32 path adds its arithmetic to that floor: measured 1.6 to 6.0 floors
+# in u over the static drop, the channels, the emulsion crops and the batch
+# members.
+FP32_TOL_RHO = 1e-5
+FP32_FLOOR_FACTOR = 8.0
+
 
 def pull_gather(S, walls):
     """Pre-collision populations from a pull-layout buffer S [2, 9, ny, nx]:
@@ -110,3 +119,32 @@ def push_scatter_masked(P, solid):
         S[:, i] = np.where(dst_solid, P[:, OPP[i]], moved)
     S[:, :, solid] = 0.0
     return S
+
+
+def oracle_runs(nx, ny, params, rhoN0, steps, force=None):
+    """Fields of the FP64 oracle after ``steps`` steps, and of the same oracle
+    with its state rounded to FP32 after every step (FP64 arithmetic
+    otherwise): the second is the error FP32 storage alone causes, the floor
+    an FP32 path is measured against."""
+    p = oracle_params(nx, ny, params)
+    f = None if force is None else torch.as_tensor(force)
+    exact = O.Oracle(p, force=f).init(rhoN0)
+    rounded = O.Oracle(p, force=f).init(rhoN0)
+    rounded.R, rounded.B = rounded.R.float().double(), rounded.B.float().double()
+    for _ in range(steps):
+        exact.step(1)
+        rounded.step(1)
+        rounded.R, rounded.B = rounded.R.float().double(), rounded.B.float().double()
+    return ({k: v.numpy() for k, v in exact.fields().items()},
+            {k: v.numpy() for k, v in rounded.fields().items()})
+
+
+def field_errors(f, fo, walls=False):
+    """e_rho = max |d rho| / rho and e_u = max |d u| / max |u| over fluid sites
+    (NaN marks solid sites and is skipped)."""
+    a = {k: fluid(np.asarray(v, dtype=np.float64), walls) for k, v in f.items()}
+    b = {k: fluid(np.asarray(v, dtype=np.float64), walls) for k, v in fo.items()}
+    e_rho = float(np.nanmax(np.abs(a["rho"] - b["rho"]) / b["rho"]))
+    du = np.hypot(a["ux"] - b["ux"], a["uy"] - b["uy"])
+    e_u = float(np.nanmax(du) / np.nanmax(np.hypot(b["ux"], b["uy"])))
+    return e_rho, e_u

@@ -196,3 +196,70 @@ def test_batch_with_masks_matches_single_lattices(storage, stencil):
     rho = b.fields(4)["rho"].cpu().numpy()
     assert np.all(np.isnan(rho[masks[4]])) and np.all(np.isfinite(rho[~masks[4]]))
     b.close()
+
+
+# ---------------------------------------------------------------------------
+# every member of a batch against the oracle (FP64 and FP32): density ratios
+# 1, 10 and 100 on lattices of sides 64 and 128, and one ragged lattice whose
+# 203 columns split into two uneven strips
+# ---------------------------------------------------------------------------
+
+ORACLE_STEPS = 200
+
+
+def ellipse(nx, ny, aspect, width=2.0):
+    """Centred axis-aligned elliptic drop, tanh(d / width) of its approximate
+    signed distance, semi-axes (min(nx, ny)/4) sqrt(AR) and .../sqrt(AR)."""
+    cx, cy = (nx - 1) / 2.0, (ny - 1) / 2.0
+    r0 = min(nx, ny) / 4.0
+    a, b = r0 * np.sqrt(aspect), r0 / np.sqrt(aspect)
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    q = np.sqrt(((x - cx) / a) ** 2 + ((y - cy) / b) ** 2)
+    return np.tanh((1.0 - q) * np.sqrt(a * b) / width)
+
+
+def oracle_lattices():
+    out = []
+    for (nx, ny, Lam, sigma, ar) in [(64, 64, 1.0, 0.02, 1.3), (64, 64, 10.0, 0.005, 1.1),
+                                     (64, 64, 100.0, 0.01, 1.45), (128, 128, 1.0, 0.001, 1.2),
+                                     (128, 128, 10.0, 0.05, 1.5), (128, 128, 100.0, 0.003, 1.0),
+                                     (203, 77, 10.0, 0.01, 1.4)]:
+        out.append((nx, ny, Wk.base_params(Lambda=Lam, sigma=sigma), ellipse(nx, ny, ar)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def batch_oracle():
+    from gpu_helpers import oracle_runs
+    lats = oracle_lattices()
+    return lats, [oracle_runs(nx, ny, prm, rn, ORACLE_STEPS) for nx, ny, prm, rn in lats]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_batch_members_against_oracle(storage, batch_oracle):
+    """After 200 steps of one batch, each member's fields against the FP64
+    oracle run on that lattice alone: FP64 within 1e-11 (u: of max |u|, or 1e-14
+    absolute); FP32 rho within 1e-5 and u within FP32_FLOOR_FACTOR times the
+    member's FP32 storage floor."""
+    from gpu_helpers import field_errors
+    from gpu_helpers import FP32_TOL_RHO, FP32_FLOOR_FACTOR
+    lats, runs = batch_oracle
+    b = lbm.Batch(lats, storage=storage, device=DEV)
+    b.step(ORACLE_STEPS)
+    for k, ((nx, ny, prm, _), (fo, fr)) in enumerate(zip(lats, runs)):
+        f = {key: v.detach().cpu().numpy() for key, v in b.fields(k).items()}
+        e_rho, e_u = field_errors(f, fo)
+        floor = field_errors(fr, fo)
+        umax = float(np.max(np.hypot(fo["ux"], fo["uy"])))
+        print("batch member %d (%dx%d, Lambda %g, sigma %g) %s: e_rho %.3e e_u %.3e (fp32 storage floor %.3e %.3e; "
+              "max|u| %.3e)" % (k, nx, ny, prm["rho0_R"] / prm["rho0_B"], prm["sigma"], storage, e_rho, e_u,
+                                floor[0], floor[1], umax))
+        if storage == "f64":
+            # u relative to max |u|, or absolute: a drop with sigma = 0.001 has a
+            # micro-current of 5e-5, carried by populations of order one whose
+            # FP64 ulp is 2e-16, so 1e-11 of it is a few ulps (measured 7e-16)
+            assert e_rho < 1e-11 and (e_u < 1e-11 or e_u * umax < 1e-14), k
+        else:
+            assert e_rho < FP32_TOL_RHO, k
+            assert e_u < FP32_FLOOR_FACTOR * floor[1], (k, e_u, floor[1])
+    b.close()
