@@ -148,6 +148,20 @@ int lbm_init(const lbm_params* p, const void* rhoN0, const void* force,
  * last step are written there (2 doubles, device).  Enqueued on `stream`. */
 int lbm_step(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t stream);
 
+/* lbm_step for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same steps, and the same FP64 masses bit for bit, but the mass reduction's
+ * per-block partial sums go to a static device array of the library (512
+ * pairs of doubles, 8 KiB, one copy per GPU, resolved by lbm_init for its
+ * device) instead of the handle's workspace.  The call allocates nothing and
+ * calls no allocating routine.  The array is shared by every call on the same
+ * GPU and keeps the last call's contents; nothing in it needs to start at
+ * zero (each partial is written before it is read), but calls that overlap in
+ * time on one GPU (different streams or threads) race on it.  Every lattice
+ * lbm_validate_params accepts fits: the reduction uses 512 partial pairs at
+ * any size.  Errors as lbm_step (LBM_EINVAL for a NULL handle or nsteps < 0). */
+int lbm_step_static(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t stream);
+
 /* Macroscopic fields of the current state (Sec. II, force-adjusted
  * observables): rho, u = (sum f c + G/2)/rho, rho^N.  Each output is NULL
  * (skipped) or a device [ny][nx] array of the arithmetic type; solid rows are

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <queue>
 #include <string>
@@ -129,6 +130,36 @@ chromo::Geom plan(const lbm_params& p, int ncu, int ntx) {
   return g;
 }
 
+// ---------------------------------------------------------------------------
+// Device scratch of lbm_step_static: the FP64 per-block partial sums of the
+// mass reduction (MASS_BLOCKS pairs, 8 KiB), one copy on every GPU the library
+// runs on, held until the process ends.  Host code never passes the array's
+// name to a kernel (on the host it is only a stand-in for the symbol): it
+// uses the device address hipGetSymbolAddress returns for each device.
+// ---------------------------------------------------------------------------
+constexpr int SCRATCH_PAIRS = MASS_BLOCKS;
+static __device__ __align__(256) double scratch[2 * SCRATCH_PAIRS];
+
+std::mutex g_scratch_mu;
+std::vector<double*> g_scratch_ptr;  // indexed by device ordinal
+
+// Address of the current device's scratch, looked up once per device (the
+// device must be current).  LBM_OK or LBM_EHIP.
+int scratch_of_device(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (dev < 0) return fail(LBM_EHIP, "invalid device %d", dev);
+  if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(LBM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
 }  // namespace
 
 struct lbm_handle {
@@ -142,6 +173,7 @@ struct lbm_handle {
   chromo::Geom g;      // forward step kernel
   chromo::Geom g_adj;  // adjoint pass 1 (workgroup shape ntx_for(storage, true))
   const chromo::Ops* ops;
+  double* scratch = nullptr;             // this device's static scratch (lbm_step_static)
   const unsigned char* solid = nullptr;  // device mask of solid sites (lbm_set_solid), or null
   void* solid_ws = nullptr;              // its field planes
 };
@@ -220,6 +252,9 @@ int lbm_init(const lbm_params* p, const void* rhoN0, const void* force, void* po
   int dev = 0, ncu = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  double* scr = nullptr;
+  st = scratch_of_device(dev, &scr);
+  if (st != LBM_OK) return st;
 
   lbm_handle* h = new (std::nothrow) lbm_handle;
   if (!h) return fail(LBM_EINVAL, "out of host memory");
@@ -234,6 +269,7 @@ int lbm_init(const lbm_params* p, const void* rhoN0, const void* force, void* po
   h->g = plan(*p, ncu > 0 ? ncu : 1, chromo::ntx_for(p->storage));
   h->g_adj = plan(*p, ncu > 0 ? ncu : 1, chromo::ntx_for(p->storage, true));
   h->ops = ops_of(p->storage);
+  h->scratch = scr;
 
   hipError_t e = h->ops->init(*p, h->g, rhoN0, pops_a, stream);
   if (e != hipSuccess) {
@@ -251,6 +287,18 @@ int lbm_step(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t str
   int st = step_impl(h, nsteps, stream);
   if (st != LBM_OK || !mass_RB_dev) return st;
   return mass_into(h, mass_RB_dev, stream);
+}
+
+int lbm_step_static(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t stream) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  if (!h->scratch) return fail(LBM_EHIP, "no device scratch for this handle");
+  static_assert(MASS_BLOCKS <= SCRATCH_PAIRS, "the mass reduction's partials must fit the scratch");
+  int st = step_impl(h, nsteps, stream);
+  if (st != LBM_OK || !mass_RB_dev) return st;
+  HIP_TRY(h->ops->mass(h->p, h->g, h->pops[h->live], h->scratch, mass_RB_dev, stream));
+  return LBM_OK;
 }
 
 int lbm_fields(lbm_handle* h, void* rho, void* ux, void* uy, void* rhoN, double* mass_RB_dev,

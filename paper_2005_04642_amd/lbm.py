@@ -24,7 +24,7 @@ LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR, LBM_FLAG_MASK_PASSE
 
 # every symbol the header declares
 EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_workspace_bytes", "lbm_init",
-            "lbm_step", "lbm_fields", "lbm_masses_host", "lbm_adjoint_workspace_bytes", "lbm_adjoint_step",
+            "lbm_step", "lbm_step_static", "lbm_fields", "lbm_masses_host", "lbm_adjoint_workspace_bytes", "lbm_adjoint_step",
             "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_solid_workspace_bytes", "lbm_set_solid",
             "lbm_current_pops", "lbm_set_pops", "lbm_step_count",
             "lbm_destroy", "lbm_last_error", "lbm_batch_pops_bytes", "lbm_batch_offsets", "lbm_batch_workspace_bytes",
@@ -79,6 +79,8 @@ def load_library(path=None):
     lib.lbm_init.restype = ctypes.c_int
     lib.lbm_step.argtypes = [vp, i32, vp, vp]
     lib.lbm_step.restype = ctypes.c_int
+    lib.lbm_step_static.argtypes = [vp, i32, vp, vp]
+    lib.lbm_step_static.restype = ctypes.c_int
     lib.lbm_fields.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     lib.lbm_fields.restype = ctypes.c_int
     lib.lbm_masses_host.argtypes = [vp, dp, vp]
@@ -201,6 +203,11 @@ def lbm_init(p, rhoN0_ptr, force_ptr, pops_a_ptr, pops_b_ptr, ws_ptr, ws_bytes, 
 def lbm_step(h, nsteps, mass_ptr, stream):
     lib = load_library()
     return _check(lib, lib.lbm_step(h, nsteps, mass_ptr, stream))
+
+
+def lbm_step_static(h, nsteps, mass_ptr, stream):
+    lib = load_library()
+    return _check(lib, lib.lbm_step_static(h, nsteps, mass_ptr, stream))
 
 
 def lbm_fields(h, rho_ptr, ux_ptr, uy_ptr, rhoN_ptr, mass_ptr, stream):
