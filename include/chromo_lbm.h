@@ -109,7 +109,9 @@ typedef struct lbm_handle lbm_handle;
 
 /* Host-only check of a parameter set (no GPU call).  LBM_OK or LBM_EINVAL.
  * Rejects: nx, ny < 1; walls with fewer than 1 fluid row; unknown storage;
- * a population buffer of 4 GiB or more; a stencil radius not in {1, 3}; non-positive densities;
+ * one lattice row of a population buffer of 4 GiB or more (the whole buffer may
+ * be larger: the kernels address it row by row); more than 2^30 sites; more
+ * than 65535 rows; a stencil radius not in {1, 3}; non-positive densities;
  * |(1-alpha_B) - Lambda (1-alpha_R)| > 1e-9 (1-alpha_B) (Sec. II density-ratio
  * relation); alpha outside [0, 1); nu <= 0 (lambda_3 = 2/(6 nu + 1) must lie in
  * (0, 2)); lambda6, lambda7 outside (0, 2); eps_n <= 0. */
@@ -188,7 +190,9 @@ int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream);
 /* Bytes of device workspace lbm_adjoint_step needs (256-byte aligned): the
  * saved intermediates and adjoint fields (39 planes of nx*ny values of the
  * arithmetic type) and the FP64 partial sums of dL/dsigma.  0 if the adjoint is
- * not provided for these parameters. */
+ * not provided for these parameters or the lattice has more than 102,261,126
+ * sites (the adjoint indexes its workspace planes with 32-bit integers; the
+ * adjoint entry points return LBM_EINVAL on such a handle). */
 size_t lbm_adjoint_workspace_bytes(const lbm_params* p);
 
 /* One step backwards.  pops_t: the state the step starts from (a population
@@ -311,7 +315,9 @@ void lbm_batch_destroy(lbm_batch* b);
 
 /* Bytes of device workspace lbm_set_solid needs: 14 planes of nx*ny values of
  * the arithmetic type and nx*ny bytes of bounce bits (256-byte multiple); 0
- * where masks are not provided. */
+ * where masks are not provided, which includes population buffers of 4 GiB or
+ * more (the masked gather addresses the whole buffer through one 32-bit
+ * offset; lbm_set_solid and lbm_batch_set_solid return LBM_EINVAL there). */
 size_t lbm_solid_workspace_bytes(const lbm_params* p);
 
 /* Give the handle a mask of solid sites.  solid_dev: device [ny][nx] bytes,

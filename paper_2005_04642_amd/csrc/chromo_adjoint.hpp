@@ -660,9 +660,9 @@ __global__ void __launch_bounds__(256) rhoN_adjoint_kernel(const void* popsv, Ge
     cols.p = (xs == g.nx - 1 ? 0 : xs + 1) * E;
     typename S::W w[S::NW];
     if constexpr (M) {
-      gather_words<S, false, true>(make_rsrc<S>(popsv, g.plane), g, ys, cols, w, bounce_bits_at(bnc, g, ys, xs));
+      gather_words<S, false, true>(popsv, g, ys, cols, w, bounce_bits_at(bnc, g, ys, xs));
     } else {
-      gather_words_any<S>(make_rsrc<S>(popsv, g.plane), g, ys, cols, w);
+      gather_words_any<S>(popsv, g, ys, cols, w);
     }
     T R[9], B[9];
     decode<S>(w, c, R, B);

@@ -40,6 +40,14 @@ int fail(int code, const char* fmt, ...) {
 
 bool radius_ok(int r) { return r == 1 || r == 3; }
 
+constexpr long long MAX_SITES = 1LL << 30;  // nx ny: 32-bit indices of two field planes
+constexpr int MAX_ROWS = 65535;             // grid dimension y of the per-row kernels
+// whole population buffers addressed through one buffer resource (the mask
+// variant of the gather and the four-pass masked step) stay below 2^32 bytes
+constexpr double WHOLE_BUFFER_LIMIT = 4294967296.0;
+// the adjoint indexes up to 21 planes of its workspace with 32-bit integers
+constexpr long long ADJ_MAX_SITES = 2147483647LL / 21;
+
 int halo(const lbm_params& p) { return p.stencil[0] + p.stencil[1] + p.stencil[3]; }
 
 // Stencil profiles with instantiations of the step kernel's mask variant, the
@@ -77,9 +85,15 @@ int validate(const lbm_params* p) {
   if (p->walls_y && p->ny < 3) return fail(LBM_EINVAL, "walls need ny >= 3 (one fluid row)");
   if (p->storage < LBM_STORAGE_F64 || p->storage > LBM_STORAGE_BF16_OFS)
     return fail(LBM_EINVAL, "storage %d not provided by this build", p->storage);
-  const double bytes = (double)words_of(p->storage) * word_bytes_of(p->storage) * (double)p->nx * (double)p->ny;
-  if (bytes >= 4294967296.0)
-    return fail(LBM_EINVAL, "lattice too large: one population buffer must stay below 4 GiB");
+  // the step kernels address each lattice row through a buffer resource of its
+  // own (byte offsets below 2^32 within a row); field planes are indexed with
+  // 32-bit integers (two planes for a force field); rows index grid dimension y
+  const double row_bytes = (double)words_of(p->storage) * word_bytes_of(p->storage) * (double)p->nx;
+  if (row_bytes >= 4294967296.0)
+    return fail(LBM_EINVAL, "lattice too wide: one row of a population buffer must stay below 4 GiB");
+  if ((double)p->nx * (double)p->ny > (double)MAX_SITES)
+    return fail(LBM_EINVAL, "lattice too large: at most %lld sites", (long long)MAX_SITES);
+  if (p->ny > MAX_ROWS) return fail(LBM_EINVAL, "lattice too tall: at most %d rows", MAX_ROWS);
   for (int k = 0; k < 4; ++k)
     if (!radius_ok(p->stencil[k])) return fail(LBM_EINVAL, "stencil radius %d not in {1,3}", p->stencil[k]);
   if (!(p->rho0_R > 0.0) || !(p->rho0_B > 0.0)) return fail(LBM_EINVAL, "densities must be positive");
@@ -332,6 +346,7 @@ int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream) {
 size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
   if (!ops_of(p->storage)->adjoint) return 0;
+  if ((long long)p->nx * p->ny > ADJ_MAX_SITES) return 0;
   const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
   size_t bytes = (size_t)chromo::adj::WS_PLANES * (size_t)p->nx * (size_t)p->ny * elem;
   bytes = (bytes + 255) / 256 * 256;
@@ -343,6 +358,9 @@ static int adjoint_supported(const lbm_handle* h) {
   if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no adjoint of the streaming-only test mode");
   if (h->solid && !special_profile(h->p.stencil))
     return fail(LBM_ENOTIMPL, "the adjoint with a solid-site mask is built for stencil profiles 3333, 3131 and 1111");
+  if ((long long)h->p.nx * h->p.ny > ADJ_MAX_SITES)
+    return fail(LBM_EINVAL, "the adjoint takes at most %lld sites (32-bit indices of its workspace planes)",
+                ADJ_MAX_SITES);
   return LBM_OK;
 }
 
@@ -396,6 +414,7 @@ int lbm_init_adjoint(lbm_handle* h, const void* rhoN0, const void* adj_pops0, vo
 size_t lbm_solid_workspace_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
   if (!ops_of(p->storage)->solid_step || p->walls_y || (p->flags & LBM_FLAG_STREAM_ONLY)) return 0;
+  if ((double)lbm_pops_bytes(p) >= WHOLE_BUFFER_LIMIT) return 0;
   const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
   const size_t plane = (size_t)p->nx * (size_t)p->ny;
   return (chromo::solid::bits_offset(plane, elem) + plane + 255) / 256 * 256;
@@ -409,6 +428,8 @@ int lbm_set_solid(lbm_handle* h, const uint8_t* solid_dev, void* workspace, size
   if (h->p.walls_y) return fail(LBM_EINVAL, "with a solid-site mask walls_y must be 0 (put the wall rows in the mask)");
   if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no solid-site mask in the streaming-only test mode");
   if (h->p.nx < 4 || h->p.ny < 4) return fail(LBM_EINVAL, "a solid-site mask needs nx, ny >= 4");
+  if ((double)lbm_pops_bytes(&h->p) >= WHOLE_BUFFER_LIMIT)
+    return fail(LBM_EINVAL, "with a solid-site mask one population buffer must stay below 4 GiB");
   const size_t need = lbm_solid_workspace_bytes(&h->p);
   if (ws_bytes < need) return fail(LBM_EINVAL, "solid workspace too small: %zu < %zu", ws_bytes, need);
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
@@ -833,6 +854,8 @@ int lbm_batch_set_solid(lbm_batch* b, int32_t k, const uint8_t* solid_dev, void*
   if (!special_profile(p.stencil))
     return fail(LBM_ENOTIMPL, "masks in batches are built for stencil profiles 3333, 3131 and 1111");
   if (p.nx < 4 || p.ny < 4) return fail(LBM_EINVAL, "a solid-site mask needs nx, ny >= 4");
+  if ((double)lbm_pops_bytes(&p) >= WHOLE_BUFFER_LIMIT)
+    return fail(LBM_EINVAL, "with a solid-site mask one population buffer must stay below 4 GiB");
   const size_t need = lbm_solid_workspace_bytes(&p);
   if (ws_bytes < need) return fail(LBM_EINVAL, "solid workspace too small: %zu < %zu", ws_bytes, need);
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");

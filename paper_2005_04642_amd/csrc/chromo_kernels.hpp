@@ -279,11 +279,42 @@ __device__ __forceinline__ void encode(const T* R, const T* B, const Coef<T>& c,
   }
 }
 
+// Buffer resource over a whole population buffer below 2^32 bytes (the host
+// keeps masked lattices' buffers so: the mask variant of the gather lets a
+// lane choose between rows).
 template <typename S>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, int plane) {
-  // < 2^32 bytes (checked on the host)
   const unsigned bytes = (unsigned)S::NW * (unsigned)plane * (unsigned)sizeof(typename S::W);
   return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
+
+// Buffer resource over one lattice row of a population buffer: a 64-bit base
+// at the row's first word and the row's NW nx words as its extent, so word q of
+// the site in column x sits at byte offset q pb + x sizeof(W).  Offsets then
+// stay within one row (below 2^32 bytes for every lattice the host accepts)
+// whatever the size of the whole buffer.  The row is wave-uniform, so the
+// base is formed in scalar registers.  Used only for buffers of 2^32 bytes or
+// more: a buffer below that goes through one resource with the row in the
+// scalar offset, which is faster for the stores (4096^2 FP32 step: 0.540 ms
+// against 0.595 ms with row-based resources, the same addresses).
+template <typename S>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* buf, const Geom& g, int row) {
+  const char* base = static_cast<const char*>(buf) + (size_t)(unsigned)row * (size_t)g.rb;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)g.rb, 0x00020000);
+}
+
+// Address a buffer of format S through one resource (the row in the scalar
+// offset) rather than row by row?  For the plain float formats when the whole
+// buffer is below 2^32 bytes; the 16-bit offset formats always go row by row
+// (their VALU-bound step runs 0.415 ms on 4096^2 that way, 0.447 ms with both
+// paths in the kernel).
+template <typename S>
+__device__ __forceinline__ bool one_resource(const Geom& g) {
+  if constexpr (S::NW == 10) {
+    return false;
+  } else {
+    return (unsigned long long)g.rb * (unsigned long long)g.ny < (1ull << 32);
+  }
 }
 
 // Column byte offsets of one thread: x - 1, x, x + 1 (periodic).
@@ -294,15 +325,16 @@ struct Cols {
 // Pull-streaming gather of the words of site (x, p): the word of link i comes
 // from the source site r - c_i, or, when r - c_i is a solid row, from the
 // reversed link's word at r itself (half-way bounce-back).  p is wave-uniform,
-// so every word / row offset is scalar.  WALLS: rows 0 and ny - 1 are solid
-// (else y is periodic).
+// so the three rows' resources and every word offset are scalar.  WALLS: rows
+// 0 and ny - 1 are solid (else y is periodic).
 //
 // MASK (solid sites anywhere, y periodic): the link's bounce bit of the site
 // (bits: the site's byte of bounce bits) chooses, per lane, between the source
-// word and the reversed link's word at the site itself; the whole byte offset
-// then goes in the per-lane offset.
+// word and the reversed link's word at the site itself; the whole byte offset,
+// row included, then goes in the per-lane offset of one resource over the
+// whole buffer.
 template <typename S, bool WALLS, bool MASK = false>
-__device__ __forceinline__ void gather_words(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
+__device__ __forceinline__ void gather_words(const void* buf, const Geom& g, int p, const Cols& x,
                                              typename S::W out[S::NW], unsigned bits = 0) {
   int rm = p - 1, rp = p + 1;
   bool bm = false, bp = false;
@@ -313,24 +345,50 @@ __device__ __forceinline__ void gather_words(__amdgpu_buffer_rsrc_t src, const G
     if (rm < 0) rm += g.ny;
     if (rp >= g.ny) rp -= g.ny;
   }
-  const unsigned ro = (unsigned)p * g.rb, rom = (unsigned)rm * g.rb, rop = (unsigned)rp * g.rb;
+  if constexpr (MASK) {
+    const __amdgpu_buffer_rsrc_t src = make_rsrc<S>(buf, g.plane);
+    const unsigned ro = (unsigned)p * g.rb, rom = (unsigned)rm * g.rb, rop = (unsigned)rp * g.rb;
 #pragma unroll
-  for (int q = 0; q < S::NW; ++q) {
-    const int i = word_link<S>(q);
-    const int dy = link_cy(i), dx = link_cx(i);
-    const bool bounce = WALLS && ((dy == 1 && bm) || (dy == -1 && bp));
-    const unsigned soff = bounce ? (unsigned)word_bounce<S>(q) * g.pb + ro
-                                 : (unsigned)q * g.pb + (dy == 1 ? rom : (dy == -1 ? rop : ro));
-    const int voff = bounce ? x.o : (dx == 1 ? x.m : (dx == -1 ? x.p : x.o));
-    if constexpr (MASK) {
+    for (int q = 0; q < S::NW; ++q) {
+      const int i = word_link<S>(q);
+      const int dy = link_cy(i), dx = link_cx(i);
+      const unsigned soff = (unsigned)q * g.pb + (dy == 1 ? rom : (dy == -1 ? rop : ro));
+      const int voff = dx == 1 ? x.m : (dx == -1 ? x.p : x.o);
       if (i != 0) {
         const unsigned own = (unsigned)x.o + (unsigned)word_bounce<S>(q) * g.pb + ro;
         const unsigned off = ((bits >> (i - 1)) & 1u) ? own : (unsigned)voff + soff;
         out[q] = load_word<typename S::W>(src, (int)off, 0);
-        continue;
+      } else {
+        out[q] = load_word<typename S::W>(src, voff, (int)soff);
       }
     }
-    out[q] = load_word<typename S::W>(src, voff, (int)soff);
+  } else if (one_resource<S>(g)) {
+    const __amdgpu_buffer_rsrc_t src = make_rsrc<S>(buf, g.plane);
+    const unsigned ro = (unsigned)p * g.rb, rom = (unsigned)rm * g.rb, rop = (unsigned)rp * g.rb;
+#pragma unroll
+    for (int q = 0; q < S::NW; ++q) {
+      const int i = word_link<S>(q);
+      const int dy = link_cy(i), dx = link_cx(i);
+      const bool bounce = WALLS && ((dy == 1 && bm) || (dy == -1 && bp));
+      const unsigned soff = bounce ? (unsigned)word_bounce<S>(q) * g.pb + ro
+                                   : (unsigned)q * g.pb + (dy == 1 ? rom : (dy == -1 ? rop : ro));
+      const int voff = bounce ? x.o : (dx == 1 ? x.m : (dx == -1 ? x.p : x.o));
+      out[q] = load_word<typename S::W>(src, voff, (int)soff);
+    }
+  } else {
+    const __amdgpu_buffer_rsrc_t r0 = row_rsrc<S>(buf, g, p);
+    const __amdgpu_buffer_rsrc_t rM = row_rsrc<S>(buf, g, rm);
+    const __amdgpu_buffer_rsrc_t rP = row_rsrc<S>(buf, g, rp);
+#pragma unroll
+    for (int q = 0; q < S::NW; ++q) {
+      const int i = word_link<S>(q);
+      const int dy = link_cy(i), dx = link_cx(i);
+      const bool bounce = WALLS && ((dy == 1 && bm) || (dy == -1 && bp));
+      const unsigned soff = (unsigned)(bounce ? word_bounce<S>(q) : q) * g.pb;
+      const int voff = bounce ? x.o : (dx == 1 ? x.m : (dx == -1 ? x.p : x.o));
+      const __amdgpu_buffer_rsrc_t r = bounce ? r0 : (dy == 1 ? rM : (dy == -1 ? rP : r0));
+      out[q] = load_word<typename S::W>(r, voff, (int)soff);
+    }
   }
 }
 
@@ -350,7 +408,7 @@ __device__ __forceinline__ unsigned bounce_bits_at(__amdgpu_buffer_rsrc_t r, con
 }
 
 template <typename S>
-__device__ __forceinline__ void gather_words_any(__amdgpu_buffer_rsrc_t src, const Geom& g, int p, const Cols& x,
+__device__ __forceinline__ void gather_words_any(const void* src, const Geom& g, int p, const Cols& x,
                                                  typename S::W out[S::NW]) {
   if (g.walls) {
     gather_words<S, true>(src, g, p, x, out);
@@ -543,7 +601,7 @@ __device__ __forceinline__ double rsqrt_pos(double x) { return 1.0 / sqrt(x); }
 // MASK: a site without mass (a solid site, whose words encode zero populations)
 // stores zero populations.
 template <typename S, typename T, int MODE, bool MASK = false>
-__device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buffer_rsrc_t dst, const T* f, T rR,
+__device__ __forceinline__ void collide_store(const StepArgs<T>& a, void* dst, const T* f, T rR,
                                               T rB, T ux, T uy, T Gx, T Gy, T inv_rho, T dPx, T dPy, T theta,
                                               T rhoN, T mx, T my, int p, const Thread& t) {
   const Coef<T>& c = a.c;
@@ -682,17 +740,24 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, __amdgpu_buf
   }
   typename S::W w[S::NW];
   encode<S>(R, B, c, w);
-  const unsigned ro = (unsigned)p * a.g.rb;
+  if (one_resource<S>(a.g)) {
+    const __amdgpu_buffer_rsrc_t dr = make_rsrc<S>(dst, a.g.plane);
+    const unsigned ro = (unsigned)p * a.g.rb;
 #pragma unroll
-  for (int q = 0; q < S::NW; ++q) store_word<typename S::W>(w[q], dst, t.cols.o, (int)(q * a.g.pb + ro));
+    for (int q = 0; q < S::NW; ++q) store_word<typename S::W>(w[q], dr, t.cols.o, (int)(q * a.g.pb + ro));
+  } else {
+    const __amdgpu_buffer_rsrc_t dr = row_rsrc<S>(dst, a.g, p);
+#pragma unroll
+    for (int q = 0; q < S::NW; ++q) store_word<typename S::W>(w[q], dr, t.cols.o, (int)(q * a.g.pb));
+  }
 }
 
 // One march iteration; S = it mod 4 selects the register-ring slots.  tM and
 // tU track the virtual rows of the next band-M gather and of band U.
 template <int S, typename ST, typename T, int NTX, int NR, int RG, int RK, int RP, int RU, bool WALLS, int MODE,
           bool MASK = false>
-__device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, __amdgpu_buffer_rsrc_t src,
-                                           __amdgpu_buffer_rsrc_t dst, Smem<T, NTX, Pipe<NR>::RING>& sm,
+__device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, const void* src, void* dst,
+                                           Smem<T, NTX, Pipe<NR>::RING>& sm,
                                            March<ST>& st, const Thread& t, RowTrack<WALLS>& tM,
                                            RowTrack<WALLS>& tU) {
   using PP = Pipe<NR>;
@@ -843,8 +908,8 @@ __device__ __forceinline__ void march_tile(const StepArgs<typename ST::math>& a,
   using PP = Pipe<NR>;
   constexpr int H = RG + RK + RU;
   const Geom& g = a.g;
-  const __amdgpu_buffer_rsrc_t src = make_rsrc<ST>(a.src, g.plane);
-  const __amdgpu_buffer_rsrc_t dst = make_rsrc<ST>(MODE != MODE_STEP ? a.src : a.dst, g.plane);
+  const void* src = a.src;
+  void* dst = MODE != MODE_STEP ? const_cast<void*>(a.src) : a.dst;  // no store outside MODE_STEP
   Thread t;
   t.tx = threadIdx.x % NTX;
   t.ty = __builtin_amdgcn_readfirstlane(threadIdx.x / NTX);
@@ -980,7 +1045,7 @@ __global__ void __launch_bounds__(256) stream_only_kernel(const void* src, void*
   cols.m = (x == 0 ? g.nx - 1 : x - 1) * E;
   cols.p = (x == g.nx - 1 ? 0 : x + 1) * E;
   W v[S::NW];
-  gather_words_any<S>(make_rsrc<S>(src, g.plane), g, p, cols, v);
+  gather_words_any<S>(src, g, p, cols, v);
   W* d = static_cast<W*>(dst) + (size_t)p * S::NW * g.nx + x;
 #pragma unroll
   for (int q = 0; q < S::NW; ++q) d[q * g.nx] = v[q];

@@ -314,8 +314,7 @@ __global__ void __launch_bounds__(256) collide_kernel(StepArgs<typename S::math>
   t.own = true;
   t.cols.o = x * (int)sizeof(W);
   t.cols.m = t.cols.p = t.cols.o;
-  const __amdgpu_buffer_rsrc_t dst = make_rsrc<S>(a.dst, g.plane);
-  collide_store<S, T, MODE_STEP>(a, dst, f, rR, rB, o[P_UX * P], o[P_UY * P], o[P_GX * P], o[P_GY * P],
+  collide_store<S, T, MODE_STEP>(a, a.dst, f, rR, rB, o[P_UX * P], o[P_UY * P], o[P_GX * P], o[P_GY * P],
                                  recip(rR + rB), dPx, dPy, theta, o[P_RN * P], o[P_MX * P], o[P_MY * P], y, t);
 }
 

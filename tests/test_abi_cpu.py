@@ -56,19 +56,35 @@ def test_validate_rejects_bad_stencil_and_huge_and_wall_height():
     p.stencil[2] = 2
     assert lbm.lbm_validate_params(p)[0] == lbm.LBM_EINVAL
     p = good()
-    p.nx, p.ny = 20000, 20000
+    p.nx, p.ny = 40000, 40000          # more than 2^30 sites
+    assert lbm.lbm_validate_params(p)[0] == lbm.LBM_EINVAL
+    p = good()
+    p.nx, p.ny = 16, 70000             # more rows than the grid's y dimension holds
+    assert lbm.lbm_validate_params(p)[0] == lbm.LBM_EINVAL
+    p = lbm.make_params(30_000_000, 2, "f64", **Wk.base_params(Lambda=10.0))  # one row of 4.3 GB
     assert lbm.lbm_validate_params(p)[0] == lbm.LBM_EINVAL
     p = good()
     p.walls_y, p.ny = 1, 2
     assert lbm.lbm_validate_params(p)[0] == lbm.LBM_EINVAL
 
 
-def test_16bit_formats_allow_larger_lattices():
-    """One population buffer must stay below 4 GiB: 72 B per site (F32) versus
-    40 B per site (16-bit offset formats)."""
-    for storage, ok in (("f32", False), ("f16", True), ("bf16", True), ("f64", False)):
-        p = lbm.make_params(10240, 10240, storage, **Wk.base_params(Lambda=10.0))
-        assert (lbm.lbm_validate_params(p)[0] == lbm.LBM_OK) == ok, storage
+def test_population_buffers_past_4_gib():
+    """The step addresses each lattice row through a buffer resource of its own,
+    so a whole population buffer may exceed 4 GiB (8192^2 FP32: 4.8 GB; 20000^2
+    FP32: 28.8 GB) in every format.  A solid-site mask addresses the whole buffer
+    through one resource (below 4 GiB), and the adjoint indexes 21 workspace
+    planes with 32-bit integers (at most 102 M sites)."""
+    for storage in ("f32", "f16", "bf16", "f64"):
+        for n in (8192, 10240, 20000):
+            p = lbm.make_params(n, n, storage, **Wk.base_params(Lambda=10.0))
+            assert lbm.lbm_validate_params(p)[0] == lbm.LBM_OK, (storage, n)
+    big = lbm.make_params(8192, 8192, "f32", **Wk.base_params(Lambda=10.0))
+    assert lbm.lbm_solid_workspace_bytes(big) == 0
+    assert lbm.lbm_adjoint_workspace_bytes(big) > 0
+    small = lbm.make_params(7680, 7680, "f32", **Wk.base_params(Lambda=10.0))
+    assert lbm.lbm_solid_workspace_bytes(small) > 0
+    huge = lbm.make_params(11000, 11000, "f32", **Wk.base_params(Lambda=10.0))
+    assert lbm.lbm_adjoint_workspace_bytes(huge) == 0
 
 
 def test_sizes():

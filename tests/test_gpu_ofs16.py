@@ -210,11 +210,12 @@ def test_ofs16_masses_and_nan(fmt):
 
 @pytest.mark.parametrize("fmt", FMTS)
 def test_ofs16_largest_lattice_class_streaming(fmt):
-    """10240^2 in a 16-bit offset format: 4.19 GB per buffer (under 4 GiB, byte
-    offsets past 2^31); the packed words stream bit-exactly at sites in the
-    first and last rows and columns."""
+    """11264^2 in a 16-bit offset format: 5.08 GB per buffer (past the 4 GiB one
+    32-bit buffer offset spans; rows are addressed through resources of their
+    own); the packed words stream bit-exactly at sites in the first and last
+    rows and columns."""
     from oracle.lattice import C
-    n = 10240
+    n = 11264
     params = Wk.base_params(Lambda=10.0)
     sim = sim_for(n, n, params, Wk.emulsion(n, n, 12, 20.0, 80.0, 6.0, 4), fmt, flags=lbm.LBM_FLAG_STREAM_ONLY)
     sim.step(2)

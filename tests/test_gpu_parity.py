@@ -482,11 +482,12 @@ def test_full_size_emulsion_50_steps(storage):
 
 
 def test_largest_lattice_class():
-    """7680^2 FP32: each population buffer is 4.25 GB, just under the 4 GiB a
-    buffer may have, so word and row byte offsets run past 2^31.  Streaming
-    is bit-exact and one full step matches the oracle at sampled sites in the
-    first and last rows and columns (the largest offsets)."""
-    n = 7680
+    """8192^2 FP32: each population buffer is 4.83 GB, past the 4 GiB that one
+    32-bit buffer offset spans (the kernels address each lattice row through a
+    resource of its own, based at the row's 64-bit address).  Streaming is
+    bit-exact and one full step matches the oracle at sampled sites in the
+    first and last rows and columns (the largest addresses)."""
+    n = 8192
     params = Wk.base_params(Lambda=10.0, sigma=0.005)
     rn = Wk.emulsion(n, n, 12, 20.0, 80.0, 6.0, 3)
     rng = np.random.default_rng(5)
@@ -518,7 +519,7 @@ def test_largest_lattice_class():
         ref = oracle_post_collision(S, 2 * half + 1, 2 * half + 1, params)[:, :, half, half]
         got = after[:, :, y, x].double().cpu().numpy()
         worst = max(worst, float(np.max(np.abs(got - ref)) / np.max(np.abs(ref))))
-    print("7680^2 f32: one step at sampled sites, max rel err %.3e" % worst)
+    print("8192^2 f32: one step at sampled sites, max rel err %.3e" % worst)
     assert worst < 2e-5
     m = sim.masses()
     assert np.isfinite(m[0]) and np.isfinite(m[1])
