@@ -370,6 +370,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-storage16", action="store_true")
     ap.add_argument("--no-solid", action="store_true")
+    ap.add_argument("--no-rollout", action="store_true",
+                    help="with the adjoint legs, skip the two 2000-step rollouts (for counter runs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="first run one plain 1 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
@@ -456,8 +458,9 @@ def main():
                                                "step vs one forward step, FP32"},
                                   **adjoint_measure(512, p_d, rn_d, torch, steps=200,
                                                     force=torch.tensor(f_d, dtype=torch.float32, device="cuda:0")))
-        out["adjoint_rollout"] = adjoint_rollout(torch)
-        out["adjoint_rollout_every_state"] = adjoint_rollout(torch, checkpoint=1)
+        if not args.no_rollout:
+            out["adjoint_rollout"] = adjoint_rollout(torch)
+            out["adjoint_rollout_every_state"] = adjoint_rollout(torch, checkpoint=1)
     if not args.no_batch:
         out["batch"] = batch_measure(torch)
     if not args.no_cpu:
