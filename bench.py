@@ -250,37 +250,12 @@ def solid_measure(n, params, rn, torch, ms_fused, steps=100, warmup=10):
     return out
 
 
-def drop_to_ellipse(n=512):
-    """The adjoint workload: n^2 periodic, circle of radius n/4 to a seeded
-    ellipse target of equal area, 8 Gaussian force bumps (amplitude 1e-6).
-    Returns (rhoN0, target, force [2, n, n], params)."""
-    import numpy as np
-    from paper_2005_04642_amd import workloads as Wk
-    rng = np.random.default_rng(2)
-    yy, xx = np.mgrid[0:n, 0:n]
-    c = (n - 1) / 2.0
-    rn0 = np.where(np.hypot(xx - c, yy - c) < n / 4, 1.0, -1.0)
-    ar = rng.uniform(1.0, 1.5)
-    ang = rng.uniform(0, np.pi)
-    xr = (xx - c) * np.cos(ang) + (yy - c) * np.sin(ang)
-    yr = -(xx - c) * np.sin(ang) + (yy - c) * np.cos(ang)
-    target = np.where(np.hypot(xr / np.sqrt(ar), yr * np.sqrt(ar)) < n / 4, 1.0, -1.0)
-    force = np.zeros((2, n, n))
-    for _ in range(8):
-        bx, by = rng.uniform(0, n, 2)
-        th = rng.uniform(0, 2 * np.pi)
-        bump = 1e-6 * np.exp(-((xx - bx) ** 2 + (yy - by) ** 2) / (2 * 24.0 ** 2))
-        force[0] += bump * np.cos(th)
-        force[1] += bump * np.sin(th)
-    return rn0, target, force, Wk.base_params(Lambda=10.0, sigma=0.01)
-
-
 def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
     """Gradient of an interface-shape loss over a checkpointed rollout of the
     drop_to_ellipse workload; FP32 storage, FP64 dL/dsigma.  Returns forward
     and backward (recompute + adjoint) times."""
-    from paper_2005_04642_amd import adjoint
-    rn0, target, force, params = drop_to_ellipse(n)
+    from paper_2005_04642_amd import adjoint, workloads as Wk
+    rn0, target, force, params = Wk.drop_to_ellipse(n)
     dev = "cuda:0"
     rn_t = torch.tensor(rn0, dtype=torch.float32, device=dev, requires_grad=True)
     f_t = torch.tensor(force, dtype=torch.float32, device=dev, requires_grad=True)
@@ -302,8 +277,8 @@ def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
     torch.cuda.synchronize()
     t2 = time.time()
     lups = n * n * steps
-    return {"workload": "%d^2 periodic drop R=%d to an ellipse target, %d steps, checkpoint every %d, FP32"
-                        % (n, n // 4, steps, checkpoint),
+    return {"workload": "%d^2 periodic drop R=%d (tanh profile of width 2) to an ellipse target, %d steps, "
+                        "checkpoint every %d, FP32" % (n, n // 4, steps, checkpoint),
             "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
             "MLUPS_forward": round(lups / (t1 - t0) / 1e6, 1), "MLUPS_backward": round(lups / (t2 - t1) / 1e6, 1),
             "ratio": round((t1 - t0) / (t2 - t1), 4), "loss": float(loss.detach()), "dL_dsigma": float(sig.grad)}
@@ -453,7 +428,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = dict({"workload": "same lattice and state, one adjoint step vs one forward step, FP32"},
                               **adjoint_measure(n, params, rn, torch))
-        rn_d, _, f_d, p_d = drop_to_ellipse(512)
+        rn_d, _, f_d, p_d = Wk.drop_to_ellipse(512)
         out["adjoint_512"] = dict({"workload": "512^2 drop of the rollout below (with its force field), one adjoint "
                                                "step vs one forward step, FP32"},
                                   **adjoint_measure(512, p_d, rn_d, torch, steps=200,

@@ -16,6 +16,7 @@ take their structure):
 * ``gaussian_bumps``   smooth per-site body-force field
 * ``circular_wall``    solid mask of a circular container (staircase wall)
 * ``config_curved_transient``  rotating dense core inside a circular wall
+* ``drop_to_ellipse``  the adjoint workload: a drop, an ellipse target, force bumps
 """
 import math
 
@@ -249,3 +250,33 @@ def config_batch(nsim=256, seed=1, width=2.0):
         prm = base_params(Lambda=Lam, sigma=sigma)
         out.append((L, L, prm, ellipse_drop(L, ar, width=width)))
     return out
+
+
+def drop_to_ellipse(n=512, width=2.0):
+    """The adjoint workload: n^2 periodic, a centred drop of radius n/4 as the
+    tanh profile tanh((n/4 - r)/width) (width None: the sharp +-1 circle), a
+    seeded target ellipse of equal area (aspect ratio ~ U[1, 1.5], angle
+    ~ U[0, pi), +-1), and 8 Gaussian force bumps of width 24, random direction,
+    amplitude 1e-6; Lambda = 10, sigma = 0.01.  From the sharp circle the
+    final-state loss is not a smooth function of sigma at working precision
+    (FP64 central differences change sign between steps h of 1e-5 and 1e-8);
+    from the tanh profile the FP64 adjoint equals them to 7 digits.  Returns
+    (rhoN0, target, force [2, n, n], params)."""
+    rng = np.random.default_rng(2)
+    yy, xx = np.mgrid[0:n, 0:n]
+    c = (n - 1) / 2.0
+    r = np.hypot(xx - c, yy - c)
+    rn0 = np.where(r < n / 4, 1.0, -1.0) if width is None else np.tanh((n / 4 - r) / width)
+    ar = rng.uniform(1.0, 1.5)
+    ang = rng.uniform(0, np.pi)
+    xr = (xx - c) * np.cos(ang) + (yy - c) * np.sin(ang)
+    yr = -(xx - c) * np.sin(ang) + (yy - c) * np.cos(ang)
+    target = np.where(np.hypot(xr / np.sqrt(ar), yr * np.sqrt(ar)) < n / 4, 1.0, -1.0)
+    force = np.zeros((2, n, n))
+    for _ in range(8):
+        bx, by = rng.uniform(0, n, 2)
+        th = rng.uniform(0, 2 * np.pi)
+        bump = 1e-6 * np.exp(-((xx - bx) ** 2 + (yy - by) ** 2) / (2 * 24.0 ** 2))
+        force[0] += bump * np.cos(th)
+        force[1] += bump * np.sin(th)
+    return rn0, target, force, base_params(Lambda=10.0, sigma=0.01)
