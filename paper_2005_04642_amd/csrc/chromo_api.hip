@@ -613,6 +613,21 @@ struct lbm_batch {
 
 namespace {
 
+// Strip widths the batch kernels of this batch may use.  With FP32 arithmetic
+// the 192-wide strips (768 threads, at most 168 VGPRs) spill registers in the
+// walled and masked variants (hipcc: 5 VGPRs for walls at stencil 3333, 13 and
+// 57 for masks at 3131 and 3333), so walled and masked batches use 128-wide
+// strips only (no spills).  Returns the count written to out.
+int batch_widths(const lbm_batch* b, int* out) {
+  int n = 0;
+  for (int i = 0; i < 3 && b->ops->batch_ntx[i]; ++i) {
+    const int w = b->ops->batch_ntx[i];
+    if (b->ops->math_bytes == 4 && w > 128 && (b->p[0].walls_y || b->masked)) continue;
+    out[n++] = w;
+  }
+  return n;
+}
+
 int batch_upload(lbm_batch* b, BatchPlan&& pl, hipStream_t s) {
   if (pl.items.size() / 2 > b->items_cap || pl.nbins > BATCH_MAX_BINS)
     return fail(LBM_EINVAL, "batch plan exceeds the workspace tables");
@@ -745,8 +760,10 @@ int lbm_batch_init(const lbm_params* p, int nsim, const void* const* rhoN0, void
   }
   const int nr = b->ops->math_bytes == 8 ? chromo::NR_F64 : chromo::NR_F32;
   const int it0 = 3 * ((nr * ((3 + nr - 1) / nr) + 3 + nr - 1) / nr);
-  int ntx0 = b->ops->batch_ntx[0];
-  for (int i = 1; i < 3 && b->ops->batch_ntx[i]; ++i) ntx0 = std::max(ntx0, b->ops->batch_ntx[i]);
+  int widths[3];
+  const int nw = batch_widths(b, widths);
+  int ntx0 = widths[0];
+  for (int i = 1; i < nw; ++i) ntx0 = std::max(ntx0, widths[i]);
   st = batch_upload(b, batch_plan(p, nsim, b->off, ncu, ntx0, 128, *b->ops, nr, it0, b->force, b->bnc), stream);
   if (st != LBM_OK) {
     delete b;
@@ -781,9 +798,11 @@ int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_
   float best = -1.0f;
   int best_ntx = b->plan.ntx, best_tycap = b->plan.tycap;
   int st = LBM_OK;
-  for (int i = 0; i < 3 && b->ops->batch_ntx[i] && st == LBM_OK; ++i) {
+  int widths[3];
+  const int nw = batch_widths(b, widths);
+  for (int i = 0; i < nw && st == LBM_OK; ++i) {
     for (int tc : BATCH_TYCAPS) {
-      st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, b->ops->batch_ntx[i], tc, *b->ops, nr,
+      st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, widths[i], tc, *b->ops, nr,
                                       it0, b->force, b->bnc),
                         stream);
       if (st != LBM_OK) break;
@@ -806,7 +825,7 @@ int lbm_batch_autotune(lbm_batch* b, void* scratch, size_t scratch_bytes, int32_
       }
       if (best < 0.0f || ms < best) {
         best = ms;
-        best_ntx = b->ops->batch_ntx[i];
+        best_ntx = widths[i];
         best_tycap = tc;
       }
     }
@@ -867,6 +886,18 @@ int lbm_batch_set_solid(lbm_batch* b, int32_t k, const uint8_t* solid_dev, void*
   b->bnc[k] = static_cast<const unsigned char*>(workspace) +
               chromo::solid::bits_offset((size_t)p.nx * (size_t)p.ny, (size_t)b->ops->math_bytes);
   b->masked = 1;
+  int widths[3];
+  const int nw = batch_widths(b, widths);
+  bool allowed = false;
+  for (int i = 0; i < nw; ++i) allowed = allowed || widths[i] == b->plan.ntx;
+  if (!allowed) {  // the batch steps with the mask variant from now on: re-plan at a width it is built for
+    const int nr = b->ops->math_bytes == 8 ? chromo::NR_F64 : chromo::NR_F32;
+    const int it0 = 3 * ((nr * ((3 + nr - 1) / nr) + 3 + nr - 1) / nr);
+    int st = batch_upload(b, batch_plan(b->p.data(), b->nsim, b->off, b->ncu, widths[0], b->plan.tycap, *b->ops, nr,
+                                        it0, b->force, b->bnc),
+                          stream);
+    return st;
+  }
   const chromo::Geom g = batch_geom(p, b->plan.ntx, b->plan.tycap);
   unsigned char* desc = &b->plan.sims[(size_t)k * b->ops->sim_desc_bytes];
   b->ops->sim_desc(p, g, (unsigned long long)b->off[k], b->force[k], b->bnc[k], desc);
