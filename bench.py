@@ -253,7 +253,9 @@ def solid_measure(n, params, rn, torch, ms_fused, steps=100, warmup=10):
 def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
     """Gradient of an interface-shape loss over a checkpointed rollout of the
     drop_to_ellipse workload; FP32 storage, FP64 dL/dsigma.  Returns forward
-    and backward (recompute + adjoint) times."""
+    and backward (recompute + adjoint) times: the backward as the rollout runs
+    it (the next segment recomputed on a second stream during the current
+    segment's adjoint steps) and, for context, on one stream."""
     from paper_2005_04642_amd import adjoint, workloads as Wk
     rn0, target, force, params = Wk.drop_to_ellipse(n)
     dev = "cuda:0"
@@ -264,24 +266,37 @@ def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
     # untimed short rollout first: allocator pools, library load and first launches
     w = adjoint.rollout(rn_t, sig, f_t, params, 2 * checkpoint, checkpoint=checkpoint, storage="f32", device=dev)
     ((w - tgt) ** 2).sum().backward()
-    rn_t.grad = None
-    f_t.grad = None
-    sig.grad = None
-    torch.cuda.synchronize()
-    t0 = time.time()
-    out = adjoint.rollout(rn_t, sig, f_t, params, steps, checkpoint=checkpoint, storage="f32", device=dev)
-    loss = ((out - tgt) ** 2).sum()
-    torch.cuda.synchronize()
-    t1 = time.time()
-    loss.backward()
-    torch.cuda.synchronize()
-    t2 = time.time()
+
+    def timed(overlap):
+        rn_t.grad = None
+        f_t.grad = None
+        sig.grad = None
+        torch.cuda.synchronize()
+        t0 = time.time()
+        out = adjoint.rollout(rn_t, sig, f_t, params, steps, checkpoint=checkpoint, storage="f32", device=dev,
+                              overlap=overlap)
+        loss = ((out - tgt) ** 2).sum()
+        torch.cuda.synchronize()
+        t1 = time.time()
+        loss.backward()
+        torch.cuda.synchronize()
+        t2 = time.time()
+        return t1 - t0, t2 - t1, float(loss.detach()), float(sig.grad)
+
+    fwd, bwd, loss, dsig = timed(None)
     lups = n * n * steps
-    return {"workload": "%d^2 periodic drop R=%d (tanh profile of width 2) to an ellipse target, %d steps, "
-                        "checkpoint every %d, FP32" % (n, n // 4, steps, checkpoint),
-            "forward_s": round(t1 - t0, 3), "backward_s": round(t2 - t1, 3),
-            "MLUPS_forward": round(lups / (t1 - t0) / 1e6, 1), "MLUPS_backward": round(lups / (t2 - t1) / 1e6, 1),
-            "ratio": round((t1 - t0) / (t2 - t1), 4), "loss": float(loss.detach()), "dL_dsigma": float(sig.grad)}
+    res = {"workload": "%d^2 periodic drop R=%d (tanh profile of width 2) to an ellipse target, %d steps, "
+                       "checkpoint every %d, FP32" % (n, n // 4, steps, checkpoint),
+           "forward_s": round(fwd, 3), "backward_s": round(bwd, 3),
+           "MLUPS_forward": round(lups / fwd / 1e6, 1), "MLUPS_backward": round(lups / bwd / 1e6, 1),
+           "ratio": round(fwd / bwd, 4), "loss": loss, "dL_dsigma": dsig}
+    if checkpoint > 1:
+        # the same backward with the recompute and the adjoint steps on one stream
+        fwd1, bwd1, _, dsig1 = timed(False)
+        res["backward_s_one_stream"] = round(bwd1, 3)
+        res["ratio_one_stream"] = round(fwd1 / bwd1, 4)
+        res["same_dL_dsigma"] = dsig1 == dsig
+    return res
 
 
 def batch_measure(torch, nsim=256, steps=20):

@@ -189,10 +189,10 @@ int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream);
 
 /* Bytes of device workspace lbm_adjoint_step needs (256-byte aligned): the
  * saved intermediates and adjoint fields (39 planes of nx*ny values of the
- * arithmetic type) and the FP64 partial sums of dL/dsigma.  0 if the adjoint is
- * not provided for these parameters or the lattice has more than 102,261,126
- * sites (the adjoint indexes its workspace planes with 32-bit integers; the
- * adjoint entry points return LBM_EINVAL on such a handle). */
+ * arithmetic type, interleaved by rows: [ny][39][nx]) and the FP64 partial
+ * sums of dL/dsigma.  0 if the adjoint is not provided for these parameters
+ * (every lattice lbm_validate_params accepts, up to 2^30 sites: 167 GB of
+ * workspace in FP32 at that size). */
 size_t lbm_adjoint_workspace_bytes(const lbm_params* p);
 
 /* One step backwards.  pops_t: the state the step starts from (a population

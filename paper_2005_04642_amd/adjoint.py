@@ -5,7 +5,8 @@
 rho^N of the final state.  It is a ``torch.autograd.Function``: the backward
 pass runs the library's hand-written adjoint (``lbm_adjoint_step``) step by
 step in reverse, recomputing the states of each checkpoint segment forward
-from the state saved at its start, and returns dL/drho^N_0, dL/dsigma and
+from the state saved at its start (the next segment's recompute overlaps the
+current segment's adjoint steps on a second stream), and returns dL/drho^N_0, dL/dsigma and
 dL/dG_ext (the per-site force density).  Every step, forward or adjoint, runs
 in the HIP library; torch only holds buffers.
 
@@ -19,7 +20,7 @@ from . import lbm
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, rhoN0, sigma, force, params, nsteps, checkpoint, storage, device):
+    def forward(ctx, rhoN0, sigma, force, params, nsteps, checkpoint, storage, device, overlap):
         p = dict(params)
         p["sigma"] = float(sigma)
         solid = p.pop("solid", None)
@@ -62,6 +63,7 @@ class _Rollout(torch.autograd.Function):
         ctx.ckpts = ckpts
         ctx.nsteps = nsteps
         ctx.checkpoint = checkpoint
+        ctx.overlap = overlap
         ctx.final = cur
         ctx.has_force = force is not None
         ctx.sigma_dtype = sigma.dtype
@@ -71,6 +73,7 @@ class _Rollout(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_rhoN):
         sim = ctx.sim
+        torch_ = sim.torch
         T = sim.dtype
         lam = sim.pops_like()
         lam_prev = sim.pops_like()
@@ -78,40 +81,93 @@ class _Rollout(torch.autograd.Function):
         dsigma = torch.zeros(1, dtype=torch.float64, device=sim.device)
         dforce = torch.zeros((2, sim.ny, sim.nx), dtype=T, device=sim.device)
         starts = sorted(ctx.ckpts)
-        for k in reversed(range(len(starts))):
-            t0 = starts[k]
-            t1 = starts[k + 1] if k + 1 < len(starts) else ctx.nsteps
-            # states t0 .. t1-1 of this segment, recomputed from its checkpoint,
-            # each step written straight into a buffer of its own
-            states = [ctx.ckpts[t0]]
-            for _ in range(t0 + 1, t1):
-                nxt = sim.pops_like()
-                sim.set_pops(states[-1], nxt)
-                sim.step(1)
-                states.append(nxt)
-            for t in reversed(range(t0, t1)):
-                sim.adjoint_step(states[t - t0], lam, lam_prev, dsigma, dforce)
-                lam, lam_prev = lam_prev, lam
+        ends = starts[1:] + [ctx.nsteps]
+        nseg = len(starts)
+        # States after a segment's checkpoint are recomputed into a set of
+        # buffers of their own.  With two sets, segment k - 1 is recomputed on
+        # a second stream while the adjoint steps of segment k run on the
+        # caller's stream; each set is reused only after the adjoint steps that
+        # read it have finished (events).  Same kernels in the same order on
+        # each stream: the gradients do not depend on the overlap.
+        longest = max(e - s for s, e in zip(starts, ends))
+        per = max(longest - 1, 1)
+        state_bytes = sim.ny * sim.nx * 18 * (8 if T == torch.float64 else 4)
+        overlap = ctx.overlap
+        if overlap is None:
+            free, _ = torch_.cuda.mem_get_info(sim.device)
+            overlap = 2 * per * state_bytes <= free // 2
+        nsets = 2 if overlap and nseg >= 2 and longest >= 2 else 1   # (checkpoint 1: nothing to recompute)
+        block = torch.empty((nsets, per, sim.ny, 2, 9, sim.nx), dtype=T, device=sim.device)
+        base = block.data_ptr()
+        main = torch_.cuda.current_stream(sim.device)
+        side = torch_.cuda.Stream(device=sim.device) if nsets == 2 else main
+        h = sim.h
+        ws = sim.adjoint_workspace()
+        wsp, wsb = ws.data_ptr(), ws.numel()
+        dsp, dfp = dsigma.data_ptr(), dforce.data_ptr()
+        ms, ss = main.cuda_stream, side.cuda_stream
+        set_pops, step, adj_step = lbm.lbm_set_pops, lbm.lbm_step, lbm.lbm_adjoint_step
+
+        def states_of(k):
+            # device pointers of the states t0 .. t1-1 of segment k
+            n = ends[k] - starts[k]
+            b = base + (k % nsets) * per * state_bytes
+            return [ctx.ckpts[starts[k]].data_ptr()] + [b + j * state_bytes for j in range(n - 1)]
+
+        def recompute(k, stream):
+            st = states_of(k)
+            for a, b in zip(st[:-1], st[1:]):
+                set_pops(h, a, b)
+                step(h, 1, None, stream)
+
+        lp, lq = lam.data_ptr(), lam_prev.data_ptr()
+        ev_rec, ev_adj = {}, {}
+        if nsets == 2:
+            side.wait_stream(main)          # the checkpoints and lambda come from the caller's stream
+            recompute(nseg - 1, ss)
+            ev_rec[nseg - 1] = side.record_event()
+        for k in reversed(range(nseg)):
+            if nsets == 2:
+                if k >= 1:
+                    if k + 1 < nseg:
+                        side.wait_event(ev_adj[k + 1])   # set (k - 1) % 2 was read by segment k + 1
+                    recompute(k - 1, ss)
+                    ev_rec[k - 1] = side.record_event()
+                main.wait_event(ev_rec[k])
+            else:
+                recompute(k, ms)
+            for st in reversed(states_of(k)):
+                adj_step(h, st, lp, lq, wsp, wsb, dsp, dfp, ms)
+                lp, lq = lq, lp
+            if nsets == 2:
+                ev_adj[k] = main.record_event()
+        L = lam if lp == lam.data_ptr() else lam_prev
         drhoN0 = torch.zeros((sim.ny, sim.nx), dtype=T, device=sim.device)
-        sim.init_adjoint(lam, drhoN0)
+        sim.init_adjoint(L, drhoN0)
+        del block
         sim.close()
         ctx.sim = None
         ctx.ckpts = None
         dsig = dsigma.to(device=ctx.sigma_device, dtype=ctx.sigma_dtype).reshape(())
         return (drhoN0, dsig, dforce if ctx.has_force else None,
-                None, None, None, None, None)
+                None, None, None, None, None, None)
 
 
-def rollout(rhoN0, sigma, force, params, nsteps, checkpoint=100, storage="f32", device="cuda:0"):
+def rollout(rhoN0, sigma, force, params, nsteps, checkpoint=100, storage="f32", device="cuda:0", overlap=None):
     """rho^N after ``nsteps`` steps from the rest state of ``rhoN0`` ([ny, nx]);
     differentiable with respect to rhoN0, sigma (0-dim tensor) and force
     ([2, ny, nx] tensor or None).
 
     Device memory: ceil(nsteps / checkpoint) + 3 population states are held
     from the forward pass to the end of the backward one (checkpoint = 1 keeps
-    every state and recomputes nothing), plus ``checkpoint`` states during the
-    backward recompute of one segment.  ``params`` may hold ``solid``, a mask of
-    solid sites ([ny, nx]; F64/F32 storage, stencil profiles 3333, 3131 and 1111)."""
+    every state and recomputes nothing), plus checkpoint - 1 recomputed states
+    per segment in the backward pass (twice that with ``overlap``).  ``params`` may hold ``solid``, a mask of
+    solid sites ([ny, nx]; F64/F32 storage, stencil profiles 3333, 3131 and 1111).
+
+    ``overlap``: recompute the next segment's states on a second stream while
+    the adjoint steps of the current one run (True), or one after the other
+    (False); None chooses True when two segments' states take at most half of
+    the free device memory.  The gradients are the same either way."""
     if not torch.is_tensor(sigma):
         sigma = torch.tensor(float(sigma), dtype=torch.float64)
-    return _Rollout.apply(rhoN0, sigma, force, params, int(nsteps), int(checkpoint), storage, device)
+    return _Rollout.apply(rhoN0, sigma, force, params, int(nsteps), int(checkpoint), storage, device, overlap)

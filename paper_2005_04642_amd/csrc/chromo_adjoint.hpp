@@ -41,53 +41,72 @@ static_assert(A_END == A_N, "local adjoint count");
 enum { B_RR, B_RB, B_JX, B_JY, B_K, B_GX, B_GY, B_N };
 enum { C_GX, C_GY, C_N };
 enum { D_RR, D_RB, D_N };
-constexpr int WS_PLANES = SV_N + A_N + B_N + C_N + D_N;
+static_assert(WS_PLANES == SV_N + A_N + B_N + C_N + D_N, "workspace planes");
+// first plane of each group within a workspace row
+constexpr int G_SV = 0, G_A = SV_N, G_B = G_A + A_N, G_C = G_B + B_N, G_D = G_C + C_N;
 // FP64 partial sums of dL/dsigma, one per 256-site block of a row; the
 // workspace keeps RED2 more doubles of slack
 __host__ __device__ inline int red_blocks(int nx, int ny) { return ((nx + 255) / 256) * ny; }
 constexpr int RED2 = 256;
 
-// App. B first-derivative stencil of radius R applied to a periodic global
-// field at (x, y): (d/dx, d/dy), the same sums as the forward ring stencils.
+// v mod n for the index of a stencil tap: v lies within 3 of [0, n) (or, for
+// the mirrored rows of a walled lattice, within [-n, 2n)), so on lattices of
+// 4 or more rows and columns one correction either way suffices; smaller ones
+// take the division (n is the same in every lane: a scalar branch).
+__device__ __forceinline__ int wrapi(int v, int n) {
+  if (n >= 4) {
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
+  }
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// App. B first-derivative stencil of radius R applied to a periodic field at
+// (x, y): (d/dx, d/dy), the same sums as the forward ring stencils.  f points
+// at the field's element (0, 0); rows lie rs elements apart (a workspace
+// plane: rs = WS_PLANES nx).
 template <int R, typename T>
-__device__ __forceinline__ void grad_at(const T* f, int nx, int ny, int x, int y, T& gx, T& gy) {
+__device__ __forceinline__ void grad_at(const T* f, size_t rs, int nx, int ny, int x, int y, T& gx, T& gy) {
   const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
+  const T* r0 = f + (size_t)y * rs;
   gx = T(0);
   gy = T(0);
 #pragma unroll
   for (int n = 1; n <= R; ++n) {
     const T b = stencil_b<R, T>(n);
-    const int xp = (x + n) % nx, xm = (x - n + nx) % nx;
-    const int yp = (y + n) % ny, ym = (y - n + ny) % ny;
-    const T d1 = f[yp * nx + xp] - f[ym * nx + xm];
-    const T d3 = f[yp * nx + xm] - f[ym * nx + xp];
-    const T d8 = f[y * nx + xp] - f[y * nx + xm];
-    const T d2 = f[yp * nx + x] - f[ym * nx + x];
+    const int xp = wrapi(x + n, nx), xm = wrapi(x - n, nx);
+    const T* rp = f + (size_t)wrapi(y + n, ny) * rs;
+    const T* rm = f + (size_t)wrapi(y - n, ny) * rs;
+    const T d1 = rp[xp] - rm[xm];
+    const T d3 = rp[xm] - rm[xp];
+    const T d8 = r0[xp] - r0[xm];
+    const T d2 = rp[x] - rm[x];
     gx += b * (wd * (d1 - d3) + wa * d8);
     gy += b * (wd * (d1 + d3) + wa * d2);
   }
 }
 
 template <int R, typename T>
-__device__ __forceinline__ T div_at(const T* fx, const T* fy, int nx, int ny, int x, int y) {
+__device__ __forceinline__ T div_at(const T* fx, const T* fy, size_t rs, int nx, int ny, int x, int y) {
   T ax, ay, bx, by;
-  grad_at<R>(fx, nx, ny, x, y, ax, ay);
-  grad_at<R>(fy, nx, ny, x, y, bx, by);
+  grad_at<R>(fx, rs, nx, ny, x, y, ax, ay);
+  grad_at<R>(fy, rs, nx, ny, x, y, bx, by);
   return ax + by;
 }
 
 template <typename T>
-__device__ __forceinline__ void grad_r(int r, const T* f, int nx, int ny, int x, int y, T& gx, T& gy) {
+__device__ __forceinline__ void grad_r(int r, const T* f, size_t rs, int nx, int ny, int x, int y, T& gx, T& gy) {
   if (r == 3) {
-    grad_at<3>(f, nx, ny, x, y, gx, gy);
+    grad_at<3>(f, rs, nx, ny, x, y, gx, gy);
   } else {
-    grad_at<1>(f, nx, ny, x, y, gx, gy);
+    grad_at<1>(f, rs, nx, ny, x, y, gx, gy);
   }
 }
 
 template <typename T>
-__device__ __forceinline__ T div_r(int r, const T* fx, const T* fy, int nx, int ny, int x, int y) {
-  return r == 3 ? div_at<3>(fx, fy, nx, ny, x, y) : div_at<1>(fx, fy, nx, ny, x, y);
+__device__ __forceinline__ T div_r(int r, const T* fx, const T* fy, size_t rs, int nx, int ny, int x, int y) {
+  return r == 3 ? div_at<3>(fx, fy, rs, nx, ny, x, y) : div_at<1>(fx, fy, rs, nx, ny, x, y);
 }
 
 // Transposes of the App. B stencils on a walled lattice (solid rows 0 and
@@ -96,14 +115,11 @@ __device__ __forceinline__ T div_r(int r, const T* fx, const T* fy, int nx, int 
 // (negated for a y-component): so fluid row `row` receives from y' =
 // row - n c_iy directly and from y' = 2F - 1 - row - n c_iy through the mirror
 // (both mod 2F, kept when inside the strip).  Returns (D_x^T l, D_y^T l) at
-// the fluid site (x, y) for a field l given on the lattice's rows.
-__device__ __forceinline__ int wrapi(int v, int n) {
-  v %= n;
-  return v < 0 ? v + n : v;
-}
-
+// the fluid site (x, y) for a field l given on the lattice's rows (rs
+// elements apart).
 template <int R, typename T>
-__device__ __forceinline__ void gradT_walls_at(const T* l, int nx, int ny, int x, int y, bool odd, T& tx, T& ty) {
+__device__ __forceinline__ void gradT_walls_at(const T* l, size_t rs, int nx, int ny, int x, int y, bool odd, T& tx,
+                                               T& ty) {
   const int F = ny - 2, row = y - 1, F2 = 2 * F;
   const T wd = T(1.0 / 36.0), wa = T(1.0 / 9.0);
   const T sg = odd ? T(-1) : T(1);
@@ -119,8 +135,8 @@ __device__ __forceinline__ void gradT_walls_at(const T* l, int nx, int ny, int x
       const int xs = wrapi(x - n * cx, nx);
       const int y1 = wrapi(row - n * cy, F2), y2 = wrapi(F2 - 1 - row - n * cy, F2);
       T v = T(0);
-      if (y1 < F) v += l[(y1 + 1) * nx + xs];
-      if (y2 < F) v += sg * l[(y2 + 1) * nx + xs];
+      if (y1 < F) v += l[(size_t)(y1 + 1) * rs + xs];
+      if (y2 < F) v += sg * l[(size_t)(y2 + 1) * rs + xs];
       tx += bw * T(cx) * v;
       ty += bw * T(cy) * v;
     }
@@ -128,12 +144,12 @@ __device__ __forceinline__ void gradT_walls_at(const T* l, int nx, int ny, int x
 }
 
 template <typename T>
-__device__ __forceinline__ void gradT_walls(int r, const T* l, int nx, int ny, int x, int y, bool odd, T& tx,
-                                            T& ty) {
+__device__ __forceinline__ void gradT_walls(int r, const T* l, size_t rs, int nx, int ny, int x, int y, bool odd,
+                                            T& tx, T& ty) {
   if (r == 3) {
-    gradT_walls_at<3>(l, nx, ny, x, y, odd, tx, ty);
+    gradT_walls_at<3>(l, rs, nx, ny, x, y, odd, tx, ty);
   } else {
-    gradT_walls_at<1>(l, nx, ny, x, y, odd, tx, ty);
+    gradT_walls_at<1>(l, rs, nx, ny, x, y, odd, tx, ty);
   }
 }
 
@@ -404,8 +420,14 @@ static __device__ __forceinline__ double block_sum(double v) {
 }
 
 // ---------------------------------------------------------------------------
-// pass 2: div u and grad Phi' transposed; u, Phi', G local
+// Passes 2-5.  The workspace is [y][WS_PLANES][x] (rows interleaved, as the
+// populations): sv, A, B, C, D point at the first plane of their group in row
+// 0, plane k of a group at row y starts (y WS_PLANES + k) nx elements after
+// it.  dforce is [2][ny][nx].
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ size_t ws_rs(const Geom& g) { return (size_t)WS_PLANES * (size_t)g.nx; }
+
+// pass 2: div u and grad Phi' transposed; u, Phi', G local
 template <typename T, bool W, bool M = false>
 __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, Radii r, const T* __restrict__ sv,
                                                     const T* __restrict__ A, T* __restrict__ B,
@@ -413,56 +435,60 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, 
                                                     const unsigned char* __restrict__ solid) {
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
-  const int P = g.plane, site = y * g.nx + x;
+  const int nx = g.nx, P = g.plane, site = y * nx + x;
+  const size_t RS = ws_rs(g), row = (size_t)y * RS + x;
+  const T* a = A + row;
+  const T* s = sv + row;
+  T* b = B + row;
   double acc = 0.0;
-  if (M && x < g.nx && solid_at<W, M>(g, solid, x, y)) {
+  if (M && x < nx && solid_at<W, M>(g, solid, x, y)) {
 #pragma unroll
-    for (int k = 0; k < B_N; ++k) B[k * P + site] = T(0);   // read by the next passes' stencils
+    for (int k = 0; k < B_N; ++k) b[k * nx] = T(0);   // read by the next passes' stencils
   }
-  if (x < g.nx && !solid_at<W, M>(g, solid, x, y)) {
+  if (x < nx && !solid_at<W, M>(g, solid, x, y)) {
     T lux, luy, lphi;
     if constexpr (M) {
       T tx, ty, wx, wy;
-      grad_r(r.u, A + A_TH * P, g.nx, g.ny, x, y, tx, ty);
-      solid_tap_weights_r(r.u, solid, g.nx, g.ny, x, y, wx, wy);
-      const T lth = A[A_TH * P + site];
-      lux = A[A_UX * P + site] - tx + lth * wx;
-      luy = A[A_UY * P + site] - ty + lth * wy;
-      solid_tap_weights_r(r.p, solid, g.nx, g.ny, x, y, wx, wy);
-      lphi = -div_r(r.p, A + A_DPX * P, A + A_DPY * P, g.nx, g.ny, x, y) + A[A_DPX * P + site] * wx +
-             A[A_DPY * P + site] * wy;
+      grad_r(r.u, A + A_TH * nx, RS, nx, g.ny, x, y, tx, ty);
+      solid_tap_weights_r(r.u, solid, nx, g.ny, x, y, wx, wy);
+      const T lth = a[A_TH * nx];
+      lux = a[A_UX * nx] - tx + lth * wx;
+      luy = a[A_UY * nx] - ty + lth * wy;
+      solid_tap_weights_r(r.p, solid, nx, g.ny, x, y, wx, wy);
+      lphi = -div_r(r.p, A + A_DPX * nx, A + A_DPY * nx, RS, nx, g.ny, x, y) + a[A_DPX * nx] * wx +
+             a[A_DPY * nx] * wy;
     } else if constexpr (W) {
       T ax, ay, bx, by;
-      gradT_walls(r.u, A + A_TH * P, g.nx, g.ny, x, y, false, ax, ay);  // theta = D_x u_x + D_y u_y (u_y odd)
-      gradT_walls(r.u, A + A_TH * P, g.nx, g.ny, x, y, true, bx, by);
-      lux = A[A_UX * P + site] + ax;
-      luy = A[A_UY * P + site] + by;
-      gradT_walls(r.p, A + A_DPX * P, g.nx, g.ny, x, y, false, ax, ay);  // grad Phi' (even)
-      gradT_walls(r.p, A + A_DPY * P, g.nx, g.ny, x, y, false, bx, by);
+      gradT_walls(r.u, A + A_TH * nx, RS, nx, g.ny, x, y, false, ax, ay);  // theta = D_x u_x + D_y u_y (u_y odd)
+      gradT_walls(r.u, A + A_TH * nx, RS, nx, g.ny, x, y, true, bx, by);
+      lux = a[A_UX * nx] + ax;
+      luy = a[A_UY * nx] + by;
+      gradT_walls(r.p, A + A_DPX * nx, RS, nx, g.ny, x, y, false, ax, ay);  // grad Phi' (even)
+      gradT_walls(r.p, A + A_DPY * nx, RS, nx, g.ny, x, y, false, bx, by);
       lphi = ax + by;
     } else {
       T tx, ty;
-      grad_r(r.u, A + A_TH * P, g.nx, g.ny, x, y, tx, ty);
-      lux = A[A_UX * P + site] - tx;  // theta = div u: transpose -grad
-      luy = A[A_UY * P + site] - ty;
-      lphi = -div_r(r.p, A + A_DPX * P, A + A_DPY * P, g.nx, g.ny, x, y);
+      grad_r(r.u, A + A_TH * nx, RS, nx, g.ny, x, y, tx, ty);
+      lux = a[A_UX * nx] - tx;  // theta = div u: transpose -grad
+      luy = a[A_UY * nx] - ty;
+      lphi = -div_r(r.p, A + A_DPX * nx, A + A_DPY * nx, RS, nx, g.ny, x, y);
     }
-    const T rR = sv[SV_RR * P + site], rB = sv[SV_RB * P + site];
+    const T rR = s[SV_RR * nx], rB = s[SV_RB * nx];
     const T rho = rR + rB;
-    const T ux = sv[SV_UX * P + site], uy = sv[SV_UY * P + site];
-    const T K = sv[SV_K * P + site];
-    const T gx = sv[SV_GNX * P + site], gy = sv[SV_GNY * P + site];
+    const T ux = s[SV_UX * nx], uy = s[SV_UY * nx];
+    const T K = s[SV_K * nx];
+    const T gx = s[SV_GNX * nx], gy = s[SV_GNY * nx];
     // Phi' = c06R rR + phiB rB - rho / 3
-    T lrR = A[A_RR * P + site] + (c.c06R - T(1.0 / 3.0)) * lphi;
-    T lrB = A[A_RB * P + site] + (c.phiB - T(1.0 / 3.0)) * lphi;
+    T lrR = a[A_RR * nx] + (c.c06R - T(1.0 / 3.0)) * lphi;
+    T lrB = a[A_RB * nx] + (c.phiB - T(1.0 / 3.0)) * lphi;
     // u = (j + G/2) / rho
     const T irho = T(1) / rho;
     const T ljx = lux * irho, ljy = luy * irho;
     const T lrho = -(lux * ux + luy * uy) * irho;
     lrR += lrho;
     lrB += lrho;
-    const T lGx = A[A_GX * P + site] + T(0.5) * ljx;
-    const T lGy = A[A_GY * P + site] + T(0.5) * ljy;
+    const T lGx = a[A_GX * nx] + T(0.5) * ljx;
+    const T lGy = a[A_GY * nx] + T(0.5) * ljy;
     // G = sigma K g / 2 + G_ext
     if (dforce) {
       dforce[site] += lGx;
@@ -470,14 +496,13 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, 
     }
     const T lGg = lGx * gx + lGy * gy;
     acc = 0.5 * (double)K * (double)lGg;
-    T* b = B + site;
-    b[B_RR * P] = lrR;
-    b[B_RB * P] = lrB;
-    b[B_JX * P] = ljx;
-    b[B_JY * P] = ljy;
-    b[B_K * P] = c.fixed_K ? T(0) : T(0.5) * sigma * lGg;
-    b[B_GX * P] = T(0.5) * sigma * K * lGx;
-    b[B_GY * P] = T(0.5) * sigma * K * lGy;
+    b[B_RR * nx] = lrR;
+    b[B_RB * nx] = lrB;
+    b[B_JX * nx] = ljx;
+    b[B_JY * nx] = ljy;
+    b[B_K * nx] = c.fixed_K ? T(0) : T(0.5) * sigma * lGg;
+    b[B_GX * nx] = T(0.5) * sigma * K * lGx;
+    b[B_GY * nx] = T(0.5) * sigma * K * lGy;
   }
   const double tot = block_sum(acc);
   if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = tot;
@@ -517,36 +542,41 @@ __global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii 
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y - 1;
   if (x >= g.nx) return;
-  const int P = g.plane, site = y * g.nx + x;
+  const int nx = g.nx;
+  const size_t RS = ws_rs(g), row = (size_t)y * RS + x;
+  T* o = C + row;
   if (solid_at<W, M>(g, solid, x, y)) {
-    if (M) C[C_GX * P + site] = C[C_GY * P + site] = T(0);
+    if (M) o[C_GX * nx] = o[C_GY * nx] = T(0);
     return;
   }
+  const T* a = A + row;
+  const T* b = B + row;
+  const T* s = sv + row;
   T kx, ky;
   if constexpr (M) {  // lambda_m = -D^T lambda_K = D lambda_K - lambda_K(s) (solid tap weights)
     T wx, wy;
-    grad_r(r.k, B + B_K * P, g.nx, g.ny, x, y, kx, ky);
-    solid_tap_weights_r(r.k, solid, g.nx, g.ny, x, y, wx, wy);
-    const T lk = B[B_K * P + site];
+    grad_r(r.k, B + B_K * nx, RS, nx, g.ny, x, y, kx, ky);
+    solid_tap_weights_r(r.k, solid, nx, g.ny, x, y, wx, wy);
+    const T lk = b[B_K * nx];
     kx -= lk * wx;
     ky -= lk * wy;
   } else if constexpr (W) {  // K = -(D_x m_x + D_y m_y), m_y odd: lambda_m = -D^T lambda_K
     T ax, ay, bx, by;
-    gradT_walls(r.k, B + B_K * P, g.nx, g.ny, x, y, false, ax, ay);
-    gradT_walls(r.k, B + B_K * P, g.nx, g.ny, x, y, true, bx, by);
+    gradT_walls(r.k, B + B_K * nx, RS, nx, g.ny, x, y, false, ax, ay);
+    gradT_walls(r.k, B + B_K * nx, RS, nx, g.ny, x, y, true, bx, by);
     kx = -ax;
     ky = -by;
   } else {
-    grad_r(r.k, B + B_K * P, g.nx, g.ny, x, y, kx, ky);
+    grad_r(r.k, B + B_K * nx, RS, nx, g.ny, x, y, kx, ky);
   }
-  const T lmx = A[A_MX * P + site] + kx;  // -(-D)^T = D
-  const T lmy = A[A_MY * P + site] + ky;
-  const T gx = sv[SV_GNX * P + site], gy = sv[SV_GNY * P + site];
+  const T lmx = a[A_MX * nx] + kx;  // -(-D)^T = D
+  const T lmy = a[A_MY * nx] + ky;
+  const T gx = s[SV_GNX * nx], gy = s[SV_GNY * nx];
   const T s2 = gx * gx + gy * gy + c.eps2;
   const T is = T(1) / sqrt(s2);
   const T dot = (lmx * gx + lmy * gy) * is * is * is;
-  C[C_GX * P + site] = B[B_GX * P + site] + lmx * is - gx * dot;
-  C[C_GY * P + site] = B[B_GY * P + site] + lmy * is - gy * dot;
+  o[C_GX * nx] = b[B_GX * nx] + lmx * is - gx * dot;
+  o[C_GY * nx] = b[B_GY * nx] + lmy * is - gy * dot;
 }
 
 // ---------------------------------------------------------------------------
@@ -560,31 +590,35 @@ __global__ void __launch_bounds__(256) colour_kernel(Geom g, Coef<T> c, Radii r,
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
-  const int P = g.plane, site = y * g.nx + x;
+  const int nx = g.nx;
+  const size_t RS = ws_rs(g), row = (size_t)y * RS + x;
+  T* o = D + row;
   if (solid_at<W, M>(g, solid, x, y)) {
-    if (M) D[D_RR * P + site] = D[D_RB * P + site] = T(0);
+    if (M) o[D_RR * nx] = o[D_RB * nx] = T(0);
     return;
   }
+  const T* cc = C + row;
   T dv;
   if constexpr (M) {  // lambda_rhoN += D^T lambda_g = -div lambda_g + lambda_g(s) . (solid tap weights)
     T wx, wy;
-    solid_tap_weights_r(r.g, solid, g.nx, g.ny, x, y, wx, wy);
-    dv = div_r(r.g, C + C_GX * P, C + C_GY * P, g.nx, g.ny, x, y) - C[C_GX * P + site] * wx -
-         C[C_GY * P + site] * wy;
+    solid_tap_weights_r(r.g, solid, nx, g.ny, x, y, wx, wy);
+    dv = div_r(r.g, C + C_GX * nx, C + C_GY * nx, RS, nx, g.ny, x, y) - cc[C_GX * nx] * wx - cc[C_GY * nx] * wy;
   } else if constexpr (W) {  // g = grad rho^N (even): lambda_rhoN += D_x^T lambda_gx + D_y^T lambda_gy
     T ax, ay, bx, by;
-    gradT_walls(r.g, C + C_GX * P, g.nx, g.ny, x, y, false, ax, ay);
-    gradT_walls(r.g, C + C_GY * P, g.nx, g.ny, x, y, false, bx, by);
+    gradT_walls(r.g, C + C_GX * nx, RS, nx, g.ny, x, y, false, ax, ay);
+    gradT_walls(r.g, C + C_GY * nx, RS, nx, g.ny, x, y, false, bx, by);
     dv = -(ax + by);
   } else {
-    dv = div_r(r.g, C + C_GX * P, C + C_GY * P, g.nx, g.ny, x, y);
+    dv = div_r(r.g, C + C_GX * nx, C + C_GY * nx, RS, nx, g.ny, x, y);
   }
-  const T lrN = A[A_RN * P + site] - dv;
-  const T a = sv[SV_RR * P + site] * c.inv_rho0R, b = sv[SV_RB * P + site] * c.inv_rho0B;
-  const T is = T(1) / (a + b);
+  const T* s = sv + row;
+  const T* b = B + row;
+  const T lrN = A[row + A_RN * nx] - dv;
+  const T ra = s[SV_RR * nx] * c.inv_rho0R, rb = s[SV_RB * nx] * c.inv_rho0B;
+  const T is = T(1) / (ra + rb);
   const T w = T(2) * lrN * is * is;
-  D[D_RR * P + site] = B[B_RR * P + site] + w * b * c.inv_rho0R;
-  D[D_RB * P + site] = B[B_RB * P + site] - w * a * c.inv_rho0B;
+  o[D_RR * nx] = b[B_RR * nx] + w * rb * c.inv_rho0R;
+  o[D_RB * nx] = b[B_RB * nx] - w * ra * c.inv_rho0B;
 }
 
 // ---------------------------------------------------------------------------
@@ -598,26 +632,27 @@ __global__ void __launch_bounds__(256) push_kernel(Geom g, const T* __restrict__
   const int x = blockIdx.x * blockDim.x + threadIdx.x;
   const int y = blockIdx.y;
   if (x >= g.nx) return;
-  const int P = g.plane;
+  const int nx = g.nx;
+  const size_t RS = ws_rs(g);
   if (solid_at<W, M>(g, solid, x, y)) {  // no fluid site reads a solid site's words
 #pragma unroll
-    for (int q = 0; q < 18; ++q) out[((size_t)y * 18 + q) * g.nx + x] = T(0);
+    for (int q = 0; q < 18; ++q) out[((size_t)y * 18 + q) * nx + x] = T(0);
     return;
   }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int cx = link_cx(i), cy = link_cy(i);
     int xs = x + cx, ys = y + cy;
-    xs = xs < 0 ? xs + g.nx : (xs >= g.nx ? xs - g.nx : xs);
+    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
     ys = ys < 0 ? ys + g.ny : (ys >= g.ny ? ys - g.ny : ys);
     // the word is pulled by link i of site s + c_i, or, when that site is
     // solid, bounced back into link opp(i) of s itself
     const bool bounce = solid_at<W, M>(g, solid, xs, ys);
     const int k = bounce ? link_opp(i) : i;
-    const int r = bounce ? y * g.nx + x : ys * g.nx + xs;
-    const T common = A[(A_F + k) * P + r] + T(link_cx(k)) * B[B_JX * P + r] + T(link_cy(k)) * B[B_JY * P + r];
-    out[((size_t)y * 18 + i) * g.nx + x] = common + D[D_RR * P + r];
-    out[((size_t)y * 18 + 9 + i) * g.nx + x] = common + D[D_RB * P + r];
+    const size_t r = bounce ? (size_t)y * RS + x : (size_t)ys * RS + xs;
+    const T common = A[r + (A_F + k) * nx] + T(link_cx(k)) * B[r + B_JX * nx] + T(link_cy(k)) * B[r + B_JY * nx];
+    out[((size_t)y * 18 + i) * nx + x] = common + D[r + D_RR * nx];
+    out[((size_t)y * 18 + 9 + i) * nx + x] = common + D[r + D_RB * nx];
   }
 }
 

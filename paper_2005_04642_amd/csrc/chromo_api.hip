@@ -45,8 +45,6 @@ constexpr int MAX_ROWS = 65535;             // grid dimension y of the per-row k
 // whole population buffers addressed through one buffer resource (the mask
 // variant of the gather and the four-pass masked step) stay below 2^32 bytes
 constexpr double WHOLE_BUFFER_LIMIT = 4294967296.0;
-// the adjoint indexes up to 21 planes of its workspace with 32-bit integers
-constexpr long long ADJ_MAX_SITES = 2147483647LL / 21;
 
 int halo(const lbm_params& p) { return p.stencil[0] + p.stencil[1] + p.stencil[3]; }
 
@@ -346,7 +344,6 @@ int lbm_masses_host(lbm_handle* h, double out[2], hipStream_t stream) {
 size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
   if (validate(p) != LBM_OK) return 0;
   if (!ops_of(p->storage)->adjoint) return 0;
-  if ((long long)p->nx * p->ny > ADJ_MAX_SITES) return 0;
   const size_t elem = p->storage == LBM_STORAGE_F64 ? 8 : 4;
   size_t bytes = (size_t)chromo::adj::WS_PLANES * (size_t)p->nx * (size_t)p->ny * elem;
   bytes = (bytes + 255) / 256 * 256;
@@ -358,9 +355,6 @@ static int adjoint_supported(const lbm_handle* h) {
   if (h->p.flags & LBM_FLAG_STREAM_ONLY) return fail(LBM_ENOTIMPL, "no adjoint of the streaming-only test mode");
   if (h->solid && !special_profile(h->p.stencil))
     return fail(LBM_ENOTIMPL, "the adjoint with a solid-site mask is built for stencil profiles 3333, 3131 and 1111");
-  if ((long long)h->p.nx * h->p.ny > ADJ_MAX_SITES)
-    return fail(LBM_EINVAL, "the adjoint takes at most %lld sites (32-bit indices of its workspace planes)",
-                ADJ_MAX_SITES);
   return LBM_OK;
 }
 

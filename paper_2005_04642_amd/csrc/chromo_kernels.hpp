@@ -86,9 +86,11 @@ struct StepArgs {
   T* out_ux;
   T* out_uy;
   T* out_rhoN;
-  // adjoint mode: dL/d(next state) at the own site ([18][ny][nx]), and the
-  // outputs: forward intermediates (planes SV_*) and local adjoints (planes
-  // adj::A_*), each [ny][nx]
+  // adjoint mode: dL/d(next state) at the own site ([ny][18][nx], as the
+  // populations), and the outputs: forward intermediates (planes SV_*) and
+  // local adjoints (planes adj::A_*), each a group of planes of the adjoint
+  // workspace (row-interleaved; the pointers address the group's first plane
+  // in row 0)
   const T* lam_next;
   T* out_save;
   T* out_adj;
@@ -108,6 +110,15 @@ enum { SV_RR, SV_RB, SV_UX, SV_UY, SV_K, SV_GNX, SV_GNY, SV_N };
 
 namespace adj {
 constexpr int A_N = 21;  // local adjoints per site (see chromo_adjoint.hpp)
+// planes of the adjoint workspace: the SV_N saved forward values, the A_N
+// local adjoints and 11 planes of the later passes, interleaved by rows
+// ([y][WS_PLANES][x], as the populations): plane k of row y starts at
+// (y WS_PLANES + k) nx
+constexpr int WS_PLANES = 39;
+template <typename T>
+__device__ __forceinline__ T* ws_row(T* group, int nx, int y) {
+  return group + (size_t)y * WS_PLANES * (size_t)nx;
+}
 template <typename T>
 __device__ void local_backward(const Coef<T>& c, const T* f, T rR, T rB, T ux, T uy, T Gx, T Gy, T dPx, T dPy,
                                T theta, T rhoN, T mx, T my, const T* lR, const T* lB, T* out);
@@ -615,8 +626,7 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, void* dst, c
     return;
   }
   if (MODE == MODE_ADJ) {
-    const int P = a.g.plane;
-    const int site = p * a.g.nx + t.xg;
+    const int nx = a.g.nx;
     const T* ln = a.lam_next + (size_t)p * 18 * a.g.nx + t.xg;  // [y][C i][x], as the populations
     T lR[9], lB[9], out[adj::A_N];
 #pragma unroll
@@ -632,13 +642,14 @@ __device__ __forceinline__ void collide_store(const StepArgs<T>& a, void* dst, c
         for (int q = 0; q < adj::A_N; ++q) out[q] = T(0);
       }
     }
+    T* oa = adj::ws_row(a.out_adj, nx, p) + t.xg;
 #pragma unroll
-    for (int q = 0; q < adj::A_N; ++q) a.out_adj[q * P + site] = out[q];
-    T* sv = a.out_save + site;
-    sv[SV_RR * P] = rR;
-    sv[SV_RB * P] = rB;
-    sv[SV_UX * P] = ux;
-    sv[SV_UY * P] = uy;
+    for (int q = 0; q < adj::A_N; ++q) oa[q * nx] = out[q];
+    T* sv = adj::ws_row(a.out_save, nx, p) + t.xg;
+    sv[SV_RR * nx] = rR;
+    sv[SV_RB * nx] = rB;
+    sv[SV_UX * nx] = ux;
+    sv[SV_UY * nx] = uy;
     return;
   }
   // modes of f (App. A projectors), summed with antisymmetric pair differences
@@ -855,7 +866,7 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, const v
       }
       if (MODE == MODE_ADJ) {
         const int v = base + PP::LU;  // virtual row of band U
-        if (t.own && v >= t.ya && v < t.yb) a.out_save[SV_K * g.plane + p * g.nx + t.xg] = K;
+        if (t.own && v >= t.ya && v < t.yb) adj::ws_row(a.out_save, g.nx, p)[SV_K * g.nx + t.xg] = K;
       }
       const T gnx = sm.at(F_GNX, ru, tx), gny = sm.at(F_GNY, ru, tx);
       T Gx = c.half_sigma * K * gnx + c.gx;
@@ -890,9 +901,9 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, const v
     const int ro = ring_row<RING>(rowO);
     const int p = WALLS ? base + 1 : base;
     if (MODE == MODE_ADJ) {
-      T* sv = a.out_save + p * g.nx + t.xg;
-      sv[SV_GNX * g.plane] = sm.at(F_GNX, ro, tx);
-      sv[SV_GNY * g.plane] = sm.at(F_GNY, ro, tx);
+      T* sv = adj::ws_row(a.out_save, g.nx, p) + t.xg;
+      sv[SV_GNX * g.nx] = sm.at(F_GNX, ro, tx);
+      sv[SV_GNY * g.nx] = sm.at(F_GNY, ro, tx);
     }
     collide_store<ST, T, MODE, MASK>(a, dst, st.rf[sO], sm.at(F_RR, ro, tx), sm.at(F_RB, ro, tx), sm.at(F_UX, ro, tx), sm.at(F_UY, ro, tx),
                                  sm.at(F_GX, ro, tx), sm.at(F_GY, ro, tx), sm.at(F_IRHO, ro, tx), dPx, dPy, theta,

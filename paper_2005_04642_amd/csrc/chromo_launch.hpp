@@ -221,8 +221,8 @@ hipError_t march_adj_masked(const StepArgs<typename S::math>& a, const int* r, h
 
 // ---------------------------------------------------------------------------
 // adjoint: save pass of the step kernel, then the five passes of
-// chromo_adjoint.hpp.  ws holds adj::WS_PLANES planes of the arithmetic type
-// followed, at the next multiple of 256 bytes, by adj::red_blocks() + adj::RED2
+// chromo_adjoint.hpp.  ws holds adj::WS_PLANES planes of the arithmetic type,
+// interleaved by rows ([y][WS_PLANES][x]), followed, at the next multiple of 256 bytes, by adj::red_blocks() + adj::RED2
 // doubles.
 // ---------------------------------------------------------------------------
 template <typename S>
@@ -232,11 +232,12 @@ hipError_t adjoint(const lbm_params& p, const Geom& g0, const void* pops, const 
   using T = typename S::math;
   StepArgs<T> a = args<S>(p, g0, pops, nullptr, force);
   const Geom& g = a.g;
-  T* sv = static_cast<T*>(ws);
-  T* A = sv + (size_t)SV_N * g.plane;
-  T* B = A + (size_t)adj::A_N * g.plane;
-  T* C = B + (size_t)adj::B_N * g.plane;
-  T* D = C + (size_t)adj::C_N * g.plane;
+  // groups of planes within a row of the row-interleaved workspace
+  T* sv = static_cast<T*>(ws) + (size_t)adj::G_SV * g.nx;
+  T* A = static_cast<T*>(ws) + (size_t)adj::G_A * g.nx;
+  T* B = static_cast<T*>(ws) + (size_t)adj::G_B * g.nx;
+  T* C = static_cast<T*>(ws) + (size_t)adj::G_C * g.nx;
+  T* D = static_cast<T*>(ws) + (size_t)adj::G_D * g.nx;
   const size_t plane_bytes = ((size_t)adj::WS_PLANES * g.plane * sizeof(T) + 255) / 256 * 256;
   double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + plane_bytes);
   a.out_save = sv;

@@ -72,8 +72,8 @@ def test_population_buffers_past_4_gib():
     """The step addresses each lattice row through a buffer resource of its own,
     so a whole population buffer may exceed 4 GiB (8192^2 FP32: 4.8 GB; 20000^2
     FP32: 28.8 GB) in every format.  A solid-site mask addresses the whole buffer
-    through one resource (below 4 GiB), and the adjoint indexes 21 workspace
-    planes with 32-bit integers (at most 102 M sites)."""
+    through one resource (below 4 GiB).  The adjoint's workspace rows are
+    addressed with 64-bit offsets: every accepted lattice has one."""
     for storage in ("f32", "f16", "bf16", "f64"):
         for n in (8192, 10240, 20000):
             p = lbm.make_params(n, n, storage, **Wk.base_params(Lambda=10.0))
@@ -84,7 +84,9 @@ def test_population_buffers_past_4_gib():
     small = lbm.make_params(7680, 7680, "f32", **Wk.base_params(Lambda=10.0))
     assert lbm.lbm_solid_workspace_bytes(small) > 0
     huge = lbm.make_params(11000, 11000, "f32", **Wk.base_params(Lambda=10.0))
-    assert lbm.lbm_adjoint_workspace_bytes(huge) == 0
+    assert lbm.lbm_adjoint_workspace_bytes(huge) >= 39 * 4 * 11000 * 11000
+    largest = lbm.make_params(32768, 32768, "f32", **Wk.base_params(Lambda=10.0))
+    assert lbm.lbm_adjoint_workspace_bytes(largest) >= 39 * 4 * 32768 * 32768
 
 
 def test_sizes():

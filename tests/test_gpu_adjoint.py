@@ -511,6 +511,28 @@ def test_checkpointing_does_not_change_gradients():
         assert np.array_equal(grads[0][2], g[2])
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_recompute_overlap_does_not_change_gradients(storage):
+    """The backward pass with the next segment recomputed on a second stream
+    gives bit-identical gradients to the one-stream backward (5 segments, the
+    last one shorter)."""
+    n, steps, params, rn0, target, force = fd_case()
+    T = torch.float64 if storage == "f64" else torch.float32
+    tgt = torch.tensor(target, dtype=T, device=DEV)
+    grads = []
+    for ov in (False, True):
+        rn_t = torch.tensor(rn0, dtype=T, device=DEV, requires_grad=True)
+        sig_t = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
+        f_t = torch.tensor(force, dtype=T, device=DEV, requires_grad=True)
+        out = adjoint.rollout(rn_t, sig_t, f_t, params, steps, checkpoint=5, storage=storage, device=DEV,
+                              overlap=ov)
+        ((out - tgt) ** 2).sum().backward()
+        grads.append((rn_t.grad.cpu().numpy(), float(sig_t.grad), f_t.grad.cpu().numpy()))
+    assert np.array_equal(grads[0][0], grads[1][0])
+    assert grads[0][1] == grads[1][1]
+    assert np.array_equal(grads[0][2], grads[1][2])
+
+
 def test_adjoint_workload_gradient_against_finite_differences():
     """The 512^2 adjoint workload (a drop of radius 128, tanh profile of width 2,
     to a seeded ellipse; 8 force bumps), 200 steps, a checkpoint every 100:
@@ -545,3 +567,47 @@ def test_adjoint_workload_gradient_against_finite_differences():
     assert abs(s32 - s64) <= 1e-4 * abs(s64)
     assert rel(f32, f64) < 1e-4
     assert rel(rn32, rn64) < 5e-2
+
+
+# ---------------------------------------------------------------------------
+# lattices past 2^31 / 21 sites
+# ---------------------------------------------------------------------------
+
+def test_adjoint_on_a_lattice_of_105m_sites():
+    """The adjoint addresses its workspace ([ny][39][nx], 16.4 GB here) with
+    64-bit row offsets.  A 10240^2 FP32 lattice (104.9 M sites) whose state and
+    adjoint input tile a 512^2 lattice's 20 x 20 times has, site by site, the
+    tiled adjoint of the 512^2 lattice: the step does the same arithmetic at
+    every site, so dL/dpops and dL/dG_ext are bit-identical; dL/dsigma is 400
+    times the small lattice's up to the order of its FP64 sum."""
+    n, reps = 512, 20
+    N = n * reps
+    params = Wk.base_params(Lambda=10.0, sigma=0.01)
+    rn0 = Wk.emulsion_crop(n, ndrops=3, seed=4)
+    small = lbm.Simulation(n, n, params, rn0, storage="f32", device=DEV)
+    big = lbm.Simulation(N, N, params, np.tile(rn0, (reps, reps)), storage="f32", device=DEV)
+    small.step(3)
+    big.step(3)
+    Ss, Sb = small.live_pops(), big.live_pops()
+    assert torch.equal(Sb, Ss.repeat(1, 1, reps, reps))
+    g = torch.Generator(device=DEV).manual_seed(11)
+    lam_s = small.pops_like()
+    lam_s.copy_(1e-3 * torch.randn((2, 9, n, n), generator=g, device=DEV))
+    lam_b = big.pops_like()
+    lam_b.copy_(lam_s.repeat(1, 1, reps, reps))
+    out_s, out_b = small.pops_like(), big.pops_like()
+    ds_s = torch.zeros(1, dtype=torch.float64, device=DEV)
+    ds_b = torch.zeros(1, dtype=torch.float64, device=DEV)
+    df_s = torch.zeros((2, n, n), dtype=torch.float32, device=DEV)
+    df_b = torch.zeros((2, N, N), dtype=torch.float32, device=DEV)
+    print("adjoint 512^2 and tiled 10240^2, FP32", flush=True)
+    small.adjoint_step(Ss, lam_s, out_s, ds_s, df_s)
+    big.adjoint_step(Sb, lam_b, out_b, ds_b, df_b)
+    torch.cuda.synchronize()
+    assert torch.equal(out_b, out_s.repeat(1, 1, reps, reps))
+    assert torch.equal(df_b, df_s.repeat(1, reps, reps))
+    a, b = float(ds_b), reps * reps * float(ds_s)
+    print("dL/dsigma 10240^2 %.12e, 400 x 512^2 %.12e" % (a, b))
+    assert abs(a - b) <= 1e-9 * abs(b)
+    small.close()
+    big.close()
