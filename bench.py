@@ -255,7 +255,8 @@ def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
     drop_to_ellipse workload; FP32 storage, FP64 dL/dsigma.  Returns forward
     and backward (recompute + adjoint) times: the backward as the rollout runs
     it (the next segment recomputed on a second stream during the current
-    segment's adjoint steps) and, for context, on one stream."""
+    segment's adjoint steps, the two streams on disjoint CUs at this size)
+    and, for context, with both streams on every CU and on one stream."""
     from paper_2005_04642_amd import adjoint, workloads as Wk
     rn0, target, force, params = Wk.drop_to_ellipse(n)
     dev = "cuda:0"
@@ -267,14 +268,14 @@ def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
     w = adjoint.rollout(rn_t, sig, f_t, params, 2 * checkpoint, checkpoint=checkpoint, storage="f32", device=dev)
     ((w - tgt) ** 2).sum().backward()
 
-    def timed(overlap):
+    def timed(overlap, recompute_cus=None):
         rn_t.grad = None
         f_t.grad = None
         sig.grad = None
         torch.cuda.synchronize()
         t0 = time.time()
         out = adjoint.rollout(rn_t, sig, f_t, params, steps, checkpoint=checkpoint, storage="f32", device=dev,
-                              overlap=overlap)
+                              overlap=overlap, recompute_cus=recompute_cus)
         loss = ((out - tgt) ** 2).sum()
         torch.cuda.synchronize()
         t1 = time.time()
@@ -291,11 +292,14 @@ def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
            "MLUPS_forward": round(lups / fwd / 1e6, 1), "MLUPS_backward": round(lups / bwd / 1e6, 1),
            "ratio": round(fwd / bwd, 4), "loss": loss, "dL_dsigma": dsig}
     if checkpoint > 1:
-        # the same backward with the recompute and the adjoint steps on one stream
+        res["recompute_cus"] = adjoint.RECOMPUTE_CUS if n * n <= adjoint.PARTITION_MAX_SITES else 0
+        # the same backward with both streams on every CU, and on one stream
+        fwd2, bwd2, _, dsig2 = timed(True, 0)
+        res["backward_s_two_streams_unconfined"] = round(bwd2, 3)
         fwd1, bwd1, _, dsig1 = timed(False)
         res["backward_s_one_stream"] = round(bwd1, 3)
         res["ratio_one_stream"] = round(fwd1 / bwd1, 4)
-        res["same_dL_dsigma"] = dsig1 == dsig
+        res["same_dL_dsigma"] = dsig1 == dsig and dsig2 == dsig
     return res
 
 

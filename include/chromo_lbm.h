@@ -164,6 +164,15 @@ int lbm_step(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t str
  * any size.  Errors as lbm_step (LBM_EINVAL for a NULL handle or nsteps < 0). */
 int lbm_step_static(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t stream);
 
+/* Advance nsteps >= 0 steps from the state in `from` (a population buffer of
+ * the handle's format), writing the state after step j into states[j] (host
+ * array of nsteps device buffers of lbm_pops_bytes(), each distinct from its
+ * source): a trajectory kept whole, as the checkpointed adjoint recomputes
+ * it, in one call.  The handle then steps on from states[nsteps-1] (as after
+ * lbm_set_pops).  LBM_EINVAL for NULL arrays or entries, or a state equal to
+ * its source.  Enqueued on `stream`. */
+int lbm_step_into(lbm_handle* h, const void* from, int32_t nsteps, void* const* states, hipStream_t stream);
+
 /* Macroscopic fields of the current state (Sec. II, force-adjusted
  * observables): rho, u = (sum f c + G/2)/rho, rho^N.  Each output is NULL
  * (skipped) or a device [ny][nx] array of the arithmetic type; solid rows are
@@ -205,6 +214,20 @@ size_t lbm_adjoint_workspace_bytes(const lbm_params* p);
  * whether or not a force field was given).  Enqueued on `stream`. */
 int lbm_adjoint_step(lbm_handle* h, const void* pops_t, const void* adj_next, void* adj_out, void* workspace,
                      size_t ws_bytes, double* dL_dsigma_dev, void* dL_dforce_dev, hipStream_t stream);
+
+/* nsteps >= 0 steps backwards through a trajectory in one call: the adjoint
+ * of the step from states[nsteps-1], then from states[nsteps-2], ... down to
+ * states[0] (states: host array of nsteps device population buffers).  adj_a
+ * holds dL/d(state after the step from states[nsteps-1]) on entry; the steps
+ * alternate between adj_a and adj_b (a -> b -> a ...), so dL/d(states[0])
+ * ends in adj_a if nsteps is even and in adj_b if it is odd.  dL/dsigma and
+ * dL/dG_ext of every step are added as in lbm_adjoint_step.  The same kernels
+ * in the same order as nsteps lbm_adjoint_step calls, without a host call per
+ * step (on small lattices the host's per-step calls otherwise cost about as
+ * much as the GPU's work).  Enqueued on `stream`. */
+int lbm_adjoint_steps(lbm_handle* h, int32_t nsteps, const void* const* states, void* adj_a, void* adj_b,
+                      void* workspace, size_t ws_bytes, double* dL_dsigma_dev, void* dL_dforce_dev,
+                      hipStream_t stream);
 
 /* Adjoint of the colour index that lbm_fields reports for the state pops:
  * adj_out (overwritten) = dL/dpops given dL_drhoN, a device [ny][nx] array
@@ -354,6 +377,30 @@ int lbm_set_pops(lbm_handle* h, void* live, void* next);
 
 /* Steps taken since lbm_init. */
 int64_t lbm_step_count(const lbm_handle* h);
+
+/* ---- sharing the GPU between two streams of work --------------------------
+ * For callers that run independent work side by side on one GPU (the
+ * checkpointed adjoint recomputes the next segment's states while it runs the
+ * current segment's adjoint steps).  On small lattices a step keeps few CUs
+ * busy for long (each tile's march starts with a fixed pipeline fill), so two
+ * streams confined to disjoint sets of CUs overlap where two unconfined ones
+ * would queue one kernel behind the other. */
+
+/* Plan the tiles of the forward step (lbm_step, lbm_fields) for ncu_step CUs
+ * and those of the adjoint's first pass for ncu_adjoint CUs instead of the
+ * whole device (0: the whole device; larger values are clamped to it).
+ * Results do not depend on the plan (every site takes the same arithmetic).
+ * Host-side only; applies to launches made after the call.  LBM_EINVAL for a
+ * NULL handle or a negative count. */
+int lbm_set_cu_budget(lbm_handle* h, int32_t ncu_step, int32_t ncu_adjoint);
+
+/* Create a HIP stream whose kernels run only on CUs [cu_first, cu_first +
+ * cu_count) of the current device, in the runtime's CU numbering (round-robin
+ * over the 8 XCDs: both bounds must be multiples of 8, so every XCD gets
+ * cu_count / 8 CUs).  Default priority.  The caller owns the stream
+ * (hipStreamDestroy).  LBM_EINVAL for a bad range or NULL out, LBM_EHIP if the
+ * runtime refuses the mask. */
+int lbm_partition_stream(int32_t cu_first, int32_t cu_count, hipStream_t* out);
 
 /* Free the host handle (device buffers stay with the caller). */
 void lbm_destroy(lbm_handle* h);

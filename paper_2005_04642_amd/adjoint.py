@@ -3,8 +3,8 @@
 ``rollout(rhoN0, sigma, force, params, nsteps, checkpoint=100)`` runs
 ``nsteps`` steps from the rest state of ``rhoN0`` and returns the colour index
 rho^N of the final state.  It is a ``torch.autograd.Function``: the backward
-pass runs the library's hand-written adjoint (``lbm_adjoint_step``) step by
-step in reverse, recomputing the states of each checkpoint segment forward
+pass runs the library's hand-written adjoint (``lbm_adjoint_steps``, one
+call per segment) step by step in reverse, recomputing the states of each checkpoint segment forward
 from the state saved at its start (the next segment's recompute overlaps the
 current segment's adjoint steps on a second stream), and returns dL/drho^N_0, dL/dsigma and
 dL/dG_ext (the per-site force density).  Every step, forward or adjoint, runs
@@ -18,9 +18,31 @@ import torch
 from . import lbm
 
 
+# Backward passes of lattices up to this many sites confine the recompute to
+# the first RECOMPUTE_CUS CUs and the adjoint steps to the others (512^2 FP32
+# drop: a forward step takes 23 us on 256 CUs and 40 us on 64, the adjoint step
+# 51 us on 256 and 54 us on 192).
+PARTITION_MAX_SITES = 1 << 20
+RECOMPUTE_CUS = 64
+
+_partitions = {}
+
+
+def _partition(device, first, count):
+    """A stream confined to CUs [first, first + count) of `device`, created
+    once per process and kept (torch.cuda.ExternalStream over
+    lbm_partition_stream)."""
+    key = (torch.device(device).index or 0, first, count)
+    if key not in _partitions:
+        with torch.cuda.device(device):
+            ptr = lbm.lbm_partition_stream(first, count)
+        _partitions[key] = torch.cuda.ExternalStream(ptr, device=device)
+    return _partitions[key]
+
+
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, rhoN0, sigma, force, params, nsteps, checkpoint, storage, device, overlap):
+    def forward(ctx, rhoN0, sigma, force, params, nsteps, checkpoint, storage, device, overlap, recompute_cus):
         p = dict(params)
         p["sigma"] = float(sigma)
         solid = p.pop("solid", None)
@@ -64,6 +86,7 @@ class _Rollout(torch.autograd.Function):
         ctx.nsteps = nsteps
         ctx.checkpoint = checkpoint
         ctx.overlap = overlap
+        ctx.recompute_cus = recompute_cus
         ctx.final = cur
         ctx.has_force = force is not None
         ctx.sigma_dtype = sigma.dtype
@@ -85,10 +108,14 @@ class _Rollout(torch.autograd.Function):
         nseg = len(starts)
         # States after a segment's checkpoint are recomputed into a set of
         # buffers of their own.  With two sets, segment k - 1 is recomputed on
-        # a second stream while the adjoint steps of segment k run on the
-        # caller's stream; each set is reused only after the adjoint steps that
-        # read it have finished (events).  Same kernels in the same order on
-        # each stream: the gradients do not depend on the overlap.
+        # a second stream while the adjoint steps of segment k run; each set is
+        # reused only after the adjoint steps that read it have finished
+        # (events).  On small lattices the two streams are confined to disjoint
+        # CUs (lbm_partition_stream, tiles planned for each share with
+        # lbm_set_cu_budget): there a step's march keeps each CU busy for long
+        # with one workgroup, and unconfined streams queue one kernel's
+        # workgroups behind the other's.  Same kernels in the same order on
+        # each stream: the gradients depend on none of this.
         longest = max(e - s for s, e in zip(starts, ends))
         per = max(longest - 1, 1)
         state_bytes = sim.ny * sim.nx * 18 * (8 if T == torch.float64 else 4)
@@ -97,16 +124,29 @@ class _Rollout(torch.autograd.Function):
             free, _ = torch_.cuda.mem_get_info(sim.device)
             overlap = 2 * per * state_bytes <= free // 2
         nsets = 2 if overlap and nseg >= 2 and longest >= 2 else 1   # (checkpoint 1: nothing to recompute)
+        rcus = ctx.recompute_cus
+        ncu = torch_.cuda.get_device_properties(sim.device).multi_processor_count // 8 * 8
+        if rcus is None:
+            rcus = RECOMPUTE_CUS if sim.nx * sim.ny <= PARTITION_MAX_SITES else 0
+        if nsets == 1 or not 0 < rcus < ncu:
+            rcus = 0
         block = torch.empty((nsets, per, sim.ny, 2, 9, sim.nx), dtype=T, device=sim.device)
         base = block.data_ptr()
-        main = torch_.cuda.current_stream(sim.device)
-        side = torch_.cuda.Stream(device=sim.device) if nsets == 2 else main
+        caller = torch_.cuda.current_stream(sim.device)
+        if rcus:
+            side = _partition(sim.device, 0, rcus)
+            main = _partition(sim.device, rcus, ncu - rcus)
+            lbm.lbm_set_cu_budget(sim.h, rcus, ncu - rcus)
+            main.wait_stream(caller)        # the checkpoints and lambda come from the caller's stream
+        else:
+            main = caller
+            side = torch_.cuda.Stream(device=sim.device) if nsets == 2 else main
         h = sim.h
         ws = sim.adjoint_workspace()
         wsp, wsb = ws.data_ptr(), ws.numel()
         dsp, dfp = dsigma.data_ptr(), dforce.data_ptr()
         ms, ss = main.cuda_stream, side.cuda_stream
-        set_pops, step, adj_step = lbm.lbm_set_pops, lbm.lbm_step, lbm.lbm_adjoint_step
+        step_into, adj_steps = lbm.lbm_step_into, lbm.lbm_adjoint_steps
 
         def states_of(k):
             # device pointers of the states t0 .. t1-1 of segment k
@@ -116,14 +156,14 @@ class _Rollout(torch.autograd.Function):
 
         def recompute(k, stream):
             st = states_of(k)
-            for a, b in zip(st[:-1], st[1:]):
-                set_pops(h, a, b)
-                step(h, 1, None, stream)
+            if len(st) > 1:
+                step_into(h, st[0], st[1:], stream)
 
-        lp, lq = lam.data_ptr(), lam_prev.data_ptr()
+        lptr = (lam.data_ptr(), lam_prev.data_ptr())
+        cur = 0                              # lptr[cur] holds dL/d(the state reached so far)
         ev_rec, ev_adj = {}, {}
         if nsets == 2:
-            side.wait_stream(main)          # the checkpoints and lambda come from the caller's stream
+            side.wait_stream(caller)
             recompute(nseg - 1, ss)
             ev_rec[nseg - 1] = side.record_event()
         for k in reversed(range(nseg)):
@@ -136,12 +176,15 @@ class _Rollout(torch.autograd.Function):
                 main.wait_event(ev_rec[k])
             else:
                 recompute(k, ms)
-            for st in reversed(states_of(k)):
-                adj_step(h, st, lp, lq, wsp, wsb, dsp, dfp, ms)
-                lp, lq = lq, lp
+            st = states_of(k)
+            adj_steps(h, st, lptr[cur], lptr[1 - cur], wsp, wsb, dsp, dfp, ms)
+            cur ^= len(st) & 1
             if nsets == 2:
                 ev_adj[k] = main.record_event()
-        L = lam if lp == lam.data_ptr() else lam_prev
+        if rcus:
+            caller.wait_stream(main)        # (main waited for every recompute)
+            lbm.lbm_set_cu_budget(h, 0, 0)
+        L = lam_prev if cur else lam
         drhoN0 = torch.zeros((sim.ny, sim.nx), dtype=T, device=sim.device)
         sim.init_adjoint(L, drhoN0)
         del block
@@ -150,10 +193,11 @@ class _Rollout(torch.autograd.Function):
         ctx.ckpts = None
         dsig = dsigma.to(device=ctx.sigma_device, dtype=ctx.sigma_dtype).reshape(())
         return (drhoN0, dsig, dforce if ctx.has_force else None,
-                None, None, None, None, None, None)
+                None, None, None, None, None, None, None)
 
 
-def rollout(rhoN0, sigma, force, params, nsteps, checkpoint=100, storage="f32", device="cuda:0", overlap=None):
+def rollout(rhoN0, sigma, force, params, nsteps, checkpoint=100, storage="f32", device="cuda:0", overlap=None,
+            recompute_cus=None):
     """rho^N after ``nsteps`` steps from the rest state of ``rhoN0`` ([ny, nx]);
     differentiable with respect to rhoN0, sigma (0-dim tensor) and force
     ([2, ny, nx] tensor or None).
@@ -167,7 +211,12 @@ def rollout(rhoN0, sigma, force, params, nsteps, checkpoint=100, storage="f32", 
     ``overlap``: recompute the next segment's states on a second stream while
     the adjoint steps of the current one run (True), or one after the other
     (False); None chooses True when two segments' states take at most half of
-    the free device memory.  The gradients are the same either way."""
+    the free device memory.  ``recompute_cus``: with the overlap, confine the
+    recompute to that many CUs (a multiple of 8) and the adjoint steps to the
+    rest; None chooses RECOMPUTE_CUS for lattices of at most
+    PARTITION_MAX_SITES sites, 0 leaves both streams on every CU.  The
+    gradients are the same either way."""
     if not torch.is_tensor(sigma):
         sigma = torch.tensor(float(sigma), dtype=torch.float64)
-    return _Rollout.apply(rhoN0, sigma, force, params, int(nsteps), int(checkpoint), storage, device, overlap)
+    return _Rollout.apply(rhoN0, sigma, force, params, int(nsteps), int(checkpoint), storage, device, overlap,
+                          recompute_cus)

@@ -1,6 +1,7 @@
 // C ABI of the chromodynamic MRT lattice Boltzmann step (see include/chromo_lbm.h).
 // Host side: parameter validation, launch planning, kernel dispatch.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdarg>
@@ -42,6 +43,10 @@ bool radius_ok(int r) { return r == 1 || r == 3; }
 
 constexpr long long MAX_SITES = 1LL << 30;  // nx ny: 32-bit indices of two field planes
 constexpr int MAX_ROWS = 65535;             // grid dimension y of the per-row kernels
+// CU masks of streams: the runtime numbers the CUs round-robin over the 8
+// XCDs (bits 0-31 select 4 CUs on each), so ranges in multiples of 8 give
+// every XCD the same share
+constexpr int PARTITION_GRAIN = 8;
 // whole population buffers addressed through one buffer resource (the mask
 // variant of the gather and the four-pass masked step) stay below 2^32 bytes
 constexpr double WHOLE_BUFFER_LIMIT = 4294967296.0;
@@ -292,6 +297,41 @@ int lbm_init(const lbm_params* p, const void* rhoN0, const void* force, void* po
   return LBM_OK;
 }
 
+int lbm_set_cu_budget(lbm_handle* h, int32_t ncu_step, int32_t ncu_adjoint) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (ncu_step < 0 || ncu_adjoint < 0) return fail(LBM_EINVAL, "CU budgets must be >= 0");
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (ncu < 1) ncu = 1;
+  const int bs = ncu_step > 0 ? std::min(ncu_step, ncu) : ncu;
+  const int ba = ncu_adjoint > 0 ? std::min(ncu_adjoint, ncu) : ncu;
+  h->g = plan(h->p, bs, chromo::ntx_for(h->p.storage));
+  h->g_adj = plan(h->p, ba, chromo::ntx_for(h->p.storage, true));
+  return LBM_OK;
+}
+
+int lbm_partition_stream(int32_t cu_first, int32_t cu_count, hipStream_t* out) {
+  g_last_error.clear();
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (cu_first < 0 || cu_count < 1 || cu_first % PARTITION_GRAIN || cu_count % PARTITION_GRAIN)
+    return fail(LBM_EINVAL, "CU range [%d, %d + %d) must start and extend in multiples of %d", cu_first, cu_first,
+                cu_count, PARTITION_GRAIN);
+  int dev = 0, ncu = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  if (cu_first + cu_count > ncu)
+    return fail(LBM_EINVAL, "CU range [%d, %d) beyond the device's %d CUs", cu_first, cu_first + cu_count, ncu);
+  std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+  for (int b = cu_first; b < cu_first + cu_count; ++b) mask[b / 32] |= 1u << (b % 32);
+  hipStream_t s = nullptr;
+  HIP_TRY(hipExtStreamCreateWithCUMask(&s, (uint32_t)mask.size(), mask.data()));
+  *out = s;
+  return LBM_OK;
+}
+
 int lbm_step(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStream_t stream) {
   g_last_error.clear();
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
@@ -310,6 +350,25 @@ int lbm_step_static(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStrea
   int st = step_impl(h, nsteps, stream);
   if (st != LBM_OK || !mass_RB_dev) return st;
   HIP_TRY(h->ops->mass(h->p, h->g, h->pops[h->live], h->scratch, mass_RB_dev, stream));
+  return LBM_OK;
+}
+
+int lbm_step_into(lbm_handle* h, const void* from, int32_t nsteps, void* const* states, hipStream_t stream) {
+  g_last_error.clear();
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  if (nsteps == 0) return LBM_OK;
+  if (!from || !states) return fail(LBM_EINVAL, "from and states must be non-NULL");
+  for (int j = 0; j < nsteps; ++j) {
+    const void* prev = j ? states[j - 1] : from;
+    if (!states[j] || states[j] == prev) return fail(LBM_EINVAL, "states[%d] is NULL or equal to its source", j);
+  }
+  for (int j = 0; j < nsteps; ++j) {
+    h->pops[h->live] = const_cast<void*>(j ? states[j - 1] : from);
+    h->pops[1 - h->live] = states[j];
+    const int st = step_impl(h, 1, stream);
+    if (st != LBM_OK) return st;
+  }
   return LBM_OK;
 }
 
@@ -365,21 +424,49 @@ static const unsigned char* bounce_bits(const lbm_handle* h) {
   return static_cast<const unsigned char*>(h->solid_ws) + chromo::solid::bits_offset((size_t)h->g.plane, elem);
 }
 
-int lbm_adjoint_step(lbm_handle* h, const void* pops_t, const void* adj_next, void* adj_out, void* workspace,
-                     size_t ws_bytes, double* dL_dsigma_dev, void* dL_dforce_dev, hipStream_t stream) {
-  g_last_error.clear();
+// argument checks shared by lbm_adjoint_step and lbm_adjoint_steps
+static int adjoint_args(lbm_handle* h, const void* adj_a, const void* adj_b, const void* workspace,
+                        size_t ws_bytes) {
   if (!h) return fail(LBM_EINVAL, "handle is NULL");
   int st = adjoint_supported(h);
   if (st != LBM_OK) return st;
-  if (!pops_t || !adj_next || !adj_out || !workspace)
-    return fail(LBM_EINVAL, "pops_t, adj_next, adj_out and workspace must be non-NULL");
-  if (adj_next == adj_out) return fail(LBM_EINVAL, "adj_next and adj_out must differ");
+  if (!adj_a || !adj_b || !workspace) return fail(LBM_EINVAL, "adjoint buffers and workspace must be non-NULL");
+  if (adj_a == adj_b) return fail(LBM_EINVAL, "the two adjoint buffers must differ");
   if (ws_bytes < lbm_adjoint_workspace_bytes(&h->p))
     return fail(LBM_EINVAL, "adjoint workspace too small: %zu < %zu", ws_bytes, lbm_adjoint_workspace_bytes(&h->p));
   if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(LBM_EINVAL, "workspace not 256-byte aligned");
+  return LBM_OK;
+}
+
+int lbm_adjoint_step(lbm_handle* h, const void* pops_t, const void* adj_next, void* adj_out, void* workspace,
+                     size_t ws_bytes, double* dL_dsigma_dev, void* dL_dforce_dev, hipStream_t stream) {
+  g_last_error.clear();
+  int st = adjoint_args(h, adj_next, adj_out, workspace, ws_bytes);
+  if (st != LBM_OK) return st;
+  if (!pops_t) return fail(LBM_EINVAL, "pops_t must be non-NULL");
   hipError_t e = h->ops->adjoint(h->p, h->g_adj, pops_t, h->force, adj_next, adj_out, workspace, dL_dsigma_dev,
                                  dL_dforce_dev, h->solid, bounce_bits(h), stream);
   if (e != hipSuccess) return fail(LBM_EHIP, "adjoint launch: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+int lbm_adjoint_steps(lbm_handle* h, int32_t nsteps, const void* const* states, void* adj_a, void* adj_b,
+                      void* workspace, size_t ws_bytes, double* dL_dsigma_dev, void* dL_dforce_dev,
+                      hipStream_t stream) {
+  g_last_error.clear();
+  int st = adjoint_args(h, adj_a, adj_b, workspace, ws_bytes);
+  if (st != LBM_OK) return st;
+  if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+  if (nsteps > 0 && !states) return fail(LBM_EINVAL, "states must be non-NULL");
+  for (int j = 0; j < nsteps; ++j)
+    if (!states[j]) return fail(LBM_EINVAL, "states[%d] is NULL", j);
+  for (int k = 0; k < nsteps; ++k) {
+    const void* in = (k & 1) ? adj_b : adj_a;
+    void* out = (k & 1) ? adj_a : adj_b;
+    hipError_t e = h->ops->adjoint(h->p, h->g_adj, states[nsteps - 1 - k], h->force, in, out, workspace,
+                                   dL_dsigma_dev, dL_dforce_dev, h->solid, bounce_bits(h), stream);
+    if (e != hipSuccess) return fail(LBM_EHIP, "adjoint launch: %s", hipGetErrorString(e));
+  }
   return LBM_OK;
 }
 

@@ -24,9 +24,10 @@ LBM_FLAG_STREAM_ONLY, LBM_FLAG_FIXED_K, LBM_FLAG_NO_RECOLOR, LBM_FLAG_MASK_PASSE
 
 # every symbol the header declares
 EXPORTED = ("lbm_validate_params", "lbm_pops_elems", "lbm_pops_bytes", "lbm_workspace_bytes", "lbm_init",
-            "lbm_step", "lbm_step_static", "lbm_fields", "lbm_masses_host", "lbm_adjoint_workspace_bytes", "lbm_adjoint_step",
+            "lbm_step", "lbm_step_static", "lbm_step_into", "lbm_fields", "lbm_masses_host",
+            "lbm_adjoint_workspace_bytes", "lbm_adjoint_step", "lbm_adjoint_steps",
             "lbm_rhoN_adjoint", "lbm_init_adjoint", "lbm_solid_workspace_bytes", "lbm_set_solid",
-            "lbm_current_pops", "lbm_set_pops", "lbm_step_count",
+            "lbm_current_pops", "lbm_set_pops", "lbm_step_count", "lbm_set_cu_budget", "lbm_partition_stream",
             "lbm_destroy", "lbm_last_error", "lbm_batch_pops_bytes", "lbm_batch_offsets", "lbm_batch_workspace_bytes",
             "lbm_batch_init", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_set_force", "lbm_batch_set_solid",
             "lbm_batch_plan_info",
@@ -89,6 +90,10 @@ def load_library(path=None):
     lib.lbm_adjoint_workspace_bytes.restype = sz
     lib.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp]
     lib.lbm_adjoint_step.restype = ctypes.c_int
+    lib.lbm_adjoint_steps.argtypes = [vp, i32, ctypes.POINTER(vp), vp, vp, vp, sz, vp, vp, vp]
+    lib.lbm_adjoint_steps.restype = ctypes.c_int
+    lib.lbm_step_into.argtypes = [vp, vp, i32, ctypes.POINTER(vp), vp]
+    lib.lbm_step_into.restype = ctypes.c_int
     lib.lbm_rhoN_adjoint.argtypes = [vp, vp, vp, vp, vp]
     lib.lbm_rhoN_adjoint.restype = ctypes.c_int
     lib.lbm_init_adjoint.argtypes = [vp, vp, vp, vp, vp]
@@ -103,6 +108,10 @@ def load_library(path=None):
     lib.lbm_set_pops.restype = ctypes.c_int
     lib.lbm_step_count.argtypes = [vp]
     lib.lbm_step_count.restype = ctypes.c_int64
+    lib.lbm_set_cu_budget.argtypes = [vp, i32, i32]
+    lib.lbm_set_cu_budget.restype = ctypes.c_int
+    lib.lbm_partition_stream.argtypes = [i32, i32, ctypes.POINTER(vp)]
+    lib.lbm_partition_stream.restype = ctypes.c_int
     lib.lbm_destroy.argtypes = [vp]
     lib.lbm_destroy.restype = None
     lib.lbm_last_error.argtypes = []
@@ -232,6 +241,26 @@ def lbm_adjoint_step(h, pops_t_ptr, adj_next_ptr, adj_out_ptr, ws_ptr, ws_bytes,
                                             dforce_ptr, stream))
 
 
+def lbm_adjoint_steps(h, state_ptrs, adj_a_ptr, adj_b_ptr, ws_ptr, ws_bytes, dsigma_ptr, dforce_ptr, stream):
+    """len(state_ptrs) adjoint steps backwards through the states (device
+    pointers, oldest first); the result is in adj_a for an even count, else
+    adj_b."""
+    lib = load_library()
+    n = len(state_ptrs)
+    arr = (ctypes.c_void_p * max(n, 1))(*state_ptrs)
+    return _check(lib, lib.lbm_adjoint_steps(h, n, arr, adj_a_ptr, adj_b_ptr, ws_ptr, ws_bytes, dsigma_ptr,
+                                             dforce_ptr, stream))
+
+
+def lbm_step_into(h, from_ptr, state_ptrs, stream):
+    """len(state_ptrs) steps from the state at from_ptr, the state after
+    step j written to state_ptrs[j]."""
+    lib = load_library()
+    n = len(state_ptrs)
+    arr = (ctypes.c_void_p * max(n, 1))(*state_ptrs)
+    return _check(lib, lib.lbm_step_into(h, from_ptr, n, arr, stream))
+
+
 def lbm_rhoN_adjoint(h, pops_ptr, dL_drhoN_ptr, adj_out_ptr, stream):
     lib = load_library()
     return _check(lib, lib.lbm_rhoN_adjoint(h, pops_ptr, dL_drhoN_ptr, adj_out_ptr, stream))
@@ -262,6 +291,20 @@ def lbm_set_pops(h, live_ptr, next_ptr):
 
 def lbm_step_count(h):
     return load_library().lbm_step_count(h)
+
+
+def lbm_set_cu_budget(h, ncu_step, ncu_adjoint):
+    lib = load_library()
+    return _check(lib, lib.lbm_set_cu_budget(h, int(ncu_step), int(ncu_adjoint)))
+
+
+def lbm_partition_stream(cu_first, cu_count):
+    """A new HIP stream (as an int handle) confined to CUs [cu_first,
+    cu_first + cu_count) of the current device; the caller owns it."""
+    lib = load_library()
+    out = ctypes.c_void_p()
+    _check(lib, lib.lbm_partition_stream(int(cu_first), int(cu_count), ctypes.byref(out)))
+    return out.value
 
 
 def lbm_destroy(h):
@@ -343,6 +386,13 @@ class Simulation:
 
     def step(self, n=1, with_mass=False):
         lbm_step(self.h, int(n), self.mass.data_ptr() if with_mass else None, self.stream())
+        return self
+
+    def set_cu_budget(self, step=0, adjoint=0):
+        """Plan the forward step's tiles for `step` CUs and the adjoint's first
+        pass for `adjoint` CUs (0: the whole device), for work run on streams
+        confined to that many CUs (lbm_partition_stream)."""
+        lbm_set_cu_budget(self.h, step, adjoint)
         return self
 
     def fields(self):

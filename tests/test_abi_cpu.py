@@ -171,3 +171,24 @@ def test_solid_mask_availability_and_argument_errors():
     assert lib.lbm_set_solid(None, None, None, 0, None) == lbm.LBM_EINVAL
     assert lib.lbm_batch_set_solid(None, 0, None, None, 0, None) == lbm.LBM_EINVAL
     assert lib.lbm_batch_set_force(None, 0, None, None) == lbm.LBM_EINVAL
+
+
+def test_partition_stream_and_cu_budget_argument_checks():
+    """Checked before any device call: CU ranges in multiples of 8, a handle
+    for the CU budget."""
+    for first, count in ((3, 8), (0, 0), (-8, 8), (8, 12)):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_partition_stream(first, count)
+        assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_set_cu_budget(None, 0, 0)
+    assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_trajectory_entry_point_argument_checks():
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_step_into(None, None, [], None)
+    assert e.value.code == lbm.LBM_EINVAL
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_adjoint_steps(None, [], None, None, None, 0, None, None, None)
+    assert e.value.code == lbm.LBM_EINVAL

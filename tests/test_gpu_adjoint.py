@@ -513,24 +513,109 @@ def test_checkpointing_does_not_change_gradients():
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_recompute_overlap_does_not_change_gradients(storage):
-    """The backward pass with the next segment recomputed on a second stream
-    gives bit-identical gradients to the one-stream backward (5 segments, the
-    last one shorter)."""
+    """The backward pass with the next segment recomputed on a second stream,
+    unconfined or with the two streams on disjoint CUs (64 for the recompute,
+    the rest for the adjoint), gives bit-identical gradients to the one-stream
+    backward (5 segments, the last one shorter)."""
     n, steps, params, rn0, target, force = fd_case()
     T = torch.float64 if storage == "f64" else torch.float32
     tgt = torch.tensor(target, dtype=T, device=DEV)
     grads = []
-    for ov in (False, True):
+    for ov, rc in ((False, 0), (True, 0), (True, 64), (None, None)):
         rn_t = torch.tensor(rn0, dtype=T, device=DEV, requires_grad=True)
         sig_t = torch.tensor(0.01, dtype=torch.float64, requires_grad=True)
         f_t = torch.tensor(force, dtype=T, device=DEV, requires_grad=True)
         out = adjoint.rollout(rn_t, sig_t, f_t, params, steps, checkpoint=5, storage=storage, device=DEV,
-                              overlap=ov)
+                              overlap=ov, recompute_cus=rc)
         ((out - tgt) ** 2).sum().backward()
         grads.append((rn_t.grad.cpu().numpy(), float(sig_t.grad), f_t.grad.cpu().numpy()))
-    assert np.array_equal(grads[0][0], grads[1][0])
-    assert grads[0][1] == grads[1][1]
-    assert np.array_equal(grads[0][2], grads[1][2])
+    for g in grads[1:]:
+        assert np.array_equal(grads[0][0], g[0])
+        assert grads[0][1] == g[1]
+        assert np.array_equal(grads[0][2], g[2])
+
+
+def test_trajectory_calls_equal_single_steps():
+    """lbm_step_into (a trajectory into separate buffers, one call) equals
+    lbm_step one step at a time, and lbm_adjoint_steps (backwards through it,
+    one call) equals lbm_adjoint_step per step: states, adjoints and
+    dL/dsigma bit for bit, for an even and an odd number of steps."""
+    n = 48
+    params = Wk.base_params(Lambda=10.0, sigma=0.01)
+    rn0 = Wk.static_drop(n, n, 12.0)
+    for steps in (6, 7):
+        sim = lbm.Simulation(n, n, params, rn0, storage="f64", device=DEV)
+        sim.step(5)
+        S0 = sim.live_pops().clone()
+        states = [S0] + [sim.pops_like() for _ in range(steps - 1)]
+        lbm.lbm_step_into(sim.h, S0.data_ptr(), [t.data_ptr() for t in states[1:]], sim.stream())
+        live, nxt = S0.clone(), sim.pops_like()
+        sim.set_pops(live, nxt)
+        ref = [S0]
+        for _ in range(steps - 1):
+            sim.step(1)
+            ref.append(sim.live_pops().clone())
+        for a, b in zip(states, ref):
+            assert torch.equal(a, b)
+        g = torch.Generator(device=DEV).manual_seed(5)
+        lam0 = 1e-3 * torch.randn((2, 9, n, n), generator=g, device=DEV, dtype=torch.float64)
+        ws = sim.adjoint_workspace()
+        # one call
+        A, B = sim.pops_like(), sim.pops_like()
+        A.copy_(lam0)
+        ds1 = torch.zeros(1, dtype=torch.float64, device=DEV)
+        df1 = torch.zeros((2, n, n), dtype=torch.float64, device=DEV)
+        lbm.lbm_adjoint_steps(sim.h, [t.data_ptr() for t in states], A.data_ptr(), B.data_ptr(), ws.data_ptr(),
+                              ws.numel(), ds1.data_ptr(), df1.data_ptr(), sim.stream())
+        got = A if steps % 2 == 0 else B
+        # step by step
+        cur, nxt = sim.pops_like(), sim.pops_like()
+        cur.copy_(lam0)
+        ds2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+        df2 = torch.zeros((2, n, n), dtype=torch.float64, device=DEV)
+        for t in reversed(states):
+            sim.adjoint_step(t, cur, nxt, ds2, df2)
+            cur, nxt = nxt, cur
+        assert torch.equal(got, cur)
+        assert float(ds1) == float(ds2)
+        assert torch.equal(df1, df2)
+        sim.close()
+
+
+def test_cu_budget_does_not_change_results():
+    """Tiles planned for fewer CUs (lbm_set_cu_budget), run on a stream
+    confined to them (lbm_partition_stream): the same states and adjoints, bit
+    for bit."""
+    n = 160
+    params = Wk.base_params(Lambda=10.0, sigma=0.01)
+    rn0 = Wk.static_drop(n, n, 40.0)
+    ref = lbm.Simulation(n, n, params, rn0, storage="f32", device=DEV)
+    ref.step(30)
+    S = ref.live_pops().clone()
+    g = torch.Generator(device=DEV).manual_seed(3)
+    lam = ref.pops_like()
+    lam.copy_(1e-3 * torch.randn((2, 9, n, n), generator=g, device=DEV))
+    outs = []
+    for budget, cus in ((0, None), (64, (0, 64)), (192, (64, 192))):
+        sim = lbm.Simulation(n, n, params, rn0, storage="f32", device=DEV)
+        sim.set_cu_budget(budget, budget)
+        # (the rollout's own confined streams, created once per process)
+        strm = adjoint._partition(DEV, *cus) if cus else torch.cuda.current_stream()
+        strm.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(strm):
+            sim.step(30)
+            out = sim.pops_like()
+            ds = torch.zeros(1, dtype=torch.float64, device=DEV)
+            sim.adjoint_step(S, lam, out, ds)
+        torch.cuda.current_stream().wait_stream(strm)
+        torch.cuda.synchronize()
+        outs.append((sim.live_pops().clone(), out, float(ds)))
+        sim.close()
+    for o in outs[1:]:
+        assert torch.equal(outs[0][0], o[0])
+        assert torch.equal(outs[0][1], o[1])
+        assert outs[0][2] == o[2]
+    ref.close()
 
 
 def test_adjoint_workload_gradient_against_finite_differences():
