@@ -535,16 +535,23 @@ def test_recompute_overlap_does_not_change_gradients(storage):
         assert np.array_equal(grads[0][2], g[2])
 
 
-def test_trajectory_calls_equal_single_steps():
+@pytest.mark.parametrize("kind", ["periodic", "walls", "mask"])
+def test_trajectory_calls_equal_single_steps(kind):
     """lbm_step_into (a trajectory into separate buffers, one call) equals
     lbm_step one step at a time, and lbm_adjoint_steps (backwards through it,
     one call) equals lbm_adjoint_step per step: states, adjoints and
-    dL/dsigma bit for bit, for an even and an odd number of steps."""
+    dL/dsigma bit for bit, for an even and an odd number of steps, on a
+    periodic, a walled and a masked lattice."""
     n = 48
     params = Wk.base_params(Lambda=10.0, sigma=0.01)
+    solid = None
+    if kind == "walls":
+        params = dict(params, walls=True)
+    elif kind == "mask":
+        solid = Wk.circular_wall(n, n, 22.0)
     rn0 = Wk.static_drop(n, n, 12.0)
     for steps in (6, 7):
-        sim = lbm.Simulation(n, n, params, rn0, storage="f64", device=DEV)
+        sim = lbm.Simulation(n, n, params, rn0, storage="f64", device=DEV, solid=solid)
         sim.step(5)
         S0 = sim.live_pops().clone()
         states = [S0] + [sim.pops_like() for _ in range(steps - 1)]
