@@ -562,8 +562,9 @@ def test_trajectory_calls_equal_single_steps(kind):
         for _ in range(steps - 1):
             sim.step(1)
             ref.append(sim.live_pops().clone())
+        rows = slice(1, n - 1) if kind == "walls" else slice(0, n)   # (wall rows hold no state: never written)
         for a, b in zip(states, ref):
-            assert torch.equal(a, b)
+            assert torch.equal(a[:, :, rows], b[:, :, rows])
         g = torch.Generator(device=DEV).manual_seed(5)
         lam0 = 1e-3 * torch.randn((2, 9, n, n), generator=g, device=DEV, dtype=torch.float64)
         ws = sim.adjoint_workspace()
