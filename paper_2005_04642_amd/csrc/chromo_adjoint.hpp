@@ -31,7 +31,10 @@
 namespace chromo {
 namespace adj {
 
-// planes of the adjoint workspace after the SV_N save planes
+// Planes of the adjoint workspace, in groups: SV (forward values pass 1
+// saves, SV_*), A (pass 1's local adjoints), B (pass 2's outputs), C (pass 3),
+// D (pass 4).  A workspace row holds the row of every plane, group after
+// group ([y][WS_PLANES][x]).
 enum {
   A_F = 0,  // 9 planes: adjoint of f_i through the collision
   A_RR = 9, A_RB, A_UX, A_UY, A_GX, A_GY, A_DPX, A_DPY, A_TH, A_RN, A_MX, A_MY,
