@@ -134,8 +134,14 @@ class _Rollout(torch.autograd.Function):
         base = block.data_ptr()
         caller = torch_.cuda.current_stream(sim.device)
         if rcus:
-            side = _partition(sim.device, 0, rcus)
-            main = _partition(sim.device, rcus, ncu - rcus)
+            try:
+                side = _partition(sim.device, 0, rcus)
+                main = _partition(sim.device, rcus, ncu - rcus)
+            except lbm.LbmError:
+                if ctx.recompute_cus:       # asked for explicitly: report it
+                    raise
+                rcus = 0                    # the runtime refused CU masks: unconfined streams
+        if rcus:
             lbm.lbm_set_cu_budget(sim.h, rcus, ncu - rcus)
             main.wait_stream(caller)        # the checkpoints and lambda come from the caller's stream
         else:
