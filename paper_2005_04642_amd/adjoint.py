@@ -50,35 +50,27 @@ class _Rollout(torch.autograd.Function):
         sim = lbm.Simulation(nx, ny, p, rhoN0.detach(), storage=storage, device=device,
                              force=None if force is None else force.detach(), solid=solid)
         # Every checkpointed state (and the final one) gets a buffer of its own,
-        # written directly by the step that produces it (lbm_set_pops); the steps
-        # in between alternate between two scratch buffers.  No state is copied
-        # after the first, so a checkpoint every step costs no extra traffic.
-        # All of them come from one allocation.
+        # written directly by the step that produces it; the steps in between
+        # alternate between two scratch buffers.  No state is copied after the
+        # first, so a checkpoint every step costs no extra traffic.  All of
+        # them come from one allocation, and the whole trajectory is one call
+        # (lbm_step_into: no host call per step).
         nseg = len(range(0, nsteps, checkpoint))
         block = torch.empty((nseg + 3, ny, 2, 9, nx), dtype=sim.dtype, device=sim.device)
         bufs = [block[i].permute(1, 2, 0, 3) for i in range(nseg + 3)]   # pops_like() views
         cur = bufs[0]
         cur.copy_(sim.live_pops())
         scratch = (bufs[1], bufs[2])
-        # (straight C calls with the stream looked up once: with a checkpoint
-        # every step the Python wrappers would cost more than the step itself)
         h, stream = sim.h, sim.stream()
-
-        def steps_into(src, dst, n):
-            lbm.lbm_set_pops(h, src.data_ptr(), dst.data_ptr())
-            lbm.lbm_step(h, n, None, stream)
-
         ckpts = {}
+        ptrs = []
         for j, t in enumerate(range(0, nsteps, checkpoint)):
             ckpts[t] = cur
             k = min(checkpoint, nsteps - t)
-            dst = bufs[3 + j]
-            if k >= 2:
-                steps_into(cur, scratch[0], 1)
-                steps_into(scratch[0], scratch[1], k - 2)
-                cur = scratch[(k - 2) % 2]   # live after the k - 1 steps so far
-            steps_into(cur, dst, 1)
-            cur = dst
+            ptrs += [scratch[i % 2].data_ptr() for i in range(k - 1)]
+            cur = bufs[3 + j]
+            ptrs.append(cur.data_ptr())
+        lbm.lbm_step_into(h, bufs[0].data_ptr(), ptrs, stream)
         sim.set_pops(cur, scratch[0])        # the Simulation's own views follow the handle again
         out = sim.fields()["rhoN"]
         ctx.sim = sim
