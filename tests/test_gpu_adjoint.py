@@ -590,6 +590,16 @@ def test_trajectory_calls_equal_single_steps(kind):
         sim.close()
 
 
+def test_partition_stream_range_beyond_the_device():
+    """A CU range past the device's CUs is refused (LBM_EINVAL) before any
+    stream is created; a whole-device range is accepted."""
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count // 8 * 8
+    with pytest.raises(lbm.LbmError) as e:
+        lbm.lbm_partition_stream(ncu - 8, 16)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert lbm.lbm_partition_stream(0, ncu)
+
+
 def test_cu_budget_does_not_change_results():
     """Tiles planned for fewer CUs (lbm_set_cu_budget), run on a stream
     confined to them (lbm_partition_stream): the same states and adjoints, bit
