@@ -192,3 +192,26 @@ def test_trajectory_entry_point_argument_checks():
     with pytest.raises(lbm.LbmError) as e:
         lbm.lbm_adjoint_steps(None, [], None, None, None, 0, None, None, None)
     assert e.value.code == lbm.LBM_EINVAL
+
+
+def test_plain_c_program_uses_the_abi(tmp_path):
+    """The header is plain C (C99, -Wall -Wextra -Werror) and a C program
+    linked against the library gets the documented results of the host-side
+    entry points (tests/c_consumer.c; no GPU needed)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    libdir = os.path.join(root, "paper_2005_04642_amd")
+    exe = str(tmp_path / "c_consumer")
+    cmd = [gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(root, "include"), "-I", "/opt/rocm/include",
+           os.path.join(root, "tests", "c_consumer.c"), "-o", exe,
+           "-L", libdir, "-lchromo_lbm", "-Wl,-rpath," + libdir]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "0 failed checks" in r.stdout
