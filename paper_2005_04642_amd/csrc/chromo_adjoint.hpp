@@ -430,6 +430,50 @@ static __device__ __forceinline__ double block_sum(double v) {
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ size_t ws_rs(const Geom& g) { return (size_t)WS_PLANES * (size_t)g.nx; }
 
+// Local part of pass 2 at one site: from the adjoints of u (with the
+// transposed div u already added: lux, luy) and of Phi' (lphi), the site's
+// saved forward values s and local adjoints a (pointers at the site, planes nx
+// apart) give the B values, dL/dG_ext and the site's dL/dsigma term.
+template <typename T>
+struct Pass2 {
+  T b[B_N];
+  T lGx, lGy;
+  double dsig;
+};
+
+template <typename T>
+__device__ __forceinline__ Pass2<T> pass2_site(const Coef<T>& c, T sigma, const T* a, const T* s, int nx, T lux,
+                                               T luy, T lphi) {
+  Pass2<T> q;
+  const T rR = s[SV_RR * nx], rB = s[SV_RB * nx];
+  const T rho = rR + rB;
+  const T ux = s[SV_UX * nx], uy = s[SV_UY * nx];
+  const T K = s[SV_K * nx];
+  const T gx = s[SV_GNX * nx], gy = s[SV_GNY * nx];
+  // Phi' = c06R rR + phiB rB - rho / 3
+  T lrR = a[A_RR * nx] + (c.c06R - T(1.0 / 3.0)) * lphi;
+  T lrB = a[A_RB * nx] + (c.phiB - T(1.0 / 3.0)) * lphi;
+  // u = (j + G/2) / rho
+  const T irho = T(1) / rho;
+  const T ljx = lux * irho, ljy = luy * irho;
+  const T lrho = -(lux * ux + luy * uy) * irho;
+  lrR += lrho;
+  lrB += lrho;
+  q.lGx = a[A_GX * nx] + T(0.5) * ljx;
+  q.lGy = a[A_GY * nx] + T(0.5) * ljy;
+  // G = sigma K g / 2 + G_ext
+  const T lGg = q.lGx * gx + q.lGy * gy;
+  q.dsig = 0.5 * (double)K * (double)lGg;
+  q.b[B_RR] = lrR;
+  q.b[B_RB] = lrB;
+  q.b[B_JX] = ljx;
+  q.b[B_JY] = ljy;
+  q.b[B_K] = c.fixed_K ? T(0) : T(0.5) * sigma * lGg;
+  q.b[B_GX] = T(0.5) * sigma * K * q.lGx;
+  q.b[B_GY] = T(0.5) * sigma * K * q.lGy;
+  return q;
+}
+
 // pass 2: div u and grad Phi' transposed; u, Phi', G local
 template <typename T, bool W, bool M = false>
 __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, Radii r, const T* __restrict__ sv,
@@ -476,36 +520,14 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, 
       luy = a[A_UY * nx] - ty;
       lphi = -div_r(r.p, A + A_DPX * nx, A + A_DPY * nx, RS, nx, g.ny, x, y);
     }
-    const T rR = s[SV_RR * nx], rB = s[SV_RB * nx];
-    const T rho = rR + rB;
-    const T ux = s[SV_UX * nx], uy = s[SV_UY * nx];
-    const T K = s[SV_K * nx];
-    const T gx = s[SV_GNX * nx], gy = s[SV_GNY * nx];
-    // Phi' = c06R rR + phiB rB - rho / 3
-    T lrR = a[A_RR * nx] + (c.c06R - T(1.0 / 3.0)) * lphi;
-    T lrB = a[A_RB * nx] + (c.phiB - T(1.0 / 3.0)) * lphi;
-    // u = (j + G/2) / rho
-    const T irho = T(1) / rho;
-    const T ljx = lux * irho, ljy = luy * irho;
-    const T lrho = -(lux * ux + luy * uy) * irho;
-    lrR += lrho;
-    lrB += lrho;
-    const T lGx = a[A_GX * nx] + T(0.5) * ljx;
-    const T lGy = a[A_GY * nx] + T(0.5) * ljy;
-    // G = sigma K g / 2 + G_ext
+    const Pass2<T> q = pass2_site(c, sigma, a, s, nx, lux, luy, lphi);
     if (dforce) {
-      dforce[site] += lGx;
-      dforce[P + site] += lGy;
+      dforce[site] += q.lGx;
+      dforce[P + site] += q.lGy;
     }
-    const T lGg = lGx * gx + lGy * gy;
-    acc = 0.5 * (double)K * (double)lGg;
-    b[B_RR * nx] = lrR;
-    b[B_RB * nx] = lrB;
-    b[B_JX * nx] = ljx;
-    b[B_JY * nx] = ljy;
-    b[B_K * nx] = c.fixed_K ? T(0) : T(0.5) * sigma * lGg;
-    b[B_GX * nx] = T(0.5) * sigma * K * lGx;
-    b[B_GY * nx] = T(0.5) * sigma * K * lGy;
+    acc = q.dsig;
+#pragma unroll
+    for (int k = 0; k < B_N; ++k) b[k * nx] = q.b[k];
   }
   const double tot = block_sum(acc);
   if (threadIdx.x == 0) part[blockIdx.y * gridDim.x + blockIdx.x] = tot;
@@ -514,6 +536,22 @@ __global__ void __launch_bounds__(256) force_kernel(Geom g, Coef<T> c, T sigma, 
 // ---------------------------------------------------------------------------
 // pass 3: K = -div m transposed; m = g / sqrt(|g|^2 + eps^2)
 // ---------------------------------------------------------------------------
+// Local part of pass 3 at one site: (kx, ky) = the transposed K = -div m
+// applied to lambda_K; bgx, bgy: the site's B_GX, B_GY.
+template <typename T>
+__device__ __forceinline__ void pass3_site(const Coef<T>& c, const T* a, const T* s, int nx, T bgx, T bgy, T kx, T ky,
+                                           T& cgx, T& cgy) {
+  const T lmx = a[A_MX * nx] + kx;  // -(-D)^T = D
+  const T lmy = a[A_MY * nx] + ky;
+  const T gx = s[SV_GNX * nx], gy = s[SV_GNY * nx];
+  const T s2 = gx * gx + gy * gy + c.eps2;
+  const T is = T(1) / sqrt(s2);
+  const T dot = (lmx * gx + lmy * gy) * is * is * is;
+  cgx = bgx + lmx * is - gx * dot;
+  cgy = bgy + lmy * is - gy * dot;
+}
+
+
 // One extra row of workgroups, dispatched first (blockIdx.y == 0; lattice row y
 // is blockIdx.y - 1): its first workgroup adds the sum of pass 2's
 // per-workgroup dL/dsigma partials to *dsigma while the other workgroups run
@@ -572,19 +610,26 @@ __global__ void __launch_bounds__(256) director_kernel(Geom g, Coef<T> c, Radii 
   } else {
     grad_r(r.k, B + B_K * nx, RS, nx, g.ny, x, y, kx, ky);
   }
-  const T lmx = a[A_MX * nx] + kx;  // -(-D)^T = D
-  const T lmy = a[A_MY * nx] + ky;
-  const T gx = s[SV_GNX * nx], gy = s[SV_GNY * nx];
-  const T s2 = gx * gx + gy * gy + c.eps2;
-  const T is = T(1) / sqrt(s2);
-  const T dot = (lmx * gx + lmy * gy) * is * is * is;
-  o[C_GX * nx] = b[B_GX * nx] + lmx * is - gx * dot;
-  o[C_GY * nx] = b[B_GY * nx] + lmy * is - gy * dot;
+  pass3_site(c, a, s, nx, b[B_GX * nx], b[B_GY * nx], kx, ky, o[C_GX * nx], o[C_GY * nx]);
 }
 
 // ---------------------------------------------------------------------------
 // pass 4: grad rho^N transposed; colour index
 // ---------------------------------------------------------------------------
+// Local part of pass 4 at one site: dv = div lambda_g (the transposed
+// grad rho^N with its sign); brr, brb: the site's B_RR, B_RB.
+template <typename T>
+__device__ __forceinline__ void pass4_site(const Coef<T>& c, const T* a, const T* s, int nx, T brr, T brb, T dv,
+                                           T& drr, T& drb) {
+  const T lrN = a[A_RN * nx] - dv;
+  const T ra = s[SV_RR * nx] * c.inv_rho0R, rb = s[SV_RB * nx] * c.inv_rho0B;
+  const T is = T(1) / (ra + rb);
+  const T w = T(2) * lrN * is * is;
+  drr = brr + w * rb * c.inv_rho0R;
+  drb = brb - w * ra * c.inv_rho0B;
+}
+
+
 template <typename T, bool W, bool M = false>
 __global__ void __launch_bounds__(256) colour_kernel(Geom g, Coef<T> c, Radii r, const T* __restrict__ sv,
                                                      const T* __restrict__ A, const T* __restrict__ B,
@@ -614,14 +659,8 @@ __global__ void __launch_bounds__(256) colour_kernel(Geom g, Coef<T> c, Radii r,
   } else {
     dv = div_r(r.g, C + C_GX * nx, C + C_GY * nx, RS, nx, g.ny, x, y);
   }
-  const T* s = sv + row;
   const T* b = B + row;
-  const T lrN = A[row + A_RN * nx] - dv;
-  const T ra = s[SV_RR * nx] * c.inv_rho0R, rb = s[SV_RB * nx] * c.inv_rho0B;
-  const T is = T(1) / (ra + rb);
-  const T w = T(2) * lrN * is * is;
-  o[D_RR * nx] = b[B_RR * nx] + w * rb * c.inv_rho0R;
-  o[D_RB * nx] = b[B_RB * nx] - w * ra * c.inv_rho0B;
+  pass4_site(c, A + row, sv + row, nx, b[B_RR * nx], b[B_RB * nx], dv, o[D_RR * nx], o[D_RB * nx]);
 }
 
 // ---------------------------------------------------------------------------
