@@ -397,7 +397,9 @@ int lbm_set_cu_budget(lbm_handle* h, int32_t ncu_step, int32_t ncu_adjoint);
 /* Create a HIP stream whose kernels run only on CUs [cu_first, cu_first +
  * cu_count) of the current device, in the runtime's CU numbering (round-robin
  * over the 8 XCDs: both bounds must be multiples of 8, so every XCD gets
- * cu_count / 8 CUs).  Default priority.  The caller owns the stream
+ * cu_count / 8 CUs; multiples of 32 also keep the CUs of each XCD evenly
+ * spread, and run markedly faster than other splits).  Default priority.
+ * The caller owns the stream
  * (hipStreamDestroy).  LBM_EINVAL for a bad range or NULL out, LBM_EHIP if the
  * runtime refuses the mask. */
 int lbm_partition_stream(int32_t cu_first, int32_t cu_count, hipStream_t* out);
