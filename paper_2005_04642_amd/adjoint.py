@@ -210,9 +210,9 @@ def rollout(rhoN0, sigma, force, params, nsteps, checkpoint=100, storage="f32", 
     the adjoint steps of the current one run (True), or one after the other
     (False); None chooses True when two segments' states take at most half of
     the free device memory.  ``recompute_cus``: with the overlap, confine the
-    recompute to that many CUs (a multiple of 8) and the adjoint steps to the
-    rest; None chooses RECOMPUTE_CUS for lattices of at most
-    PARTITION_MAX_SITES sites, 0 leaves both streams on every CU.  The
+    recompute to that many CUs (a multiple of 8; multiples of 32 run best) and
+    the adjoint steps to the rest; None chooses RECOMPUTE_CUS for lattices of
+    at most PARTITION_MAX_SITES sites, 0 leaves both streams on every CU.  The
     gradients are the same either way."""
     if not torch.is_tensor(sigma):
         sigma = torch.tensor(float(sigma), dtype=torch.float64)
