@@ -10,8 +10,10 @@ update = read + write of one site's population words: 144 B for FP32 storage,
 80 B for the 16-bit offset formats), the CPU oracle timed on a bounded
 sample of the same workload, and the adjoint: one lbm_adjoint_step against one
 forward step on the same lattice, the gradient of an interface-shape loss
-over a checkpointed 512^2 rollout of 2000 steps (forward vs backward time), and
-a batch of 256 uneven lattices in one launch per step.
+over a checkpointed 512^2 rollout of 2000 steps (forward vs backward time),
+one eighth of the lattice as a slab of rows with and without halo rows (the
+share of one GPU if the lattice were split over eight), and a batch of 256
+uneven lattices in one launch per step.
 """
 import argparse
 import hashlib
@@ -303,6 +305,39 @@ def adjoint_rollout(torch, n=512, steps=2000, checkpoint=100):
     return res
 
 
+def shard_measure(n, params, rn, torch, nslabs=8, halo=10, steps=200, warmup=20):
+    """The step on one GPU's share of the benchmark lattice split into nslabs
+    slabs of rows (the layout a halo exchange between GPUs would use): the
+    slab alone, and the slab with the halo rows each GPU would march besides
+    its own (halo = field-chain radius 9 + 1 for the gather, on either side),
+    the periodic wrap standing in for the exchanged rows.  The initial colour
+    index is the benchmark's, cut to the slab's rows; FP32."""
+    import numpy as np
+    from paper_2005_04642_amd import lbm
+    rows = n // nslabs
+    out = {"workload": "rows 0..%d of the %dx%d emulsion (one of %d slabs), FP32, %d steps after %d"
+                       % (rows - 1, n, n, nslabs, steps, warmup),
+           "halo_rows_per_side": halo, "halo_bytes_per_face": halo * n * 72}
+    for label, ny in (("slab", rows), ("slab_with_halo", rows + 2 * halo)):
+        sim = lbm.Simulation(n, ny, params, np.ascontiguousarray(rn[:ny]), storage="f32", device="cuda:0")
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.step(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        sim.masses()
+        sim.close()
+        ms = e0.elapsed_time(e1) / steps
+        out[label] = {"nx": n, "ny": ny, "ms_per_step": round(ms, 5), "MLUPS": round(n * ny / ms / 1e3, 1),
+                      "GB_s": round(BYTES_PER_LU["f32"] * n * ny / ms / 1e6, 1)}
+    # useful updates per second of a GPU that marches its slab and both halos
+    out["MLUPS_own_rows_with_halo"] = round(n * rows / out["slab_with_halo"]["ms_per_step"] / 1e3, 1)
+    return out
+
+
 def batch_measure(torch, nsim=256, steps=20):
     """256 independent periodic drops of uneven size (64..512) stepped by one
     launch per step, after the autotuner picked the tile shape; against the same
@@ -362,6 +397,7 @@ def main():
     ap.add_argument("--no-copy-roof", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-shard", action="store_true")
     ap.add_argument("--no-storage16", action="store_true")
     ap.add_argument("--no-solid", action="store_true")
     ap.add_argument("--no-rollout", action="store_true",
@@ -455,6 +491,8 @@ def main():
         if not args.no_rollout:
             out["adjoint_rollout"] = adjoint_rollout(torch)
             out["adjoint_rollout_every_state"] = adjoint_rollout(torch, checkpoint=1)
+    if not args.no_shard and args.storage == "f32":
+        out["shard"] = shard_measure(n, params, rn, torch)
     if not args.no_batch:
         out["batch"] = batch_measure(torch)
     if not args.no_cpu:
