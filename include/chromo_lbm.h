@@ -46,8 +46,11 @@
  * rhoN0, force and the field outputs use the arithmetic type: double for
  * LBM_STORAGE_F64, float for every other format.
  *
- * Streams: every call only enqueues work on the given stream; none of them
- * synchronises, except lbm_masses_host (documented there).
+ * Streams: every call only enqueues work on the given stream, except those
+ * whose comments say they wait for it: lbm_masses_host, and the batch calls
+ * that copy host tables to the device (lbm_batch_init, lbm_batch_autotune,
+ * lbm_batch_set_force, lbm_batch_set_solid) or read results back
+ * (lbm_batch_masses_host).
  *
  * Errors: every entry point returns an lbm_status value; on failure
  * lbm_last_error() gives a message (thread-local).  Handles are not thread-safe.
