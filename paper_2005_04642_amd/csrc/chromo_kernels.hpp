@@ -363,7 +363,7 @@ __device__ __forceinline__ void gather_words(const void* buf, const Geom& g, int
     const __amdgpu_buffer_rsrc_t src = make_rsrc<S>(buf, g.plane);
     const unsigned ro = (unsigned)p * g.rb, rom = (unsigned)rm * g.rb, rop = (unsigned)rp * g.rb;
 #pragma unroll
-    for (int q = 0; q < S::NW; ++q) {
+    for (int q = Q0; q < Q1; ++q) {
       const int i = word_link<S>(q);
       const int dy = link_cy(i), dx = link_cx(i);
       const unsigned soff = (unsigned)q * g.pb + (dy == 1 ? rom : (dy == -1 ? rop : ro));
@@ -577,22 +577,23 @@ struct March {
   T fx[2], fy[2];  // body force of the band-U rows, loaded one iteration ahead
   unsigned bn;     // mask variant: bounce bits of the next band-M row, loaded one iteration ahead
   int prow;        // the next band-M row (wave-uniform), whose words are gathered in two parts
+  unsigned bng;    // mask variant: that row's bounce bits (bn moves on to the following row)
 };
 
 // The words of the next band-M row are gathered in two parts: the first two
 // thirds in band M, the rest just before band U.  Measured on the 4096^2 step
-// (same box, same results): FP32 0.540 -> 0.493 ms, FP16 0.408 -> 0.404 ms;
-// one third or one half first ran slower than two thirds, and five sixths or
-// more first slower than a single part.  The adjoint's march (pass 1) runs
-// 0.5 % slower split and keeps one part, as does the mask variant, whose
-// bounce bits move on to the following row in band M.
+// (same box, same results): FP32 0.540 -> 0.493 ms, FP16 0.408 -> 0.404 ms,
+// with a mask (21.6 % solid) FP32 0.667 -> 0.563 ms; one third or one half
+// first ran slower than two thirds, and five sixths or more first slower
+// than a single part.  The adjoint's march (pass 1) runs 0.5 % slower split
+// and keeps one part.
 template <typename S>
 constexpr int gather_split() {
   return S::NW * 2 / 3;
 }
 template <int MODE, bool MASK>
 constexpr bool split_gather() {
-  return !MASK && MODE != MODE_ADJ;
+  return MODE != MODE_ADJ;
 }
 
 struct Thread {
@@ -833,7 +834,8 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, const v
     if constexpr (!split_gather<MODE, MASK>()) {
       gather_words<ST, WALLS, MASK>(src, g, st.prow, t.cols, st.pw, st.bn);
     } else {
-      gather_words<ST, WALLS, MASK, 0, gather_split<ST>()>(src, g, st.prow, t.cols, st.pw);
+      if constexpr (MASK) st.bng = st.bn;
+      gather_words<ST, WALLS, MASK, 0, gather_split<ST>()>(src, g, st.prow, t.cols, st.pw, MASK ? st.bng : 0u);
     }
     if constexpr (!is_ofs16<ST>::value) __builtin_amdgcn_s_setprio(0);
     tM.advance(g);
@@ -873,7 +875,8 @@ __device__ __forceinline__ void march_iter(int it, const StepArgs<T>& a, const v
   // the rest of the next band-M row's words (see gather_split)
   if constexpr (split_gather<MODE, MASK>()) {
     if constexpr (!is_ofs16<ST>::value) __builtin_amdgcn_s_setprio(1);
-    gather_words<ST, WALLS, MASK, gather_split<ST>(), ST::NW>(src, g, st.prow, t.cols, st.pw);
+    gather_words<ST, WALLS, MASK, gather_split<ST>(), ST::NW>(src, g, st.prow, t.cols, st.pw,
+                                                              MASK ? st.bng : 0u);
     if constexpr (!is_ofs16<ST>::value) __builtin_amdgcn_s_setprio(0);
   }
 
