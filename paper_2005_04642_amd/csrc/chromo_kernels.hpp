@@ -582,11 +582,11 @@ struct March {
 
 // The words of the next band-M row are gathered in two parts: the first two
 // thirds in band M, the rest just before band U.  Measured on the 4096^2 step
-// (same box, same results): FP32 0.540 -> 0.493 ms, FP16 0.408 -> 0.404 ms,
-// with a mask (21.6 % solid) FP32 0.667 -> 0.563 ms; one third or one half
-// first ran slower than two thirds, and five sixths or more first slower
-// than a single part.  The adjoint's march (pass 1) runs 0.5 % slower split
-// and keeps one part.
+// (one MI355X, back to back, same results): FP32 0.540 -> 0.493 ms, FP16
+// 0.408 -> 0.404 ms, with a mask (21.6 % solid) FP32 0.667 -> 0.563 ms; one
+// third or one half first ran slower than two thirds, and five sixths or more
+// first slower than a single part.  The adjoint's march (pass 1) runs 0.5 %
+// slower split and keeps one part.
 template <typename S>
 constexpr int gather_split() {
   return S::NW * 2 / 3;
