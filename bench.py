@@ -406,7 +406,7 @@ def main():
                     help="first run one plain 1 GiB device copy (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the lattice would be "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the lattice would be "
               "split into slabs with a halo exchange per step, not implemented). Use --gpus 1.",
               file=sys.stderr)
         sys.exit(2)

@@ -70,7 +70,7 @@ typedef enum lbm_status {
   LBM_OK = 0,
   LBM_EINVAL = -1,      /* bad sizes, NULL pointers or inconsistent parameters */
   LBM_EHIP = -2,        /* a HIP runtime call or kernel launch failed */
-  LBM_ENOTIMPL = -3,    /* entry point or option not provided by this build */
+  LBM_ENOTIMPL = -3,    /* entry point or option not provided by this library */
   LBM_ENONFINITE = -4   /* a per-colour mass is not finite */
 } lbm_status;
 

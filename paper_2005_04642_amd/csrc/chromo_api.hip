@@ -87,7 +87,7 @@ int validate(const lbm_params* p) {
   if (p->walls_y != 0 && p->walls_y != 1) return fail(LBM_EINVAL, "walls_y must be 0 or 1");
   if (p->walls_y && p->ny < 3) return fail(LBM_EINVAL, "walls need ny >= 3 (one fluid row)");
   if (p->storage < LBM_STORAGE_F64 || p->storage > LBM_STORAGE_BF16_OFS)
-    return fail(LBM_EINVAL, "storage %d not provided by this build", p->storage);
+    return fail(LBM_EINVAL, "storage %d not provided by this library", p->storage);
   // the step kernels address each lattice row through a buffer resource of its
   // own (byte offsets below 2^32 within a row); field planes are indexed with
   // 32-bit integers (two planes for a force field); rows index grid dimension y
