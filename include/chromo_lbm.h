@@ -172,8 +172,10 @@ int lbm_step_static(lbm_handle* h, int32_t nsteps, double* mass_RB_dev, hipStrea
  * array of nsteps device buffers of lbm_pops_bytes(), each distinct from its
  * source): a trajectory kept whole, as the checkpointed adjoint recomputes
  * it, in one call.  The handle then steps on from states[nsteps-1] (as after
- * lbm_set_pops).  LBM_EINVAL for NULL arrays or entries, or a state equal to
- * its source.  Enqueued on `stream`. */
+ * lbm_set_pops), with states[nsteps-2] (`from` when nsteps is 1) as its other
+ * buffer: the next lbm_step writes there, so re-point the handle with
+ * lbm_set_pops first to keep the trajectory whole.  LBM_EINVAL for NULL arrays
+ * or entries, or a state equal to its source.  Enqueued on `stream`. */
 int lbm_step_into(lbm_handle* h, const void* from, int32_t nsteps, void* const* states, hipStream_t stream);
 
 /* Macroscopic fields of the current state (Sec. II, force-adjusted
