@@ -590,6 +590,27 @@ def test_trajectory_calls_equal_single_steps(kind):
         sim.close()
 
 
+def test_step_into_hands_the_last_two_states_to_the_handle():
+    """After lbm_step_into the handle steps on from states[-1] and writes its
+    next step into states[-2] (its other buffer), as the header states."""
+    n = 40
+    params = Wk.base_params(Lambda=10.0, sigma=0.01)
+    sim = lbm.Simulation(n, n, params, Wk.static_drop(n, n, 10.0), storage="f64", device=DEV)
+    sim.step(3)
+    S0 = sim.live_pops().clone()
+    states = [sim.pops_like() for _ in range(3)]
+    lbm.lbm_step_into(sim.h, S0.data_ptr(), [t.data_ptr() for t in states], sim.stream())
+    first, last = states[0].clone(), states[2].clone()
+    sim.step(1)                             # from states[-1] into the handle's other buffer
+    ref = sim.pops_like()
+    lbm.lbm_step_into(sim.h, last.data_ptr(), [ref.data_ptr()], sim.stream())   # the same step, into ref
+    torch.cuda.synchronize()
+    assert torch.equal(states[1], ref)      # it was states[-2]
+    assert torch.equal(states[2], last)     # read, not written
+    assert torch.equal(states[0], first)    # the rest of the trajectory untouched
+    sim.close()
+
+
 def test_partition_stream_range_beyond_the_device():
     """A CU range past the device's CUs is refused (LBM_EINVAL) before any
     stream is created; a whole-device range is accepted."""
